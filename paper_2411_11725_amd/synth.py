@@ -1,0 +1,140 @@
+"""Seeded synthetic inputs (meshes, materials, initial magnetisations).
+
+This module holds no arithmetic of the method: it only draws random numbers
+and lays out parameter arrays.  Both the GPU path and its checker take their
+inputs from here, rounded to float32 (the GPU's storage precision), so that
+both start from bit-identical values.
+
+Workloads (every value in SI; mT fields are converted with H = B / mu0):
+  standard_cube   16 x 16 x 4 cells of 2 nm, Ms 8e5, A 1.3e-11, alpha 0.02,
+                  random unit m0 per node (seed 101)
+  film            256 x 64 x 1 cells of 3.9 x 3.9 x 3 nm, Ms 8e5, A 1.3e-11,
+                  alpha 0.02, m0 tilted 10 deg from +x in-plane, field step
+                  (-25, 4, 0) mT
+  block           128 x 128 x 32 cells of 2 nm, Ms 1e6, A 1.5e-11, alpha 1,
+                  Ku ~ U[0, 5e5] per cell, easy axes uniform on the sphere,
+                  random unit m0 per node (seed 103)
+  magnonic        256 x 128 x 1 cells of 4 x 4 x 5 nm, Ms 1.4e5, A 3.5e-12,
+                  alpha 1e-3 ramped linearly to 0.5 over the outer 16 cells of
+                  every in-plane edge, per-cell field map (init 0), 1 mT drive
+                  along +y at 10 GHz on the cells 16 <= x < 20
+"""
+import math
+
+import numpy as np
+
+MU0_SI = 4.0e-7 * math.pi  # only to convert mT inputs to A/m
+
+
+def random_unit_vectors(count, rng):
+    """Gaussian 3-vectors normalised to unit length, shape (3, count)."""
+    v = rng.standard_normal((3, count))
+    return v / np.linalg.norm(v, axis=0, keepdims=True)
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def make_problem(n, h, Ms, A, alpha, gamma=2.211e5, m0="random", seed=0,
+                 Ku=None, easy="random", h_uniform=(0.0, 0.0, 0.0),
+                 h_cell=None, drive_mask=None, drive_amp=(0.0, 0.0, 0.0),
+                 drive_freq=0.0, drive_phase=0.0):
+    """Return a dict of float32 arrays describing one problem.
+
+    Cell arrays have shape (N3, N2, N1), cell vectors (3, N3, N2, N1) and the
+    nodal magnetisation (3, N3+1, N2+1, N1+1): C order, x fastest.
+    Scalars Ms, A, alpha, Ku may be numbers (uniform) or cell arrays.
+    """
+    n1, n2, n3 = n
+    cells = (n3, n2, n1)
+    nodes = (n3 + 1, n2 + 1, n1 + 1)
+    rng = np.random.default_rng(seed)
+
+    def cellv(x):
+        return _f32(np.broadcast_to(np.asarray(x, dtype=np.float64), cells))
+
+    out = {"n": tuple(n), "h": tuple(float(v) for v in h), "gamma": float(gamma)}
+    out["Ms"] = cellv(Ms)
+    out["A"] = cellv(A)
+    out["alpha"] = cellv(alpha)
+    if isinstance(m0, str) and m0 == "random":
+        m = random_unit_vectors(int(np.prod(nodes)), rng).reshape((3,) + nodes)
+    else:
+        m = np.broadcast_to(np.asarray(m0, dtype=np.float64).reshape(3, 1, 1, 1),
+                            (3,) + nodes)
+    out["m0"] = _f32(m)
+    if Ku is not None:
+        if isinstance(Ku, tuple) and Ku[0] == "uniform":
+            out["Ku"] = _f32(rng.uniform(Ku[1], Ku[2], size=cells))
+        else:
+            out["Ku"] = cellv(Ku)
+        if isinstance(easy, str) and easy == "random":
+            out["easy"] = _f32(random_unit_vectors(int(np.prod(cells)), rng).reshape((3,) + cells))
+        else:
+            out["easy"] = _f32(np.broadcast_to(np.asarray(easy, dtype=np.float64).reshape(3, 1, 1, 1),
+                                               (3,) + cells))
+    else:
+        out["Ku"] = None
+        out["easy"] = None
+    out["h_uniform"] = np.asarray(h_uniform, dtype=np.float32)
+    out["h_cell"] = None if h_cell is None else _f32(h_cell)
+    out["drive_mask"] = None if drive_mask is None else _f32(drive_mask)
+    out["drive_amp"] = np.asarray(drive_amp, dtype=np.float32)
+    out["drive_freq"] = float(drive_freq)
+    out["drive_phase"] = float(drive_phase)
+    return out
+
+
+def standard_cube(seed=101):
+    return make_problem((16, 16, 4), (2e-9, 2e-9, 2e-9), 8.0e5, 1.3e-11, 0.02,
+                        seed=seed)
+
+
+def film(seed=102):
+    th = math.radians(10.0)
+    return make_problem((256, 64, 1), (3.9e-9, 3.9e-9, 3e-9), 8.0e5, 1.3e-11, 0.02,
+                        m0=(math.cos(th), math.sin(th), 0.0), seed=seed,
+                        h_uniform=(-25e-3 / MU0_SI, 4e-3 / MU0_SI, 0.0))
+
+
+def block(n=(128, 128, 32), seed=103):
+    return make_problem(n, (2e-9, 2e-9, 2e-9), 1.0e6, 1.5e-11, 1.0, seed=seed,
+                        Ku=("uniform", 0.0, 5e5), easy="random")
+
+
+def magnonic(n=(256, 128, 1), seed=105):
+    n1, n2, n3 = n
+    ramp = 16
+    x = np.arange(n1)
+    y = np.arange(n2)
+    # distance (in cells) to the nearest in-plane edge
+    dx = np.minimum(x, n1 - 1 - x)[None, :]
+    dy = np.minimum(y, n2 - 1 - y)[:, None]
+    dist = np.minimum(dx, dy).astype(np.float64)
+    frac = np.clip((ramp - dist) / ramp, 0.0, 1.0)
+    alpha = 1e-3 + (0.5 - 1e-3) * frac
+    alpha = np.broadcast_to(alpha, (n3, n2, n1))
+    mask = np.zeros((n3, n2, n1))
+    mask[:, :, 16:20] = 1.0
+    return make_problem(n, (4e-9, 4e-9, 5e-9), 1.4e5, 3.5e-12, alpha,
+                        m0=(1.0, 0.0, 0.0), seed=seed,
+                        h_cell=np.zeros((3, n3, n2, n1)), drive_mask=mask,
+                        drive_amp=(0.0, 1e-3 / MU0_SI, 0.0), drive_freq=10e9)
+
+
+def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
+                 hetero=True):
+    """Small heterogeneous problem used by the parity tests: every term on,
+    per-cell Ms, A, alpha, Ku, easy axes and applied field."""
+    rng = np.random.default_rng(seed)
+    n1, n2, n3 = n
+    cells = (n3, n2, n1)
+    Ms = rng.uniform(4e5, 1.2e6, size=cells) if hetero else 8e5
+    A = rng.uniform(5e-12, 2e-11, size=cells) if hetero else 1.3e-11
+    alpha = rng.uniform(0.01, 0.5, size=cells) if hetero else 0.1
+    hc = rng.uniform(-5e4, 5e4, size=(3,) + cells) if field else None
+    return make_problem(n, h, Ms, A, alpha, seed=seed + 1,
+                        Ku=("uniform", 0.0, 5e5) if anis else None,
+                        easy="random", h_uniform=(1e4, -2e4, 3e4) if field else (0, 0, 0),
+                        h_cell=hc)
