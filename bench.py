@@ -1,0 +1,195 @@
+"""Benchmark: LLG cell-updates/s of the fused HIP hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload block|film|cube]
+
+A step is one accepted Dormand-Prince 5(4) step (6 new right-hand sides with
+first-same-as-last) of the whole hot path: demag FFT convolution, local terms,
+LLG right-hand side, stage combination, float64 error norm and the device-side
+step controller.  Inputs are seeded synthetic problems resident in HBM before
+the timed region.  The metric follows the paper's benchmark (Sec. 6): cells x
+right-hand-side evaluations / wall time.
+
+Printed JSON line extras:
+  roofline      the dominant kernel's algorithmic bytes per launch divided by
+                its average launch time (HIP events on the mesh stream over
+                the timed region), against the 8 TB/s HBM peak;
+  kernels       the same for every kernel slot;
+  cpu_baseline  the float64 oracle on the host, timed on a bounded sample of
+                the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # the block relaxation: 128 x 128 x 32 cells of 2 nm, alpha = 1, random Ku
+    # and easy axes, DP45 rtol 1e-5
+    "block": dict(desc="3D block 128x128x32 cells (2 nm), alpha=1 relaxation, per-cell Ku, DP45 rtol 1e-5",
+                  make="block", terms=("exchange", "demag", "anisotropy"), dt0=1e-14),
+    "film": dict(desc="thin film 256x64x1 cells (3.9x3.9x3 nm), field step (-25,4,0) mT, DP45 rtol 1e-5",
+                 make="film", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
+    "cube": dict(desc="16x16x4 cells (2 nm), random start, DP45 rtol 1e-5",
+                 make="standard_cube", terms=("exchange", "demag"), dt0=1e-14),
+}
+
+
+def byte_model(n, pad, nn, has_anis, has_hcell, stage_reads):
+    """Algorithmic bytes per launch of each kernel slot (inputs + outputs once)."""
+    n1, n2, n3 = n
+    p1, p2, p3 = pad
+    k1 = p1 // 2 + 1
+    nc = n1 * n2 * n3
+    c8 = 8  # complex64
+    out = {}
+    out["xfwd"] = 12 * nn + 4 * nc + 3 * n3 * n2 * k1 * c8
+    if n3 > 1:
+        out["yfwd"] = 3 * n3 * n2 * k1 * c8 + 3 * n3 * p2 * k1 * c8
+        tensor = 6 * (p3 // 2 + 1) * (p2 // 2 + 1) * k1 * 4
+        out["conv"] = 2 * 3 * n3 * p2 * k1 * c8 + tensor
+        out["yinv"] = 3 * n3 * p2 * k1 * c8 + 3 * n3 * n2 * k1 * c8
+    else:
+        tensor = 4 * (p2 // 2 + 1) * k1 * 4
+        out["conv"] = 2 * 3 * n2 * k1 * c8 + tensor
+    out["xinv"] = 3 * n3 * n2 * k1 * c8 + 12 * nc
+    cell = 12 * nc + 8 * nc + (16 * nc if has_anis else 0) + (12 * nc if has_hcell else 0)
+    # stage input, state, node coefficients, k_s and y_{s+1} written, earlier k_j read
+    out["stencil"] = cell + 12 * nn * (1 + 1 + 1 + 2) + 12 * nn * stage_reads
+    return out
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if the
+    kernel source has not changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters_%s.md" % kernel)
+    src = os.path.join(ROOT, "paper_2411_11725_amd", "csrc", "demag.hip" if kernel != "stencil" else "stencil.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source sha256: ([0-9a-f]{64})", text)
+    b = re.search(r"hbm bytes per launch: ([0-9.eE+]+)", text)
+    if not m or not b:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(1):
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(p, terms_mask, evals=4):
+    """Oracle right-hand-side evaluations of the same workload on the host."""
+    import numpy as np
+
+    import oracle
+    from oracle.field import demag_cell_field
+
+    mesh = oracle.Mesh(p["n"], p["h"])
+    f = lambda a: None if a is None else np.asarray(a, dtype=np.float64)
+    mat = oracle.Material(Ms=f(p["Ms"]), A=f(p["A"]), alpha=f(p["alpha"]), gamma=p["gamma"],
+                          Ku=f(p["Ku"]), easy=f(p["easy"]), h_cell=f(p["h_cell"]),
+                          h_uniform=f(p["h_uniform"]), drive_mask=f(p["drive_mask"]),
+                          drive_amp=f(p["drive_amp"]), drive_freq=p["drive_freq"],
+                          drive_phase=p["drive_phase"])
+    m = f(p["m0"])
+    t0 = time.perf_counter()
+    demag_cell_field(mesh, mat, m)            # tensor and its spectrum: set-up, not timed
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        oracle.llg_rhs(mesh, mat, m, 0.0, terms_mask)
+    dt = time.perf_counter() - t0
+    return {"value": mesh.n_cells * evals / dt, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d float64 right-hand-side evaluations of the full %dx%dx%d mesh "
+                      "(numpy, one thread; %.1f s tensor set-up excluded)" % (evals, *p["n"], setup)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="block", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the hot path is a single-GPU build "
+              "(multi-GPU sharding is design only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_11725_amd import binding as B
+    from paper_2411_11725_amd import synth
+
+    W = WORKLOADS[args.workload]
+    p = getattr(synth, W["make"])()
+    tmask = {"exchange": B.NM_T_EXCHANGE, "demag": B.NM_T_DEMAG, "anisotropy": B.NM_T_ANIS,
+             "zeeman": B.NM_T_ZEEMAN}
+    terms = sum(tmask[t] for t in W["terms"])
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    mesh = B.mesh_from_problem(p, device="cuda:0", stream=stream)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    nn, nc, pad = B.nm_mesh_info(mesh)
+    m = torch.as_tensor(p["m0"], device="cuda:0").contiguous()
+    clk = B.nm_clock(0.0, W["dt0"], 0, 0, 0, 0.0)
+    t_cap = 20e-9
+    B.nm_llg_step(mesh, m, clk, B.NM_DP45, terms, t_end=t_cap, max_steps=args.warmup)
+    torch.cuda.synchronize()
+    rhs0, acc0 = clk.rhs_evals, clk.accepted
+    B.nm_profile_enable(mesh, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.nm_llg_step(mesh, m, clk, B.NM_DP45, terms, t_end=t_cap, max_steps=args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = B.nm_profile_read(mesh)
+    B.nm_profile_enable(mesh, False)
+    rhs = clk.rhs_evals - rhs0
+    steps = clk.accepted - acc0
+    value = nc * rhs / elapsed
+
+    # DP45 stages read on average ~2.7 earlier k_j in the epilogue
+    bm = byte_model(p["n"], pad, nn, p["Ku"] is not None, p["h_cell"] is not None, 2.7)
+    kernels = {}
+    for slot, (ms, cnt) in prof.items():
+        if cnt == 0 or slot not in bm:
+            continue
+        avg_s = ms / cnt * 1e-3
+        kernels[slot] = {"launches": cnt, "avg_us": avg_s * 1e6, "bytes_per_launch": bm[slot],
+                         "gbs": bm[slot] / avg_s / 1e9, "frac": bm[slot] / avg_s / 1e9 / HBM_PEAK_GBS}
+    dom = max(kernels, key=lambda k: prof[k][0])
+    ach = kernels[dom]["gbs"]
+    traffic = counter_traffic(dom)
+    B.nm_mesh_destroy(mesh)
+
+    out = {
+        "metric": "LLG cell-updates/s", "value": value, "unit": "cell-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / max(steps, 1) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded; float64 tensor set-up and error norm)",
+        "config": {"workload": W["desc"], "cells": nc, "nodes": nn, "padded": list(pad),
+                   "rhs_evals": rhs, "integrator": "DP45", "terms": list(W["terms"]),
+                   "setup_s": setup_s},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, terms)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * nm.h -- C ABI of the MI355X nodal finite-difference micromagnetics library.
+ *
+ * The library evaluates the effective field of the nodal finite-difference
+ * scheme of Abert et al., "NeuralMag: an open-source nodal finite-difference
+ * code for inverse micromagnetics" (Sec. 3), and advances the
+ * Landau-Lifshitz-Gilbert equation (Sec. 2, Eq. llg) with RK4 or the adaptive
+ * Dormand-Prince 5(4) pair (Sec. 5.3).  All compute runs in hand-written HIP
+ * kernels for gfx950 in float32; float64 is used only for the demagnetisation
+ * tensor set-up and for the adaptive step's error norm.
+ *
+ * Conventions shared by every call
+ *  - Grid: N1 x N2 x N3 cells of size h1 x h2 x h3 (metres); nodes
+ *    n = c + i with i in {0,1}^3 (Sec. 3.1), i.e. (N1+1)(N2+1)(N3+1) nodes.
+ *  - Layout: structure of arrays, x fastest.  A nodal vector field is
+ *    float[3][N3+1][N2+1][N1+1]; a cell scalar float[N3][N2][N1]; a cell
+ *    vector float[3][N3][N2][N1].
+ *  - Pointers named "device" must point to GPU memory of the current device.
+ *    The caller owns every pointer it passes; the library owns its internal
+ *    buffers (allocated in nm_mesh_create, released in nm_mesh_destroy).  No
+ *    hot call (nm_heff, nm_llg_rhs, nm_llg_step) allocates.
+ *  - Streams: work is enqueued on the stream given at mesh creation
+ *    (hipStream_t cast to void*; NULL means the null stream).  Calls return
+ *    without synchronising unless stated otherwise.
+ *  - Units: SI; fields in A/m, mu0 = 4 pi 1e-7 exactly.
+ *  - Errors: every call returns an nm_status; NM_OK is 0.  On error nothing
+ *    has been enqueued and nm_last_error() returns a message (per thread).
+ *  - Threads: a mesh must not be used by two threads at once.
+ */
+#ifndef NM_H
+#define NM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NM_OK = 0,
+    NM_EINVAL = -1,        /* bad argument (sizes, NULL pointer, unknown flag) */
+    NM_ENOMEM = -2,        /* device allocation failed */
+    NM_EHIP = -3,          /* a HIP runtime call failed */
+    NM_ENOTREADY = -4,     /* result not available yet */
+    NM_ENONFINITE = -5,    /* the state or the step error became NaN/Inf */
+    NM_ESTEPSIZE = -6,     /* adaptive step fell below dt_min */
+    NM_EUNSUPPORTED = -8   /* valid request this build does not handle */
+} nm_status;
+
+/* Energy / field terms (bit mask). */
+enum {
+    NM_T_EXCHANGE = 1,     /* int A |grad m|^2, Eq. exchange_energy */
+    NM_T_DEMAG = 2,        /* cuboid-cell FFT demagnetisation, Sec. 3.2 */
+    NM_T_ANIS = 4,         /* uniaxial -int Ku (m.e)^2 */
+    NM_T_ZEEMAN = 8,       /* -mu0 int Ms m.H_ext */
+    NM_T_ALL = 15
+};
+
+/* Time integrators (Sec. 5.3). */
+enum { NM_RK4 = 1, NM_DP45 = 2 };
+
+typedef struct nm_mesh nm_mesh;
+
+/* Grid and constants.  n[k] >= 2 for k = 0, 1 and n[2] >= 1; every padded
+ * FFT length (next power of two >= 2 n[k] - 1) must not exceed 1024. */
+typedef struct {
+    int n[3];          /* cells N1, N2, N3 */
+    double h[3];       /* cell edges (m), > 0 */
+    double gamma;      /* reduced gyromagnetic ratio, m/(A s), > 0 */
+    void *stream;      /* hipStream_t for all work on this mesh */
+} nm_mesh_desc;
+
+/* Cell-wise material parameters (Eqs. ms_discrete, cell_basis) and applied
+ * field; all pointers are device pointers to float cell arrays, copied by
+ * nm_mesh_create (the caller may free them afterwards).
+ *   H_ext,c(t) = h_uniform + h_cell[c] + drive_mask[c] drive_amp sin(2 pi f t + phase) */
+typedef struct {
+    const float *Ms;          /* required, A/m, >= 0 (0 marks vacuum cells) */
+    const float *A;           /* required, J/m */
+    const float *alpha;       /* required, Gilbert damping */
+    const float *Ku;          /* optional, J/m^3 (uniaxial); with easy */
+    const float *easy;        /* optional, 3*N unit easy axes; with Ku */
+    const float *h_cell;      /* optional, 3*N per-cell applied field */
+    float h_uniform[3];       /* uniform applied field */
+    const float *drive_mask;  /* optional, per-cell weight of the drive */
+    float drive_amp[3];       /* drive amplitude (A/m) */
+    double drive_freq;        /* Hz */
+    double drive_phase;       /* rad */
+} nm_material;
+
+/* Adaptive / fixed stepping parameters. */
+typedef struct {
+    int method;            /* NM_RK4 or NM_DP45 */
+    unsigned terms;        /* field terms, NM_T_* mask */
+    double rtol, atol;     /* DP45 tolerances (RMS norm, float64) */
+    double dt_min, dt_max; /* DP45 bounds on the step (dt_max <= 0: none) */
+    double stop_torque;    /* > 0: DP45 stops once max_n |dm/dt| < stop_torque (1/s) */
+    double *log;           /* optional device buffer, 3 doubles (t, dt, accepted)
+                              per DP45 attempt */
+    long log_capacity;     /* attempts that fit in log */
+} nm_integrator;
+
+/* Integrator clock, read and written by nm_llg_step. */
+typedef struct {
+    double t;              /* current time (s) */
+    double dt;             /* RK4: the step; DP45: the next step proposal */
+    long accepted, rejected, rhs_evals;
+    double max_torque;     /* DP45: max_n |dm/dt| after the last accepted step */
+} nm_clock;
+
+/* Create a mesh: validates desc and mat, allocates every internal buffer
+ * (FFT workspace, tensor, per-node coefficients) and computes the lumped
+ * mass M_n = mu0 sum_{c containing n} Ms_c V/8 (Eq. mass_lumping) and the
+ * nodal damping.  Synchronises the stream before returning. */
+nm_status nm_mesh_create(const nm_mesh_desc *desc, const nm_material *mat, nm_mesh **out);
+
+/* Release a mesh and all its buffers (synchronises its stream).  NULL is ignored. */
+nm_status nm_mesh_destroy(nm_mesh *mesh);
+
+/* Sizes: nodes, cells and the padded FFT grid (any output may be NULL). */
+nm_status nm_mesh_info(const nm_mesh *mesh, int64_t *n_nodes, int64_t *n_cells, int pad[3]);
+
+/* Device bytes nm_mesh_create would allocate for this grid. */
+size_t nm_mesh_footprint_bytes(const nm_mesh_desc *desc, int integrator);
+
+/* Replace the per-cell applied-field map (device, 3*N floats; NULL clears it). */
+nm_status nm_mesh_set_field(nm_mesh *mesh, const float *h_cell);
+
+/* Demagnetisation tensor (Sec. 3.2): float64 Newell closed form near the
+ * source cell, tent-weighted Gauss-Legendre integral of the dipole kernel
+ * further out, transformed in float64 to the real k-space tensor of the
+ * zero-padded grid and stored in float32.  Idempotent; must precede any call
+ * with NM_T_DEMAG. */
+nm_status nm_demag_tensor_init(nm_mesh *mesh);
+
+/* The float64 real-space tensor N(d) for 0 <= d_k < n[k], written to the
+ * device buffer out[6][n3][n2][n1] (xx, yy, zz, xy, xz, yz).  Stand-alone:
+ * no mesh needed; enqueued on stream. */
+nm_status nm_newell_octant(const int n[3], const double h[3], double *out, void *stream);
+
+/* Effective field (Eq. heff with Eq. mass_lumping) of the selected terms at
+ * time t: m and h are device nodal vector fields (3 * n_nodes floats). */
+nm_status nm_heff(nm_mesh *mesh, const float *m, float *h, unsigned terms, double t);
+
+/* Cell-centred demagnetisation field H_c = -sum N(c-c') Ms_c' mbar_c'
+ * (device, 3 * n_cells floats). */
+nm_status nm_demag_cell_field(nm_mesh *mesh, const float *m, float *h_cell_out);
+
+/* LLG right-hand side dm/dt (Eq. llg) of the selected terms at time t. */
+nm_status nm_llg_rhs(nm_mesh *mesh, const float *m, float *dmdt, unsigned terms, double t);
+
+/* Energies in J: e[0] exchange, e[1] demag, e[2] anisotropy, e[3] Zeeman,
+ * e[4] total (host array).  Synchronises the stream. */
+nm_status nm_energy(nm_mesh *mesh, const float *m, unsigned terms, double t, double e[5]);
+
+/* Advance m (device, in place) from clk->t to t_end with at most max_steps
+ * steps (RK4: steps of clk->dt, the last one shortened to land on t_end;
+ * DP45: accepted steps, starting from the proposal clk->dt).  Updates *clk.
+ * Synchronises the stream.  Returns NM_ENONFINITE / NM_ESTEPSIZE when the
+ * DP45 controller fails; m then holds the last accepted state. */
+nm_status nm_llg_step(nm_mesh *mesh, float *m, nm_clock *clk, const nm_integrator *integ,
+                      double t_end, long max_steps);
+
+/* Per-kernel timing (measurement only).  While enabled, every kernel the
+ * mesh launches is bracketed by a pair of HIP events on the mesh stream and
+ * its duration is accumulated in one of these slots. */
+enum {
+    NM_PROF_XFWD = 0,      /* nodal -> cell average, R2C along x */
+    NM_PROF_YFWD = 1,      /* FFT along y (3D) */
+    NM_PROF_CONV = 2,      /* fused FFT + k-space product + inverse (z in 3D, y in films) */
+    NM_PROF_YINV = 3,      /* inverse FFT along y (3D) */
+    NM_PROF_XINV = 4,      /* C2R along x -> cell field */
+    NM_PROF_STENCIL = 5,   /* local terms + LLG + stage epilogue */
+    NM_PROF_CONTROL = 6,   /* step controller / bookkeeping */
+    NM_PROF_OTHER = 7,
+    NM_PROF_SLOTS = 8
+};
+
+/* on != 0: start profiling (clears the accumulators); on == 0: stop. */
+nm_status nm_profile_enable(nm_mesh *mesh, int on);
+
+/* Synchronise the stream and return, per slot, the summed kernel time (ms)
+ * and the number of launches since profiling was enabled (host arrays of
+ * NM_PROF_SLOTS entries). */
+nm_status nm_profile_read(nm_mesh *mesh, double ms[NM_PROF_SLOTS], long long counts[NM_PROF_SLOTS]);
+
+/* Message describing the last error on the calling thread. */
+const char *nm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NM_H */

@@ -1,0 +1,212 @@
+"""ctypes binding of libnm.so: the C entry points of include/nm.h under the same
+names, plus argument marshalling from torch device tensors.
+
+Nothing here computes: every call goes to the HIP library, which must be
+built (paper_2411_11725_amd/build.py).  A missing library raises at the
+first call; there is no fallback.
+"""
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int, c_int64, c_long, c_uint, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnm.so")
+
+NM_OK, NM_EINVAL, NM_ENOMEM, NM_EHIP, NM_ENOTREADY = 0, -1, -2, -3, -4
+NM_ENONFINITE, NM_ESTEPSIZE, NM_EUNSUPPORTED = -5, -6, -8
+NM_T_EXCHANGE, NM_T_DEMAG, NM_T_ANIS, NM_T_ZEEMAN, NM_T_ALL = 1, 2, 4, 8, 15
+NM_RK4, NM_DP45 = 1, 2
+
+# entry points declared in include/nm.h
+EXPORTS = [
+    "nm_mesh_create", "nm_mesh_destroy", "nm_mesh_info", "nm_mesh_footprint_bytes",
+    "nm_mesh_set_field", "nm_demag_tensor_init", "nm_newell_octant", "nm_heff",
+    "nm_demag_cell_field", "nm_llg_rhs", "nm_energy", "nm_llg_step", "nm_profile_enable",
+    "nm_profile_read", "nm_last_error",
+]
+PROF_SLOTS = ["xfwd", "yfwd", "conv", "yinv", "xinv", "stencil", "control", "other"]
+
+
+class nm_mesh_desc(ctypes.Structure):
+    _fields_ = [("n", c_int * 3), ("h", c_double * 3), ("gamma", c_double), ("stream", c_void_p)]
+
+
+class nm_material(ctypes.Structure):
+    _fields_ = [("Ms", c_void_p), ("A", c_void_p), ("alpha", c_void_p), ("Ku", c_void_p),
+                ("easy", c_void_p), ("h_cell", c_void_p), ("h_uniform", c_float * 3),
+                ("drive_mask", c_void_p), ("drive_amp", c_float * 3),
+                ("drive_freq", c_double), ("drive_phase", c_double)]
+
+
+class nm_integrator(ctypes.Structure):
+    _fields_ = [("method", c_int), ("terms", c_uint), ("rtol", c_double), ("atol", c_double),
+                ("dt_min", c_double), ("dt_max", c_double), ("stop_torque", c_double),
+                ("log", c_void_p), ("log_capacity", c_long)]
+
+
+class nm_clock(ctypes.Structure):
+    _fields_ = [("t", c_double), ("dt", c_double), ("accepted", c_long), ("rejected", c_long),
+                ("rhs_evals", c_long), ("max_torque", c_double)]
+
+
+class NMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("nm status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Open libnm.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libnm.so not built; run paper_2411_11725_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = c_void_p
+        sig = {
+            "nm_mesh_create": ([POINTER(nm_mesh_desc), POINTER(nm_material), POINTER(c_void_p)], c_int),
+            "nm_mesh_destroy": ([P], c_int),
+            "nm_mesh_info": ([P, POINTER(c_int64), POINTER(c_int64), POINTER(c_int)], c_int),
+            "nm_mesh_footprint_bytes": ([POINTER(nm_mesh_desc), c_int], ctypes.c_size_t),
+            "nm_mesh_set_field": ([P, P], c_int),
+            "nm_demag_tensor_init": ([P], c_int),
+            "nm_newell_octant": ([POINTER(c_int), POINTER(c_double), P, P], c_int),
+            "nm_heff": ([P, P, P, c_uint, c_double], c_int),
+            "nm_demag_cell_field": ([P, P, P], c_int),
+            "nm_llg_rhs": ([P, P, P, c_uint, c_double], c_int),
+            "nm_energy": ([P, P, c_uint, c_double, POINTER(c_double)], c_int),
+            "nm_llg_step": ([P, P, POINTER(nm_clock), POINTER(nm_integrator), c_double, c_long], c_int),
+            "nm_profile_enable": ([P, c_int], c_int),
+            "nm_profile_read": ([P, POINTER(c_double), POINTER(ctypes.c_longlong)], c_int),
+            "nm_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != NM_OK:
+        raise NMError(status, lib().nm_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+# ---------------------------------------------------------------- entry points
+def nm_mesh_create(n, h, gamma, Ms, A, alpha, Ku=None, easy=None, h_cell=None,
+                   h_uniform=(0.0, 0.0, 0.0), drive_mask=None, drive_amp=(0.0, 0.0, 0.0),
+                   drive_freq=0.0, drive_phase=0.0, stream=None):
+    """Create a mesh from float32 device tensors (copied by the library)."""
+    desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), _stream_handle(stream))
+    mat = nm_material(_ptr(Ms), _ptr(A), _ptr(alpha), _ptr(Ku), _ptr(easy), _ptr(h_cell),
+                      (c_float * 3)(*h_uniform), _ptr(drive_mask), (c_float * 3)(*drive_amp),
+                      float(drive_freq), float(drive_phase))
+    out = c_void_p()
+    _check(lib().nm_mesh_create(ctypes.byref(desc), ctypes.byref(mat), ctypes.byref(out)))
+    return out
+
+
+def nm_mesh_destroy(mesh):
+    _check(lib().nm_mesh_destroy(mesh))
+
+
+def nm_mesh_info(mesh):
+    nn, nc, pad = c_int64(), c_int64(), (c_int * 3)()
+    _check(lib().nm_mesh_info(mesh, ctypes.byref(nn), ctypes.byref(nc), pad))
+    return nn.value, nc.value, tuple(pad)
+
+
+def nm_mesh_footprint_bytes(n, h, gamma=2.211e5, integrator=NM_DP45):
+    desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), None)
+    return lib().nm_mesh_footprint_bytes(ctypes.byref(desc), integrator)
+
+
+def nm_mesh_set_field(mesh, h_cell):
+    _check(lib().nm_mesh_set_field(mesh, _ptr(h_cell)))
+
+
+def nm_demag_tensor_init(mesh):
+    _check(lib().nm_demag_tensor_init(mesh))
+
+
+def nm_newell_octant(n, h, out, stream=None):
+    _check(lib().nm_newell_octant((c_int * 3)(*n), (c_double * 3)(*h), _ptr(out),
+                                  _stream_handle(stream)))
+
+
+def nm_heff(mesh, m, h, terms=NM_T_ALL, t=0.0):
+    _check(lib().nm_heff(mesh, _ptr(m), _ptr(h), terms, float(t)))
+
+
+def nm_demag_cell_field(mesh, m, out):
+    _check(lib().nm_demag_cell_field(mesh, _ptr(m), _ptr(out)))
+
+
+def nm_llg_rhs(mesh, m, dmdt, terms=NM_T_ALL, t=0.0):
+    _check(lib().nm_llg_rhs(mesh, _ptr(m), _ptr(dmdt), terms, float(t)))
+
+
+def nm_energy(mesh, m, terms=NM_T_ALL, t=0.0):
+    e = (c_double * 5)()
+    _check(lib().nm_energy(mesh, _ptr(m), terms, float(t), e))
+    return {"exchange": e[0], "demag": e[1], "anisotropy": e[2], "zeeman": e[3], "total": e[4]}
+
+
+def nm_llg_step(mesh, m, clock, method=NM_RK4, terms=NM_T_ALL, t_end=0.0, max_steps=1 << 40,
+                rtol=1e-5, atol=1e-5, dt_min=1e-20, dt_max=0.0, stop_torque=0.0, log=None):
+    """Advance m in place; clock is an nm_clock updated in place."""
+    integ = nm_integrator(method, terms, rtol, atol, dt_min, dt_max, stop_torque, _ptr(log),
+                          0 if log is None else log.numel() // 3)
+    _check(lib().nm_llg_step(mesh, _ptr(m), ctypes.byref(clock), ctypes.byref(integ),
+                             float(t_end), int(max_steps)))
+    return clock
+
+
+def nm_profile_enable(mesh, on=True):
+    _check(lib().nm_profile_enable(mesh, 1 if on else 0))
+
+
+def nm_profile_read(mesh):
+    """{slot: (milliseconds, launches)} accumulated since nm_profile_enable."""
+    ms = (c_double * 8)()
+    cnt = (ctypes.c_longlong * 8)()
+    _check(lib().nm_profile_read(mesh, ms, cnt))
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(PROF_SLOTS)}
+
+
+def nm_last_error():
+    return lib().nm_last_error().decode()
+
+
+# ------------------------------------------------------------ marshalling
+def mesh_from_problem(p, device="cuda", stream=None, tensor=True):
+    """Upload a problem dict (see synth.make_problem) and create its mesh."""
+    import torch
+
+    def dev(a):
+        return None if a is None else torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
+
+    arrays = {k: dev(p[k]) for k in ("Ms", "A", "alpha", "Ku", "easy", "h_cell", "drive_mask")}
+    mesh = nm_mesh_create(p["n"], p["h"], p["gamma"], arrays["Ms"], arrays["A"], arrays["alpha"],
+                          Ku=arrays["Ku"], easy=arrays["easy"], h_cell=arrays["h_cell"],
+                          h_uniform=tuple(float(v) for v in p["h_uniform"]),
+                          drive_mask=arrays["drive_mask"],
+                          drive_amp=tuple(float(v) for v in p["drive_amp"]),
+                          drive_freq=p["drive_freq"], drive_phase=p["drive_phase"], stream=stream)
+    if tensor:
+        nm_demag_tensor_init(mesh)
+    return mesh

@@ -1,0 +1,540 @@
+// C ABI of the library: mesh lifetime, argument checks and the drivers of the
+// field, energy and time-stepping kernels.
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "nm_internal.h"
+
+namespace nm {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string &msg) { g_error = msg; }
+
+static std::mutex g_tw_mutex;
+static std::map<int, float2 *> g_tw;
+
+// exp(-2 pi i t / kTwN), built in float64 on the host, one table per device
+const float2 *twiddles(int device) {
+    std::lock_guard<std::mutex> lock(g_tw_mutex);
+    auto it = g_tw.find(device);
+    if (it != g_tw.end()) return it->second;
+    std::vector<float2> host(kTwN);
+    const double pi = 3.14159265358979323846;
+    for (int t = 0; t < kTwN; ++t) {
+        const double a = -2.0 * pi * t / kTwN;
+        host[t] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    float2 *dev = nullptr;
+    if (hipMalloc(&dev, sizeof(float2) * kTwN) != hipSuccess) return nullptr;
+    if (hipMemcpy(dev, host.data(), sizeof(float2) * kTwN, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(dev);
+        return nullptr;
+    }
+    g_tw[device] = dev;
+    return dev;
+}
+
+// ------------------------------------------------------------- set-up kernels
+__global__ void k_cell_setup(const float *__restrict__ Ms, const float *__restrict__ A,
+                             float *__restrict__ wc, float *__restrict__ A2, long long nc, float w) {
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nc) return;
+    wc[c] = w * Ms[c];
+    A2[c] = 2.f * A[c];
+}
+
+// M_n = mu0 sum_{c containing n} Ms_c V/8 (Eq. mass_lumping); Ms-weighted damping
+__global__ void k_node_setup(const float *__restrict__ Ms, const float *__restrict__ alpha,
+                             const float *__restrict__ wc, float *__restrict__ inv_mass,
+                             float *__restrict__ alpha_n, float *__restrict__ gp_n, int N1, int N2,
+                             int N3, double gamma) {
+    const int NX = N1 + 1, NY = N2 + 1;
+    const long long nn = (long long)NX * NY * (N3 + 1);
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nn) return;
+    const int x = (int)(n % NX), y = (int)((n / NX) % NY), z = (int)(n / ((long long)NX * NY));
+    double M = 0.0, sa = 0.0, sm = 0.0;
+    for (int i3 = 0; i3 < 2; ++i3)
+        for (int i2 = 0; i2 < 2; ++i2)
+            for (int i1 = 0; i1 < 2; ++i1) {
+                const int cx = x - i1, cy = y - i2, cz = z - i3;
+                if (cx < 0 || cy < 0 || cz < 0 || cx >= N1 || cy >= N2 || cz >= N3) continue;
+                const long long c = ((long long)cz * N2 + cy) * N1 + cx;
+                M += wc[c];
+                sm += Ms[c];
+                sa += (double)Ms[c] * alpha[c];
+            }
+    const double a = sm > 0.0 ? sa / sm : 0.0;
+    inv_mass[n] = M > 0.0 ? (float)(1.0 / M) : 0.f;
+    alpha_n[n] = (float)a;
+    gp_n[n] = (float)(gamma / (1.0 + a * a));
+}
+
+}  // namespace nm
+
+using namespace nm;
+
+#define NM_REQUIRE(cond, code, msg)  \
+    do {                             \
+        if (!(cond)) {               \
+            set_error(msg);          \
+            return code;             \
+        }                            \
+    } while (0)
+
+#define NM_HIP(call, what)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess) {                                                     \
+            set_error(std::string(what) + ": " + hipGetErrorString(e_));            \
+            return e_ == hipErrorOutOfMemory ? NM_ENOMEM : NM_EHIP;                 \
+        }                                                                           \
+    } while (0)
+
+static int pad_len(int n) {
+    if (n <= 1) return 1;
+    int p = 1;
+    while (p < 2 * n - 1) p <<= 1;
+    return p;
+}
+
+struct Sizes {
+    int P1, P2, P3, K1, P2h, P3h;
+    long long nn, nc, spec, tensor, partials, eblocks;
+};
+
+static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
+    const int n1 = d->n[0], n2 = d->n[1], n3 = d->n[2];
+    if (n1 < 2 || n2 < 2 || n3 < 1) return false;
+    s->P1 = pad_len(n1);
+    s->P2 = pad_len(n2);
+    s->P3 = pad_len(n3);
+    if (s->P1 > kMaxFFT || s->P2 > kMaxFFT || s->P3 > kMaxFFT) return false;
+    s->K1 = s->P1 / 2 + 1;
+    s->P2h = s->P2 / 2 + 1;
+    s->P3h = s->P3 / 2 + 1;
+    s->nn = (long long)(n1 + 1) * (n2 + 1) * (n3 + 1);
+    s->nc = (long long)n1 * n2 * n3;
+    s->spec = 3LL * n3 * s->P2 * s->K1;
+    s->tensor = 6LL * s->P3h * s->P2h * s->K1;
+    s->partials = (s->nn + 255) / 256;
+    s->eblocks = (s->nc + 255) / 256;
+    return true;
+}
+
+static size_t footprint(const Sizes &s) {
+    size_t b = 0;
+    b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive
+    b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
+    b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
+    b += sizeof(float) * 3 * s.nc;                              // demag cell field
+    b += sizeof(float) * 3 * s.nn * 10;                         // y[2], acc, k[7]
+    b += sizeof(Ctrl) + sizeof(ErrPartial) * s.partials + sizeof(double) * (4 * s.eblocks + 4);
+    return b;
+}
+
+static void free_mesh(nm_mesh *m) {
+    if (!m) return;
+    prof_free(m);
+    void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
+                    m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
+                    m->ctrl, m->partials, m->ered};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    for (int j = 0; j < 7; ++j)
+        if (m->k[j]) hipFree(m->k[j]);
+    if (m->ctrl_host) hipHostFree(m->ctrl_host);
+    delete m;
+}
+
+template <typename T>
+static hipError_t dalloc(T **p, long long count) {
+    return hipMalloc((void **)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+}
+
+extern "C" size_t nm_mesh_footprint_bytes(const nm_mesh_desc *desc, int integrator) {
+    (void)integrator;
+    Sizes s;
+    if (!desc || !sizes_of(desc, &s)) return 0;
+    return footprint(s);
+}
+
+extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *mat, nm_mesh **out) {
+    NM_REQUIRE(d && mat && out, NM_EINVAL, "nm_mesh_create: NULL argument");
+    *out = nullptr;
+    Sizes s;
+    NM_REQUIRE(sizes_of(d, &s), NM_EINVAL,
+               "nm_mesh_create: need n[0], n[1] >= 2, n[2] >= 1 and padded lengths <= 1024");
+    for (int k = 0; k < 3; ++k)
+        NM_REQUIRE(std::isfinite(d->h[k]) && d->h[k] > 0.0, NM_EINVAL, "nm_mesh_create: h must be > 0");
+    NM_REQUIRE(std::isfinite(d->gamma) && d->gamma > 0.0, NM_EINVAL, "nm_mesh_create: gamma must be > 0");
+    NM_REQUIRE(mat->Ms && mat->A && mat->alpha, NM_EINVAL, "nm_mesh_create: Ms, A and alpha are required");
+    NM_REQUIRE((mat->Ku == nullptr) == (mat->easy == nullptr), NM_EINVAL,
+               "nm_mesh_create: Ku and easy must be given together");
+    NM_REQUIRE(std::isfinite(mat->drive_freq) && std::isfinite(mat->drive_phase), NM_EINVAL,
+               "nm_mesh_create: non-finite drive parameters");
+
+    nm_mesh *m = new nm_mesh();
+    std::memset(m, 0, sizeof(nm_mesh));
+    m->N1 = d->n[0];
+    m->N2 = d->n[1];
+    m->N3 = d->n[2];
+    m->NX = m->N1 + 1;
+    m->NY = m->N2 + 1;
+    m->NZ = m->N3 + 1;
+    m->P1 = s.P1;
+    m->P2 = s.P2;
+    m->P3 = s.P3;
+    m->K1 = s.K1;
+    m->P2h = s.P2h;
+    m->P3h = s.P3h;
+    for (int k = 0; k < 3; ++k) m->h[k] = d->h[k];
+    m->V = d->h[0] * d->h[1] * d->h[2];
+    m->gamma = d->gamma;
+    m->n_nodes = s.nn;
+    m->n_cells = s.nc;
+    m->stream = (hipStream_t)d->stream;
+    m->n_partials = (int)s.partials;
+    m->n_eblocks = (int)s.eblocks;
+    m->has_anis = mat->Ku != nullptr;
+    m->has_hcell = mat->h_cell != nullptr;
+    m->has_drive = mat->drive_mask != nullptr;
+    for (int k = 0; k < 3; ++k) {
+        m->h_uniform[k] = mat->h_uniform[k];
+        m->drive_amp[k] = mat->drive_amp[k];
+    }
+    m->drive_freq = mat->drive_freq;
+    m->drive_phase = mat->drive_phase;
+
+    // element matrices by axis-difference pattern (bit k set: a_k != b_k)
+    for (int mask = 0; mask < 8; ++mask) {
+        double mm[3], ss[3];
+        for (int k = 0; k < 3; ++k) {
+            const bool diff = (mask >> k) & 1;
+            mm[k] = d->h[k] * (diff ? 1.0 : 2.0) / 6.0;
+            ss[k] = (diff ? -1.0 : 1.0) / d->h[k];
+        }
+        m->Kp[mask] = (float)(ss[0] * mm[1] * mm[2] + mm[0] * ss[1] * mm[2] + mm[0] * mm[1] * ss[2]);
+        m->Mp[mask] = (float)(mm[0] * mm[1] * mm[2]);
+    }
+
+    hipError_t e = hipGetDevice(&m->device);
+    const long long nc = s.nc, nn = s.nn;
+    if (e == hipSuccess) e = dalloc(&m->Ms, nc);
+    if (e == hipSuccess) e = dalloc(&m->A2, nc);
+    if (e == hipSuccess) e = dalloc(&m->wc, nc);
+    if (e == hipSuccess) e = dalloc(&m->h_cell, 3 * nc);
+    if (e == hipSuccess && m->has_anis) e = dalloc(&m->Ku, nc);
+    if (e == hipSuccess && m->has_anis) e = dalloc(&m->easy, 3 * nc);
+    if (e == hipSuccess && m->has_drive) e = dalloc(&m->drive_mask, nc);
+    if (e == hipSuccess) e = dalloc(&m->inv_mass, nn);
+    if (e == hipSuccess) e = dalloc(&m->alpha_n, nn);
+    if (e == hipSuccess) e = dalloc(&m->gp_n, nn);
+    if (e == hipSuccess) e = dalloc(&m->spec, s.spec);
+    if (e == hipSuccess) e = dalloc(&m->tensor, s.tensor);
+    if (e == hipSuccess) e = dalloc(&m->hd, 3 * nc);
+    if (e == hipSuccess) e = dalloc(&m->y[0], 3 * nn);
+    if (e == hipSuccess) e = dalloc(&m->y[1], 3 * nn);
+    if (e == hipSuccess) e = dalloc(&m->acc, 3 * nn);
+    for (int j = 0; j < 7 && e == hipSuccess; ++j) e = dalloc(&m->k[j], 3 * nn);
+    if (e == hipSuccess) e = dalloc(&m->ctrl, 1);
+    if (e == hipSuccess) e = dalloc(&m->partials, s.partials);
+    if (e == hipSuccess) e = dalloc(&m->ered, 4 * s.eblocks + 4);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&m->ctrl_host, sizeof(Ctrl), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        set_error(std::string("nm_mesh_create: allocation failed: ") + hipGetErrorString(e));
+        free_mesh(m);
+        return NM_ENOMEM;
+    }
+    hipStream_t st = m->stream;
+    float *Atmp = m->A2;  // A is staged in A2 and doubled in place
+    e = hipMemcpyAsync(m->Ms, mat->Ms, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(Atmp, mat->A, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && m->has_anis)
+        e = hipMemcpyAsync(m->Ku, mat->Ku, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && m->has_anis)
+        e = hipMemcpyAsync(m->easy, mat->easy, sizeof(float) * 3 * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && m->has_hcell)
+        e = hipMemcpyAsync(m->h_cell, mat->h_cell, sizeof(float) * 3 * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && m->has_drive)
+        e = hipMemcpyAsync(m->drive_mask, mat->drive_mask, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    // alpha is only needed here: stage it in acc (3 * nn >= nc floats)
+    if (e == hipSuccess) e = hipMemcpyAsync(m->acc, mat->alpha, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_cell_setup, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, m->Ms,
+                           Atmp, m->wc, m->A2, nc, (float)(kMu0 * m->V / 8.0));
+        hipLaunchKernelGGL(k_node_setup, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->Ms,
+                           m->acc, m->wc, m->inv_mass, m->alpha_n, m->gp_n, m->N1, m->N2, m->N3,
+                           m->gamma);
+        e = hipGetLastError();
+    }
+    std::vector<float> im;
+    if (e == hipSuccess) {
+        im.resize(nn);
+        e = hipMemcpyAsync(im.data(), m->inv_mass, sizeof(float) * nn, hipMemcpyDeviceToHost, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_error(std::string("nm_mesh_create: set-up failed: ") + hipGetErrorString(e));
+        free_mesh(m);
+        return NM_EHIP;
+    }
+    for (long long i = 0; i < nn; ++i) m->n_active += im[i] > 0.f;
+    *out = m;
+    return NM_OK;
+}
+
+extern "C" nm_status nm_mesh_destroy(nm_mesh *m) {
+    if (!m) return NM_OK;
+    hipStreamSynchronize(m->stream);
+    free_mesh(m);
+    return NM_OK;
+}
+
+extern "C" nm_status nm_mesh_info(const nm_mesh *m, int64_t *n_nodes, int64_t *n_cells, int pad[3]) {
+    NM_REQUIRE(m, NM_EINVAL, "nm_mesh_info: NULL mesh");
+    if (n_nodes) *n_nodes = m->n_nodes;
+    if (n_cells) *n_cells = m->n_cells;
+    if (pad) {
+        pad[0] = m->P1;
+        pad[1] = m->P2;
+        pad[2] = m->P3;
+    }
+    return NM_OK;
+}
+
+extern "C" nm_status nm_mesh_set_field(nm_mesh *m, const float *h_cell) {
+    NM_REQUIRE(m, NM_EINVAL, "nm_mesh_set_field: NULL mesh");
+    if (!h_cell) {
+        m->has_hcell = false;
+        return NM_OK;
+    }
+    NM_HIP(hipMemcpyAsync(m->h_cell, h_cell, sizeof(float) * 3 * m->n_cells, hipMemcpyDeviceToDevice,
+                          m->stream),
+           "nm_mesh_set_field");
+    m->has_hcell = true;
+    return NM_OK;
+}
+
+extern "C" nm_status nm_demag_tensor_init(nm_mesh *m) {
+    NM_REQUIRE(m, NM_EINVAL, "nm_demag_tensor_init: NULL mesh");
+    if (m->tensor_ready) return NM_OK;
+    NM_HIP(build_kspace_tensor(m), "nm_demag_tensor_init");
+    m->tensor_ready = true;
+    return NM_OK;
+}
+
+extern "C" nm_status nm_newell_octant(const int n[3], const double h[3], double *out, void *stream) {
+    NM_REQUIRE(n && h && out, NM_EINVAL, "nm_newell_octant: NULL argument");
+    NM_REQUIRE(n[0] >= 1 && n[1] >= 1 && n[2] >= 1, NM_EINVAL, "nm_newell_octant: n must be >= 1");
+    for (int k = 0; k < 3; ++k)
+        NM_REQUIRE(std::isfinite(h[k]) && h[k] > 0.0, NM_EINVAL, "nm_newell_octant: h must be > 0");
+    NM_HIP(launch_newell_octant(n[0], n[1], n[2], h, out, (hipStream_t)stream), "nm_newell_octant");
+    return NM_OK;
+}
+
+static nm_status check_terms(nm_mesh *m, unsigned terms, const char *who) {
+    if (terms & ~(unsigned)NM_T_ALL) {
+        set_error(std::string(who) + ": unknown term bits");
+        return NM_EINVAL;
+    }
+    if ((terms & NM_T_DEMAG) && !m->tensor_ready) {
+        set_error(std::string(who) + ": NM_T_DEMAG needs nm_demag_tensor_init first");
+        return NM_EINVAL;
+    }
+    return NM_OK;
+}
+
+static nm_status eval_nodes(nm_mesh *m, const float *mag, float *out, unsigned terms, double t,
+                            int mode, const char *who) {
+    NM_REQUIRE(m && mag && out, NM_EINVAL, std::string(who) + ": NULL argument");
+    NM_REQUIRE(std::isfinite(t), NM_EINVAL, std::string(who) + ": non-finite time");
+    nm_status st = check_terms(m, terms, who);
+    if (st != NM_OK) return st;
+    if (terms & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, mag), who);
+    StageSpec sp{};
+    sp.mode = mode;
+    sp.stage = 0;
+    sp.in = mag;
+    sp.out = out;
+    sp.t0 = t;
+    sp.use_ctrl = false;
+    NM_HIP(launch_stencil(m, terms, sp), who);
+    return NM_OK;
+}
+
+extern "C" nm_status nm_heff(nm_mesh *m, const float *mag, float *h, unsigned terms, double t) {
+    return eval_nodes(m, mag, h, terms, t, kModeField, "nm_heff");
+}
+
+extern "C" nm_status nm_llg_rhs(nm_mesh *m, const float *mag, float *dmdt, unsigned terms, double t) {
+    return eval_nodes(m, mag, dmdt, terms, t, kModeRhs, "nm_llg_rhs");
+}
+
+extern "C" nm_status nm_demag_cell_field(nm_mesh *m, const float *mag, float *hout) {
+    NM_REQUIRE(m && mag && hout, NM_EINVAL, "nm_demag_cell_field: NULL argument");
+    NM_REQUIRE(m->tensor_ready, NM_EINVAL, "nm_demag_cell_field: call nm_demag_tensor_init first");
+    NM_HIP(demag_forward_conv_inverse(m, mag), "nm_demag_cell_field");
+    NM_HIP(hipMemcpyAsync(hout, m->hd, sizeof(float) * 3 * m->n_cells, hipMemcpyDeviceToDevice, m->stream),
+           "nm_demag_cell_field");
+    return NM_OK;
+}
+
+extern "C" nm_status nm_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]) {
+    NM_REQUIRE(m && mag && e, NM_EINVAL, "nm_energy: NULL argument");
+    nm_status st = check_terms(m, terms, "nm_energy");
+    if (st != NM_OK) return st;
+    if (terms & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, mag), "nm_energy");
+    NM_HIP(launch_energy(m, mag, terms, t, e), "nm_energy");
+    return NM_OK;
+}
+
+// --------------------------------------------------------------- stepping
+namespace {
+
+// Dormand & Prince (1980) RK5(4)7FM tableau
+const double kDPc[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+const double kDPa[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84},
+};
+const double kDPb[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
+const double kDPbs[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
+                         187.0 / 2100, 1.0 / 40};
+
+hipError_t dp45_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *mstate) {
+    if (terms & NM_T_DEMAG) {
+        hipError_t e = demag_forward_conv_inverse_ctrl(m, in, m->ctrl);
+        if (e != hipSuccess) return e;
+    }
+    StageSpec sp{};
+    sp.mode = kModeDP45;
+    sp.stage = s;
+    sp.in = in;
+    sp.mstate = mstate;
+    sp.y_next = s < 7 ? m->y[(s + 1) % 2] : nullptr;
+    sp.c = kDPc[s - 1];
+    sp.use_ctrl = true;
+    for (int j = 0; j < 7; ++j) {
+        sp.a[j] = (s < 7 && j < 6) ? kDPa[s][j] : 0.0;  // row s+1 (1-based) of the tableau
+        sp.e[j] = kDPb[j] - kDPbs[j];
+    }
+    return launch_stencil(m, terms, sp);
+}
+
+hipError_t rk4_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *y_next, float *mstate) {
+    if (terms & NM_T_DEMAG) {
+        hipError_t e = demag_forward_conv_inverse_ctrl(m, in, m->ctrl);
+        if (e != hipSuccess) return e;
+    }
+    StageSpec sp{};
+    sp.mode = kModeRK4;
+    sp.stage = s;
+    sp.in = in;
+    sp.y_next = y_next;
+    sp.mstate = mstate;
+    sp.c = s == 1 ? 0.0 : (s == 4 ? 1.0 : 0.5);
+    sp.use_ctrl = true;
+    return launch_stencil(m, terms, sp);
+}
+
+}  // namespace
+
+extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm_integrator *in,
+                                 double t_end, long max_steps) {
+    NM_REQUIRE(m && mag && clk && in, NM_EINVAL, "nm_llg_step: NULL argument");
+    NM_REQUIRE(in->method == NM_RK4 || in->method == NM_DP45, NM_EINVAL, "nm_llg_step: unknown method");
+    NM_REQUIRE(std::isfinite(clk->t) && std::isfinite(t_end) && t_end >= clk->t, NM_EINVAL,
+               "nm_llg_step: need finite t <= t_end");
+    NM_REQUIRE(std::isfinite(clk->dt) && clk->dt > 0.0, NM_EINVAL, "nm_llg_step: clk->dt must be > 0");
+    NM_REQUIRE(max_steps > 0, NM_EINVAL, "nm_llg_step: max_steps must be > 0");
+    if (in->method == NM_DP45)
+        NM_REQUIRE(in->rtol > 0.0 && in->atol > 0.0, NM_EINVAL, "nm_llg_step: DP45 needs rtol, atol > 0");
+    NM_REQUIRE(!in->log || in->log_capacity >= 0, NM_EINVAL, "nm_llg_step: bad log capacity");
+    nm_status st = check_terms(m, in->terms, "nm_llg_step");
+    if (st != NM_OK) return st;
+    if (t_end == clk->t) return NM_OK;
+    NM_REQUIRE(m->n_active > 0, NM_EINVAL, "nm_llg_step: the mesh has no magnetic node");
+
+    Ctrl *C = m->ctrl_host;
+    std::memset(C, 0, sizeof(Ctrl));
+    C->t = clk->t;
+    C->dt_prop = clk->dt;
+    C->dt = std::fmin(clk->dt, t_end - clk->t);
+    C->t_end = t_end;
+    C->rtol = in->rtol;
+    C->atol = in->atol;
+    C->dt_min = in->dt_min;
+    C->dt_max = in->dt_max;
+    C->stop_torque = in->stop_torque;
+    C->norm_scale = 1.0 / (3.0 * (double)m->n_active);
+    C->max_accepted = max_steps;
+    C->log = in->log;
+    C->log_cap = in->log ? in->log_capacity : 0;
+    NM_HIP(hipMemcpyAsync(m->ctrl, C, sizeof(Ctrl), hipMemcpyHostToDevice, m->stream), "nm_llg_step");
+    NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
+    const unsigned terms = in->terms;
+
+    if (in->method == NM_RK4) {
+        const double span = (t_end - clk->t) / clk->dt;
+        long nsteps = (long)std::ceil(span * (1.0 - 1e-12));
+        if (nsteps < 1) nsteps = 1;
+        if (nsteps > max_steps) nsteps = max_steps;
+        for (long k = 0; k < nsteps; ++k) {
+            NM_HIP(rk4_stage(m, terms, 1, mag, m->y[0], mag), "nm_llg_step");
+            NM_HIP(rk4_stage(m, terms, 2, m->y[0], m->y[1], mag), "nm_llg_step");
+            NM_HIP(rk4_stage(m, terms, 3, m->y[1], m->y[0], mag), "nm_llg_step");
+            NM_HIP(rk4_stage(m, terms, 4, m->y[0], nullptr, mag), "nm_llg_step");
+            NM_HIP(launch_rk4_advance(m), "nm_llg_step");
+        }
+        NM_HIP(hipMemcpyAsync(C, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream), "nm_llg_step");
+        NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
+    } else {
+        // first stage (FSAL keeps k1 for every later attempt)
+        NM_HIP(dp45_stage(m, terms, 1, mag, mag), "nm_llg_step");
+        const int batch = 16;
+        long long seen = -1;
+        for (;;) {
+            for (int q = 0; q < batch; ++q) {
+                for (int s = 2; s <= 7; ++s) NM_HIP(dp45_stage(m, terms, s, m->y[s % 2], mag), "nm_llg_step");
+                NM_HIP(launch_dp45_control(m), "nm_llg_step");
+                NM_HIP(launch_dp45_finish(m, mag, kDPa[1][0]), "nm_llg_step");
+            }
+            NM_HIP(hipMemcpyAsync(C, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream), "nm_llg_step");
+            NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
+            if (C->done) break;
+            // every attempt either advances t or shrinks dt towards dt_min, so
+            // the controller must make progress; anything else is a bug
+            NM_REQUIRE(C->attempts > seen, NM_EHIP, "nm_llg_step: controller made no progress");
+            seen = C->attempts;
+        }
+        C->rhs_evals += 1;
+    }
+    clk->t = C->t;
+    clk->dt = in->method == NM_RK4 ? clk->dt : C->dt_prop;
+    clk->accepted += C->accepted;
+    clk->rejected += C->rejected;
+    clk->rhs_evals += C->rhs_evals;
+    clk->max_torque = C->max_torque;
+    if (C->status == NM_ENONFINITE) {
+        set_error("nm_llg_step: non-finite error norm or state");
+        return NM_ENONFINITE;
+    }
+    if (C->status == NM_ESTEPSIZE) {
+        set_error("nm_llg_step: step size fell below dt_min");
+        return NM_ESTEPSIZE;
+    }
+    return NM_OK;
+}
+
+extern "C" const char *nm_last_error(void) { return g_error.c_str(); }

@@ -1,0 +1,383 @@
+// Demagnetisation field by zero-padded FFT convolution (Sec. 3.2), gfx950.
+//
+// Pipeline for a nodal magnetisation m (float32, SoA, x fastest):
+//   x pass   nodal -> cell average M_c = Ms_c (1/8) sum of the 8 corners (the
+//            exact cell mean of the trilinear m^h), real-to-complex FFT along
+//            x (length P1 through a complex FFT of length P1/2), only the N2 N3
+//            non-zero rows;
+//   y pass   complex FFT along y of the N3 non-zero z planes (3D), rows >= N2
+//            read as zeros;
+//   z conv   FFT along z, H^ = -N^ M^ with the real symmetric k-space tensor,
+//            inverse FFT along z, keeping the N3 planes (3D); for single-layer
+//            films (N3 = 1) the same fusion happens along y instead;
+//   y pass   inverse along y, keeping the N2 rows (3D);
+//   x pass   complex-to-real along x, keeping the N1 cells -> cell field H_c.
+// The spectrum lives in one workspace spec[3][N3][P2][K1] (K1 = P1/2 + 1):
+// every pass reads and writes whole column tiles in place, so no transposes
+// are needed and loads / stores of a tile are contiguous along x.
+// The tensor carries the 1/(P1 P2 P3) normalisation of the inverse transform.
+#include "fft_engine.h"
+
+namespace nm {
+
+__host__ __device__ constexpr int x_rows_per_block(int L) { return L >= 512 ? 1 : 512 / L; }
+
+// ---------------------------------------------------------------- x forward
+template <int L>
+__global__ void __launch_bounds__(256)
+k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
+       const float2 *__restrict__ tw, int N1, int N2, int N3, int P2, int K1,
+       const Ctrl *__restrict__ ctrl) {
+    constexpr int RB = x_rows_per_block(L);
+    constexpr int NP = 3 * RB;
+    __shared__ float2 s[NP * L];
+    if (ctrl && ctrl->done) return;
+    const int tid = threadIdx.x;
+    const int rows = N2 * N3;
+    const int row0 = blockIdx.x * RB;
+    const int NX = N1 + 1, NY = N2 + 1;
+    const long long nn = (long long)NX * NY * (N3 + 1);
+    for (int it = tid; it < RB * L; it += 256) {
+        const int rb = it / L, n = it - (it / L) * L;
+        const int row = row0 + rb;
+        float2 v[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        if (row < rows) {
+            const int y = row % N2, z = row / N2;
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                const int x = 2 * n + hh;
+                if (x < N1) {
+                    const float ms = 0.125f * Ms[((long long)z * N2 + y) * N1 + x];
+                    const long long b00 = ((long long)z * NY + y) * NX + x;
+                    const long long b01 = b00 + NX;
+                    const long long b10 = b00 + (long long)NX * NY;
+                    const long long b11 = b10 + NX;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const float *mc = mag + c * nn;
+                        const float sum = ((mc[b00] + mc[b00 + 1]) + (mc[b01] + mc[b01 + 1]))
+                                        + ((mc[b10] + mc[b10 + 1]) + (mc[b11] + mc[b11 + 1]));
+                        if (hh == 0) v[c].x = ms * sum; else v[c].y = ms * sum;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s[(c * RB + rb) * L + n] = v[c];
+    }
+    __syncthreads();
+    lds_fft<L, -1, NP, 256, false>(s, tw, tid);
+    // untangle the half-length transform: X_k = E_k + W^k O_k, W = exp(-2 pi i / P1)
+    for (int it = tid; it < RB * (L + 1); it += 256) {
+        const int rb = it / (L + 1), k = it - (it / (L + 1)) * (L + 1);
+        const int row = row0 + rb;
+        if (row >= rows) continue;
+        const int y = row % N2, z = row / N2;
+        const float2 w = twiddle<-1>(tw, k * (kTwN / (2 * L)));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 zk = s[(c * RB + rb) * L + (k & (L - 1))];
+            const float2 zc = cconj(s[(c * RB + rb) * L + ((L - k) & (L - 1))]);
+            const float2 e = cscale(cadd(zk, zc), 0.5f);
+            const float2 d = cscale(csub(zk, zc), 0.5f);
+            const float2 o = make_float2(d.y, -d.x);  // -i d
+            spec[(((long long)c * N3 + z) * P2 + y) * K1 + k] = cadd(e, cmul(w, o));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- x inverse
+template <int L>
+__global__ void __launch_bounds__(256)
+k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__restrict__ tw,
+       int N1, int N2, int N3, int P2, int K1, const Ctrl *__restrict__ ctrl) {
+    constexpr int RB = x_rows_per_block(L);
+    constexpr int NP = 3 * RB;
+    __shared__ float2 s[NP * L];
+    if (ctrl && ctrl->done) return;
+    const int tid = threadIdx.x;
+    const int rows = N2 * N3;
+    const int row0 = blockIdx.x * RB;
+    const long long nc = (long long)N1 * N2 * N3;
+    for (int it = tid; it < RB * L; it += 256) {
+        const int rb = it / L, k = it - (it / L) * L;
+        const int row = row0 + rb;
+        if (row < rows) {
+            const int y = row % N2, z = row / N2;
+            // Z_k = E_k + i O_k with E_k = X_k + conj X_{L-k},
+            // O_k = (X_k - conj X_{L-k}) W^-k: the length-L inverse then yields
+            // P1 * (a_2n + i a_2n+1)
+            const float2 wi = twiddle<1>(tw, k * (kTwN / (2 * L)));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float2 *rowp = spec + (((long long)c * N3 + z) * P2 + y) * K1;
+                const float2 xk = rowp[k];
+                const float2 xc = cconj(rowp[L - k]);
+                const float2 e = cadd(xk, xc);
+                const float2 o = cmul(csub(xk, xc), wi);
+                s[(c * RB + rb) * L + k] = make_float2(e.x - o.y, e.y + o.x);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) s[(c * RB + rb) * L + k] = make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();
+    lds_fft<L, 1, NP, 256, false>(s, tw, tid);
+    for (int it = tid; it < RB * L; it += 256) {
+        const int rb = it / L, n = it - (it / L) * L;
+        const int row = row0 + rb;
+        if (row >= rows) continue;
+        const int y = row % N2, z = row / N2;
+        const long long cb = ((long long)z * N2 + y) * N1;
+        const int x0 = 2 * n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 v = s[(c * RB + rb) * L + n];
+            if (x0 < N1) hd[c * nc + cb + x0] = v.x;
+            if (x0 + 1 < N1) hd[c * nc + cb + x0 + 1] = v.y;
+        }
+    }
+}
+
+// ------------------------------------------------------- y pass (3D, 1 comp)
+// columns (z < N3, kx < K1); elements along y at stride K1
+template <int L, int DIR, int TB>
+__global__ void __launch_bounds__(256)
+k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1, int n_in,
+        int n_out, const Ctrl *__restrict__ ctrl) {
+    __shared__ float2 s[L * TB];
+    if (ctrl && ctrl->done) return;
+    const int tid = threadIdx.x;
+    const int ncols = N3 * K1;
+    const int col0 = blockIdx.x * TB;
+    float2 *base = spec + (long long)blockIdx.y * N3 * L * K1;
+    for (int it = tid; it < L * TB; it += 256) {
+        const int b = it % TB, e = it / TB;
+        const int col = col0 + b;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < ncols && e < n_in) {
+            const int z = col / K1, kx = col - (col / K1) * K1;
+            v = base[((long long)z * L + e) * K1 + kx];
+        }
+        s[e * TB + b] = v;
+    }
+    __syncthreads();
+    lds_fft<L, DIR, TB, 256, true>(s, tw, tid);
+    for (int it = tid; it < n_out * TB; it += 256) {
+        const int b = it % TB, e = it / TB;
+        const int col = col0 + b;
+        if (col < ncols) {
+            const int z = col / K1, kx = col - (col / K1) * K1;
+            base[((long long)z * L + e) * K1 + kx] = s[e * TB + b];
+        }
+    }
+}
+
+// ------------------------------------------- k-space product of one element
+__device__ __forceinline__ void tensor_apply(const float *__restrict__ T, long long tstride,
+                                             long long tidx, float sy, float sz, bool full3d,
+                                             float2 &mx, float2 &my, float2 &mz) {
+    const float xx = T[tidx], yy = T[tstride + tidx], zz = T[2 * tstride + tidx];
+    const float xy = sy * T[3 * tstride + tidx];
+    float xz = 0.f, yz = 0.f;
+    if (full3d) {
+        xz = sz * T[4 * tstride + tidx];
+        yz = sy * sz * T[5 * tstride + tidx];
+    }
+    const float2 hx = make_float2(-(xx * mx.x + xy * my.x + xz * mz.x), -(xx * mx.y + xy * my.y + xz * mz.y));
+    const float2 hy = make_float2(-(xy * mx.x + yy * my.x + yz * mz.x), -(xy * mx.y + yy * my.y + yz * mz.y));
+    const float2 hz = make_float2(-(xz * mx.x + yz * my.x + zz * mz.x), -(xz * mx.y + yz * my.y + zz * mz.y));
+    mx = hx;
+    my = hy;
+    mz = hz;
+}
+
+// ------------------------------------------- z forward + product + z inverse
+// columns (ky < P2, kx < K1) are contiguous; elements along z at stride P2 K1
+template <int L, int TB>
+__global__ void __launch_bounds__(256)
+k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
+        int N3, int P2, int K1, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
+    constexpr int NP = 3 * TB;
+    __shared__ float2 s[L * NP];
+    if (ctrl && ctrl->done) return;
+    const int tid = threadIdx.x;
+    const long long plane = (long long)P2 * K1;
+    const int ncols = P2 * K1;
+    const int col0 = blockIdx.x * TB;
+    for (int it = tid; it < L * NP; it += 256) {
+        const int p = it % NP, e = it / NP;
+        const int c = p / TB, b = p - (p / TB) * TB;
+        const int col = col0 + b;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < ncols && e < N3) v = spec[((long long)c * N3 + e) * plane + col];
+        s[e * NP + p] = v;
+    }
+    __syncthreads();
+    lds_fft<L, -1, NP, 256, true>(s, tw, tid);
+    const long long tstride = (long long)P3h * P2h * K1;
+    for (int it = tid; it < L * TB; it += 256) {
+        const int b = it % TB, kz = it / TB;
+        const int col = col0 + b;
+        if (col >= ncols) continue;
+        const int ky = col / K1, kx = col - (col / K1) * K1;
+        const bool fy = ky > P2 / 2, fz = kz > L / 2;
+        const int kyr = fy ? P2 - ky : ky, kzr = fz ? L - kz : kz;
+        const long long tidx = ((long long)kzr * P2h + kyr) * K1 + kx;
+        float2 mx = s[kz * NP + b], my = s[kz * NP + TB + b], mz = s[kz * NP + 2 * TB + b];
+        tensor_apply(T, tstride, tidx, fy ? -1.f : 1.f, fz ? -1.f : 1.f, true, mx, my, mz);
+        s[kz * NP + b] = mx;
+        s[kz * NP + TB + b] = my;
+        s[kz * NP + 2 * TB + b] = mz;
+    }
+    __syncthreads();
+    lds_fft<L, 1, NP, 256, true>(s, tw, tid);
+    for (int it = tid; it < N3 * NP; it += 256) {
+        const int p = it % NP, e = it / NP;
+        const int c = p / TB, b = p - (p / TB) * TB;
+        const int col = col0 + b;
+        if (col < ncols) spec[((long long)c * N3 + e) * plane + col] = s[e * NP + p];
+    }
+}
+
+// ------------------------------------ y forward + product + y inverse (N3 = 1)
+template <int L, int TB>
+__global__ void __launch_bounds__(256)
+k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
+        int N2, int K1, int P2h, const Ctrl *__restrict__ ctrl) {
+    constexpr int NP = 3 * TB;
+    __shared__ float2 s[L * NP];
+    if (ctrl && ctrl->done) return;
+    const int tid = threadIdx.x;
+    const long long cstride = (long long)L * K1;
+    const int col0 = blockIdx.x * TB;
+    for (int it = tid; it < L * NP; it += 256) {
+        const int p = it % NP, e = it / NP;
+        const int c = p / TB, b = p - (p / TB) * TB;
+        const int col = col0 + b;
+        float2 v = make_float2(0.f, 0.f);
+        if (col < K1 && e < N2) v = spec[c * cstride + (long long)e * K1 + col];
+        s[e * NP + p] = v;
+    }
+    __syncthreads();
+    lds_fft<L, -1, NP, 256, true>(s, tw, tid);
+    const long long tstride = (long long)P2h * K1;
+    for (int it = tid; it < L * TB; it += 256) {
+        const int b = it % TB, ky = it / TB;
+        const int col = col0 + b;
+        if (col >= K1) continue;
+        const bool fy = ky > L / 2;
+        const int kyr = fy ? L - ky : ky;
+        float2 mx = s[ky * NP + b], my = s[ky * NP + TB + b], mz = s[ky * NP + 2 * TB + b];
+        tensor_apply(T, tstride, (long long)kyr * K1 + col, fy ? -1.f : 1.f, 1.f, false, mx, my, mz);
+        s[ky * NP + b] = mx;
+        s[ky * NP + TB + b] = my;
+        s[ky * NP + 2 * TB + b] = mz;
+    }
+    __syncthreads();
+    lds_fft<L, 1, NP, 256, true>(s, tw, tid);
+    for (int it = tid; it < N2 * NP; it += 256) {
+        const int p = it % NP, e = it / NP;
+        const int c = p / TB, b = p - (p / TB) * TB;
+        const int col = col0 + b;
+        if (col < K1) spec[c * cstride + (long long)e * K1 + col] = s[e * NP + p];
+    }
+}
+
+// --------------------------------------------------------------- dispatch
+// column tiles: one component per block in the y passes (L * TB = 4096
+// elements), three in the fused passes (3 L TB <= 4096 elements)
+__host__ __device__ constexpr int tb_single(int L) { return L >= 1024 ? 4 : (4096 / L > 64 ? 64 : 4096 / L); }
+__host__ __device__ constexpr int tb_triple(int L) { return L <= 16 ? 64 : 1024 / L; }
+
+template <int L>
+static void launch_x_fwd(nm_mesh *m, const float *mag, const float2 *tw, const Ctrl *ctrl) {
+    constexpr int RB = x_rows_per_block(L);
+    const int rows = m->N2 * m->N3;
+    ProfScope ps(m, NM_PROF_XFWD);
+    hipLaunchKernelGGL((k_xfwd<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->stream, mag,
+                       m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->P2, m->K1, ctrl);
+}
+template <int L>
+static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    constexpr int RB = x_rows_per_block(L);
+    const int rows = m->N2 * m->N3;
+    ProfScope ps(m, NM_PROF_XINV);
+    hipLaunchKernelGGL((k_xinv<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->stream, m->spec,
+                       m->hd, tw, m->N1, m->N2, m->N3, m->P2, m->K1, ctrl);
+}
+template <int L, int DIR>
+static void launch_y(nm_mesh *m, const float2 *tw, int n_in, int n_out, const Ctrl *ctrl) {
+    constexpr int TB = tb_single(L);
+    const int ncols = m->N3 * m->K1;
+    ProfScope ps(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV);
+    hipLaunchKernelGGL((k_ypass<L, DIR, TB>), dim3((ncols + TB - 1) / TB, 3), dim3(256), 0,
+                       m->stream, m->spec, tw, m->N3, m->K1, n_in, n_out, ctrl);
+}
+template <int L>
+static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    constexpr int TB = tb_triple(L);
+    const int ncols = m->P2 * m->K1;
+    ProfScope ps(m, NM_PROF_CONV);
+    hipLaunchKernelGGL((k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->stream,
+                       m->spec, m->tensor, tw, m->N3, m->P2, m->K1, m->P2h, m->P3h, ctrl);
+}
+template <int L>
+static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    constexpr int TB = tb_triple(L);
+    ProfScope ps(m, NM_PROF_CONV);
+    hipLaunchKernelGGL((k_yconv<L, TB>), dim3((m->K1 + TB - 1) / TB), dim3(256), 0, m->stream,
+                       m->spec, m->tensor, tw, m->N2, m->K1, m->P2h, ctrl);
+}
+
+#define NM_DISPATCH_POW2(LEN, FN, ...)                       \
+    switch (LEN) {                                           \
+        case 2: FN<2>(__VA_ARGS__); break;                   \
+        case 4: FN<4>(__VA_ARGS__); break;                   \
+        case 8: FN<8>(__VA_ARGS__); break;                   \
+        case 16: FN<16>(__VA_ARGS__); break;                 \
+        case 32: FN<32>(__VA_ARGS__); break;                 \
+        case 64: FN<64>(__VA_ARGS__); break;                 \
+        case 128: FN<128>(__VA_ARGS__); break;               \
+        case 256: FN<256>(__VA_ARGS__); break;               \
+        case 512: FN<512>(__VA_ARGS__); break;               \
+        case 1024: FN<1024>(__VA_ARGS__); break;             \
+        default: return hipErrorInvalidValue;                \
+    }
+
+template <int L>
+static void launch_y_fwd(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    launch_y<L, -1>(m, tw, m->N2, L, ctrl);
+}
+template <int L>
+static void launch_y_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    launch_y<L, 1>(m, tw, L, m->N2, ctrl);
+}
+
+static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl) {
+    const float2 *tw = twiddles(m->device);
+    if (!tw) return hipErrorOutOfMemory;
+    const int L1 = m->P1 / 2;
+    if (L1 > 512) return hipErrorInvalidValue;
+    NM_DISPATCH_POW2(L1, launch_x_fwd, m, mag, tw, ctrl);
+    if (m->N3 > 1) {
+        NM_DISPATCH_POW2(m->P2, launch_y_fwd, m, tw, ctrl);
+        NM_DISPATCH_POW2(m->P3, launch_zconv, m, tw, ctrl);
+        NM_DISPATCH_POW2(m->P2, launch_y_inv, m, tw, ctrl);
+    } else {
+        NM_DISPATCH_POW2(m->P2, launch_yconv, m, tw, ctrl);
+    }
+    NM_DISPATCH_POW2(L1, launch_x_inv, m, tw, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag) {
+    return demag_pipeline(m, mag, nullptr);
+}
+
+hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl) {
+    return demag_pipeline(m, mag, ctrl);
+}
+
+}  // namespace nm

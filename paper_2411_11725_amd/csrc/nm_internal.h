@@ -1,0 +1,131 @@
+// Internal declarations of the MI355X nodal finite-difference library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "nm.h"
+
+namespace nm {
+
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;  // mu0 = 4 pi 1e-7
+constexpr int kTwN = 4096;        // twiddle table: tw[t] = exp(-2 pi i t / kTwN)
+constexpr int kMaxFFT = 1024;     // longest padded axis handled
+constexpr int kBlock = 256;       // threads per block of the pointwise kernels
+
+// Device-resident integrator state (read by every stepping kernel so that a
+// whole attempt can be replayed without host round trips).
+struct Ctrl {
+    double t, dt, dt_prop, t_end;
+    double rtol, atol, dt_min, dt_max, stop_torque;
+    double err, max_torque;
+    double norm_scale;       // 1 / (3 * active nodes): RMS over node components
+    long long accepted, rejected, rhs_evals, attempts, max_accepted;
+    int done, status, rejected_last, accept;
+    double *log;
+    long long log_cap;
+};
+
+// Block partials written by the last DP45 stage and reduced by the controller.
+struct ErrPartial {
+    double sumsq;
+    float maxf;
+    int nonfinite;
+};
+
+struct ProfState;  // per-kernel event timing (measurement only)
+
+}  // namespace nm
+
+struct nm_mesh {
+    int N1, N2, N3;          // cells
+    int NX, NY, NZ;          // nodes per axis (N + 1)
+    int P1, P2, P3;          // padded FFT lengths (powers of two)
+    int K1;                  // P1 / 2 + 1 complex x-frequencies
+    int P2h, P3h;            // P2 / 2 + 1, P3 / 2 + 1 stored tensor frequencies
+    double h[3], V, gamma;
+    int64_t n_nodes, n_cells;
+    hipStream_t stream;
+    int device;
+
+    // owned material copies (cell arrays) and derived quantities
+    float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;
+    float *wc;               // mu0 Ms_c V / 8: weight of a cell-constant field
+    float h_uniform[3], drive_amp[3];
+    double drive_freq, drive_phase;
+    bool has_anis, has_hcell, has_drive;
+    float Kp[8], Mp[8];      // element matrices by axis-difference pattern
+
+    // nodal coefficients
+    float *inv_mass, *alpha_n, *gp_n;
+
+    // demagnetisation
+    float2 *spec;            // [3][N3][P2][K1] complex workspace
+    float *tensor;           // [6][P3h][P2h][K1] real k-space tensor / (P1 P2 P3)
+    float *hd;               // [3][n_cells] demag cell field
+    bool tensor_ready;
+
+    // integrator buffers
+    float *y[2], *acc, *k[7];
+    nm::Ctrl *ctrl;          // device controller state
+    nm::Ctrl *ctrl_host;     // pinned mirror for read-back
+    int64_t n_active;        // nodes with positive lumped mass
+    nm::ErrPartial *partials;
+    int n_partials;
+    double *ered;            // energy block partials [4][n_eblocks]
+    int n_eblocks;
+    nm::ProfState *prof;     // non-null while profiling is enabled
+};
+
+namespace nm {
+
+void set_error(const std::string &msg);
+
+// event pair around one kernel launch when the mesh is being profiled
+void prof_begin(nm_mesh *m, int slot);
+void prof_end(nm_mesh *m, int slot);
+void prof_free(nm_mesh *m);
+struct ProfScope {
+    nm_mesh *m;
+    int slot;
+    ProfScope(nm_mesh *mm, int s) : m(mm), slot(s) { if (m->prof) prof_begin(m, s); }
+    ~ProfScope() { if (m->prof) prof_end(m, slot); }
+};
+const float2 *twiddles(int device);   // per-device table (created on first use)
+
+// demag FFT pipeline: m (nodal, stage input) -> mesh->hd (cell field); the
+// ctrl variant skips its kernels once the device controller reports done
+hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag);
+hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl);
+
+// tensor set-up: octant in float64 and the k-space transform
+hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], double *out,
+                                hipStream_t s);
+hipError_t build_kspace_tensor(nm_mesh *m);
+
+// stencil / LLG / stage kernels
+enum StencilMode { kModeField = 0, kModeRhs = 1, kModeRK4 = 2, kModeDP45 = 3 };
+
+struct StageSpec {
+    int mode;
+    int stage;               // 1-based stage index
+    const float *in;         // stage input (nodal m)
+    float *out;              // field / rhs output (modes 0, 1)
+    float *y_next;           // next stage input
+    float *mstate;           // state at the start of the step (stepping modes)
+    double t0;               // time when ctrl is null
+    double c;                // stage time = t + c dt
+    double a[7];             // coefficients of y_{s+1} = m + dt sum_j a_j k_j
+    double e[7];             // DP45 error weights b_j - b*_j
+    bool use_ctrl;
+};
+
+hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp);
+hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]);
+hipError_t launch_dp45_control(nm_mesh *m);
+hipError_t launch_dp45_finish(nm_mesh *m, float *mstate, double a21);
+hipError_t launch_rk4_advance(nm_mesh *m);
+
+}  // namespace nm

@@ -1,0 +1,116 @@
+// Per-kernel timing with HIP events (measurement only; off by default).
+#include <vector>
+
+#include "nm_internal.h"
+
+namespace nm {
+
+struct ProfState {
+    std::vector<hipEvent_t> pool;                 // free events
+    std::vector<int> slot;                        // pending launches
+    std::vector<hipEvent_t> start, stop;
+    hipEvent_t open[NM_PROF_SLOTS] = {};
+    double ms[NM_PROF_SLOTS] = {};
+    long long count[NM_PROF_SLOTS] = {};
+};
+
+static hipEvent_t take(ProfState *p) {
+    if (p->pool.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+}
+
+void prof_begin(nm_mesh *m, int s) {
+    ProfState *p = m->prof;
+    hipEvent_t e = take(p);
+    if (e && hipEventRecord(e, m->stream) == hipSuccess) p->open[s] = e;
+}
+
+void prof_end(nm_mesh *m, int s) {
+    ProfState *p = m->prof;
+    hipEvent_t b = p->open[s];
+    p->open[s] = nullptr;
+    if (!b) return;
+    hipEvent_t e = take(p);
+    if (!e || hipEventRecord(e, m->stream) != hipSuccess) {
+        p->pool.push_back(b);
+        return;
+    }
+    p->slot.push_back(s);
+    p->start.push_back(b);
+    p->stop.push_back(e);
+}
+
+static void drain(ProfState *p) {
+    for (size_t i = 0; i < p->slot.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->start[i], p->stop[i]) == hipSuccess) {
+            p->ms[p->slot[i]] += ms;
+            p->count[p->slot[i]] += 1;
+        }
+        p->pool.push_back(p->start[i]);
+        p->pool.push_back(p->stop[i]);
+    }
+    p->slot.clear();
+    p->start.clear();
+    p->stop.clear();
+}
+
+void prof_free(nm_mesh *m) {
+    if (!m->prof) return;
+    hipStreamSynchronize(m->stream);
+    drain(m->prof);
+    for (hipEvent_t e : m->prof->pool) hipEventDestroy(e);
+    delete m->prof;
+    m->prof = nullptr;
+}
+
+}  // namespace nm
+
+using namespace nm;
+
+extern "C" nm_status nm_profile_enable(nm_mesh *m, int on) {
+    if (!m) {
+        set_error("nm_profile_enable: NULL mesh");
+        return NM_EINVAL;
+    }
+    if (!on) {
+        prof_free(m);
+        return NM_OK;
+    }
+    prof_free(m);
+    m->prof = new ProfState();
+    for (int i = 0; i < 4096; ++i) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        m->prof->pool.push_back(e);
+    }
+    return NM_OK;
+}
+
+extern "C" nm_status nm_profile_read(nm_mesh *m, double ms[NM_PROF_SLOTS], long long counts[NM_PROF_SLOTS]) {
+    if (!m || !ms || !counts) {
+        set_error("nm_profile_read: NULL argument");
+        return NM_EINVAL;
+    }
+    for (int s = 0; s < NM_PROF_SLOTS; ++s) {
+        ms[s] = 0.0;
+        counts[s] = 0;
+    }
+    if (!m->prof) return NM_OK;
+    if (hipStreamSynchronize(m->stream) != hipSuccess) {
+        set_error("nm_profile_read: stream synchronisation failed");
+        return NM_EHIP;
+    }
+    drain(m->prof);
+    for (int s = 0; s < NM_PROF_SLOTS; ++s) {
+        ms[s] = m->prof->ms[s];
+        counts[s] = m->prof->count[s];
+    }
+    return NM_OK;
+}
