@@ -122,7 +122,7 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
     s->nc = (long long)n1 * n2 * n3;
     s->spec = 3LL * n3 * s->P2 * s->K1;
     s->tensor = 6LL * s->P3h * s->P2h * s->K1;
-    s->partials = (s->nn + 255) / 256;
+    s->partials = (s->nn + 255) / 256;   // one DP45 error partial per node block
     s->eblocks = (s->nc + 255) / 256;
     return true;
 }
@@ -130,6 +130,7 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
 static size_t footprint(const Sizes &s) {
     size_t b = 0;
     b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive
+    b += sizeof(float) * s.nc * (4 + 4 + 3 + 1);              // cellA, cellB, wstat, wdrive
     b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
     b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
     b += sizeof(float) * 3 * s.nc;                              // demag cell field
@@ -138,12 +139,22 @@ static size_t footprint(const Sizes &s) {
     return b;
 }
 
+static void drop_graph(nm_mesh *m) {
+    if (m->gexec) hipGraphExecDestroy(m->gexec);
+    m->gexec = nullptr;
+    m->g_method = 0;
+    m->g_terms = 0;
+    m->g_mag = nullptr;
+}
+
 static void free_mesh(nm_mesh *m) {
     if (!m) return;
     prof_free(m);
+    drop_graph(m);
+    if (m->cap_stream) hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
-                    m->ctrl, m->partials, m->ered};
+                    m->ctrl, m->partials, m->ered, m->cellA, m->cellB, m->wstat, m->wdrive};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int j = 0; j < 7; ++j)
@@ -224,11 +235,17 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     }
 
     hipError_t e = hipGetDevice(&m->device);
+    // the per-device twiddle table is built here, never inside a graph capture
+    if (e == hipSuccess && !twiddles(m->device)) e = hipErrorOutOfMemory;
     const long long nc = s.nc, nn = s.nn;
     if (e == hipSuccess) e = dalloc(&m->Ms, nc);
     if (e == hipSuccess) e = dalloc(&m->A2, nc);
     if (e == hipSuccess) e = dalloc(&m->wc, nc);
     if (e == hipSuccess) e = dalloc(&m->h_cell, 3 * nc);
+    if (e == hipSuccess) e = dalloc(&m->cellA, nc);
+    if (e == hipSuccess) e = dalloc(&m->cellB, nc);
+    if (e == hipSuccess) e = dalloc(&m->wstat, 3 * nc);
+    if (e == hipSuccess && m->has_drive) e = dalloc(&m->wdrive, nc);
     if (e == hipSuccess && m->has_anis) e = dalloc(&m->Ku, nc);
     if (e == hipSuccess && m->has_anis) e = dalloc(&m->easy, 3 * nc);
     if (e == hipSuccess && m->has_drive) e = dalloc(&m->drive_mask, nc);
@@ -246,6 +263,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess) e = dalloc(&m->partials, s.partials);
     if (e == hipSuccess) e = dalloc(&m->ered, 4 * s.eblocks + 4);
     if (e == hipSuccess) e = hipHostMalloc((void **)&m->ctrl_host, sizeof(Ctrl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         set_error(std::string("nm_mesh_create: allocation failed: ") + hipGetErrorString(e));
         free_mesh(m);
@@ -272,6 +290,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
                            m->acc, m->wc, m->inv_mass, m->alpha_n, m->gp_n, m->N1, m->N2, m->N3,
                            m->gamma);
         e = hipGetLastError();
+        if (e == hipSuccess) e = launch_cell_pack(m);
     }
     std::vector<float> im;
     if (e == hipSuccess) {
@@ -310,14 +329,17 @@ extern "C" nm_status nm_mesh_info(const nm_mesh *m, int64_t *n_nodes, int64_t *n
 
 extern "C" nm_status nm_mesh_set_field(nm_mesh *m, const float *h_cell) {
     NM_REQUIRE(m, NM_EINVAL, "nm_mesh_set_field: NULL mesh");
+    drop_graph(m);  // the field map is baked into captured kernel arguments
     if (!h_cell) {
         m->has_hcell = false;
+        NM_HIP(launch_cell_pack(m), "nm_mesh_set_field");
         return NM_OK;
     }
     NM_HIP(hipMemcpyAsync(m->h_cell, h_cell, sizeof(float) * 3 * m->n_cells, hipMemcpyDeviceToDevice,
                           m->stream),
            "nm_mesh_set_field");
     m->has_hcell = true;
+    NM_HIP(launch_cell_pack(m), "nm_mesh_set_field");
     return NM_OK;
 }
 
@@ -356,7 +378,8 @@ static nm_status eval_nodes(nm_mesh *m, const float *mag, float *out, unsigned t
     NM_REQUIRE(std::isfinite(t), NM_EINVAL, std::string(who) + ": non-finite time");
     nm_status st = check_terms(m, terms, who);
     if (st != NM_OK) return st;
-    if (terms & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, mag), who);
+    if (terms & NM_T_DEMAG)
+        NM_HIP(demag_forward_conv_inverse(m, mag, (terms & NM_T_ZEEMAN) ? 2 : 1), who);
     StageSpec sp{};
     sp.mode = mode;
     sp.stage = 0;
@@ -379,7 +402,7 @@ extern "C" nm_status nm_llg_rhs(nm_mesh *m, const float *mag, float *dmdt, unsig
 extern "C" nm_status nm_demag_cell_field(nm_mesh *m, const float *mag, float *hout) {
     NM_REQUIRE(m && mag && hout, NM_EINVAL, "nm_demag_cell_field: NULL argument");
     NM_REQUIRE(m->tensor_ready, NM_EINVAL, "nm_demag_cell_field: call nm_demag_tensor_init first");
-    NM_HIP(demag_forward_conv_inverse(m, mag), "nm_demag_cell_field");
+    NM_HIP(demag_forward_conv_inverse(m, mag, 0), "nm_demag_cell_field");
     NM_HIP(hipMemcpyAsync(hout, m->hd, sizeof(float) * 3 * m->n_cells, hipMemcpyDeviceToDevice, m->stream),
            "nm_demag_cell_field");
     return NM_OK;
@@ -389,7 +412,7 @@ extern "C" nm_status nm_energy(nm_mesh *m, const float *mag, unsigned terms, dou
     NM_REQUIRE(m && mag && e, NM_EINVAL, "nm_energy: NULL argument");
     nm_status st = check_terms(m, terms, "nm_energy");
     if (st != NM_OK) return st;
-    if (terms & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, mag), "nm_energy");
+    if (terms & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, mag, 0), "nm_energy");
     NM_HIP(launch_energy(m, mag, terms, t, e), "nm_energy");
     return NM_OK;
 }
@@ -397,55 +420,30 @@ extern "C" nm_status nm_energy(nm_mesh *m, const float *mag, unsigned terms, dou
 // --------------------------------------------------------------- stepping
 namespace {
 
-// Dormand & Prince (1980) RK5(4)7FM tableau
-const double kDPc[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
-const double kDPa[7][6] = {
-    {0, 0, 0, 0, 0, 0},
-    {1.0 / 5, 0, 0, 0, 0, 0},
-    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
-    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
-    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
-    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
-    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84},
-};
-const double kDPb[7] = {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0};
-const double kDPbs[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
-                         187.0 / 2100, 1.0 / 40};
-
-hipError_t dp45_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *mstate) {
+hipError_t stage(nm_mesh *m, unsigned terms, int mode, int s, const float *in, float *y_next,
+                 float *mstate) {
     if (terms & NM_T_DEMAG) {
-        hipError_t e = demag_forward_conv_inverse_ctrl(m, in, m->ctrl);
+        hipError_t e = demag_forward_conv_inverse_ctrl(m, in, m->ctrl, (terms & NM_T_ZEEMAN) ? 2 : 1);
         if (e != hipSuccess) return e;
     }
     StageSpec sp{};
-    sp.mode = kModeDP45;
-    sp.stage = s;
-    sp.in = in;
-    sp.mstate = mstate;
-    sp.y_next = s < 7 ? m->y[(s + 1) % 2] : nullptr;
-    sp.c = kDPc[s - 1];
-    sp.use_ctrl = true;
-    for (int j = 0; j < 7; ++j) {
-        sp.a[j] = (s < 7 && j < 6) ? kDPa[s][j] : 0.0;  // row s+1 (1-based) of the tableau
-        sp.e[j] = kDPb[j] - kDPbs[j];
-    }
-    return launch_stencil(m, terms, sp);
-}
-
-hipError_t rk4_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *y_next, float *mstate) {
-    if (terms & NM_T_DEMAG) {
-        hipError_t e = demag_forward_conv_inverse_ctrl(m, in, m->ctrl);
-        if (e != hipSuccess) return e;
-    }
-    StageSpec sp{};
-    sp.mode = kModeRK4;
+    sp.mode = mode;
     sp.stage = s;
     sp.in = in;
     sp.y_next = y_next;
     sp.mstate = mstate;
-    sp.c = s == 1 ? 0.0 : (s == 4 ? 1.0 : 0.5);
     sp.use_ctrl = true;
     return launch_stencil(m, terms, sp);
+}
+
+// DP45 stage s reads y_s from y[s % 2] (stage 1 reads the state) and writes
+// y_{s+1} to y[(s + 1) % 2]
+hipError_t dp45_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *mstate) {
+    return stage(m, terms, kModeDP45, s, in, s < 7 ? m->y[(s + 1) % 2] : nullptr, mstate);
+}
+
+hipError_t rk4_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *y_next, float *mstate) {
+    return stage(m, terms, kModeRK4, s, in, y_next, mstate);
 }
 
 }  // namespace
@@ -485,31 +483,62 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
     NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
     const unsigned terms = in->terms;
 
+    // one batch of steps / attempts, either launched directly (profiling)
+    // or captured once into a graph and replayed
+    const int batch = in->method == NM_RK4 ? 8 : 16;
+    auto enqueue_batch = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < batch && e == hipSuccess; ++q) {
+            if (in->method == NM_RK4) {
+                if (e == hipSuccess) e = rk4_stage(m, terms, 1, mag, m->y[0], mag);
+                if (e == hipSuccess) e = rk4_stage(m, terms, 2, m->y[0], m->y[1], mag);
+                if (e == hipSuccess) e = rk4_stage(m, terms, 3, m->y[1], m->y[0], mag);
+                if (e == hipSuccess) e = rk4_stage(m, terms, 4, m->y[0], nullptr, mag);
+                if (e == hipSuccess) e = launch_rk4_advance(m);
+            } else {
+                for (int s = 2; s <= 7 && e == hipSuccess; ++s) e = dp45_stage(m, terms, s, m->y[s % 2], mag);
+                if (e == hipSuccess) e = launch_dp45_control(m);
+                if (e == hipSuccess) e = launch_dp45_finish(m, mag);
+            }
+        }
+        return e;
+    };
+    const bool use_graph = m->prof == nullptr;
+    if (use_graph && !(m->gexec && m->g_method == in->method && m->g_terms == terms && m->g_mag == mag)) {
+        drop_graph(m);
+        hipStream_t user = m->stream;
+        m->stream = m->cap_stream;
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
+        hipError_t e2 = e == hipSuccess ? enqueue_batch() : e;
+        if (e == hipSuccess) e = hipStreamEndCapture(m->cap_stream, &graph);
+        m->stream = user;
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec, graph, nullptr, nullptr, 0);
+        if (graph) hipGraphDestroy(graph);
+        NM_HIP(e, "nm_llg_step: graph capture");
+        m->g_method = in->method;
+        m->g_terms = terms;
+        m->g_mag = mag;
+    }
+    auto run_batch = [&]() -> hipError_t {
+        return use_graph ? hipGraphLaunch(m->gexec, m->stream) : enqueue_batch();
+    };
+
     if (in->method == NM_RK4) {
         const double span = (t_end - clk->t) / clk->dt;
         long nsteps = (long)std::ceil(span * (1.0 - 1e-12));
         if (nsteps < 1) nsteps = 1;
         if (nsteps > max_steps) nsteps = max_steps;
-        for (long k = 0; k < nsteps; ++k) {
-            NM_HIP(rk4_stage(m, terms, 1, mag, m->y[0], mag), "nm_llg_step");
-            NM_HIP(rk4_stage(m, terms, 2, m->y[0], m->y[1], mag), "nm_llg_step");
-            NM_HIP(rk4_stage(m, terms, 3, m->y[1], m->y[0], mag), "nm_llg_step");
-            NM_HIP(rk4_stage(m, terms, 4, m->y[0], nullptr, mag), "nm_llg_step");
-            NM_HIP(launch_rk4_advance(m), "nm_llg_step");
-        }
+        for (long k = 0; k < nsteps; k += batch) NM_HIP(run_batch(), "nm_llg_step");
         NM_HIP(hipMemcpyAsync(C, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream), "nm_llg_step");
         NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
     } else {
         // first stage (FSAL keeps k1 for every later attempt)
         NM_HIP(dp45_stage(m, terms, 1, mag, mag), "nm_llg_step");
-        const int batch = 16;
         long long seen = -1;
         for (;;) {
-            for (int q = 0; q < batch; ++q) {
-                for (int s = 2; s <= 7; ++s) NM_HIP(dp45_stage(m, terms, s, m->y[s % 2], mag), "nm_llg_step");
-                NM_HIP(launch_dp45_control(m), "nm_llg_step");
-                NM_HIP(launch_dp45_finish(m, mag, kDPa[1][0]), "nm_llg_step");
-            }
+            NM_HIP(run_batch(), "nm_llg_step");
             NM_HIP(hipMemcpyAsync(C, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream), "nm_llg_step");
             NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
             if (C->done) break;

@@ -23,6 +23,9 @@ namespace nm {
 __host__ __device__ constexpr int x_rows_per_block(int L) { return L >= 512 ? 1 : 512 / L; }
 
 // ---------------------------------------------------------------- x forward
+// block (by, z): the RB cell rows y0 <= y < y0 + RB of plane z.  The node rows
+// they touch (y0 .. y0 + RB at z and z + 1) are staged in LDS once, so every
+// node value is fetched once per block rather than once per adjacent cell.
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
@@ -31,32 +34,39 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
+    extern __shared__ float nodes[];  // [3][2][RB + 1][NX]
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
-    const int rows = N2 * N3;
-    const int row0 = blockIdx.x * RB;
+    const int y0 = blockIdx.x * RB, z = blockIdx.y;
+    const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
     const long long nn = (long long)NX * NY * (N3 + 1);
+    const int per = (RB + 1) * NX;
+    for (int i = tid; i < 6 * per; i += 256) {
+        const int c = i / (2 * per);
+        const int rem = i - c * 2 * per;
+        const int zz = rem / per;
+        const int rr = rem - zz * per;
+        const int yy = rr / NX, xx = rr - (rr / NX) * NX;
+        const int gy = y0 + yy;
+        nodes[i] = gy < NY ? mag[c * nn + ((long long)(z + zz) * NY + gy) * NX + xx] : 0.f;
+    }
+    __syncthreads();
     for (int it = tid; it < RB * L; it += 256) {
         const int rb = it / L, n = it - (it / L) * L;
-        const int row = row0 + rb;
         float2 v[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        if (row < rows) {
-            const int y = row % N2, z = row / N2;
+        if (rb < nrows) {
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 const int x = 2 * n + hh;
                 if (x < N1) {
-                    const float ms = 0.125f * Ms[((long long)z * N2 + y) * N1 + x];
-                    const long long b00 = ((long long)z * NY + y) * NX + x;
-                    const long long b01 = b00 + NX;
-                    const long long b10 = b00 + (long long)NX * NY;
-                    const long long b11 = b10 + NX;
+                    const float ms = 0.125f * Ms[((long long)z * N2 + y0 + rb) * N1 + x];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float *mc = mag + c * nn;
-                        const float sum = ((mc[b00] + mc[b00 + 1]) + (mc[b01] + mc[b01 + 1]))
-                                        + ((mc[b10] + mc[b10 + 1]) + (mc[b11] + mc[b11 + 1]));
+                        const float *b0 = nodes + (c * 2 + 0) * per + rb * NX + x;  // (z, y)
+                        const float *b1 = nodes + (c * 2 + 1) * per + rb * NX + x;  // (z + 1, y)
+                        const float sum = ((b0[0] + b0[1]) + (b0[NX] + b0[NX + 1]))
+                                        + ((b1[0] + b1[1]) + (b1[NX] + b1[NX + 1]));
                         if (hh == 0) v[c].x = ms * sum; else v[c].y = ms * sum;
                     }
                 }
@@ -70,9 +80,8 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     // untangle the half-length transform: X_k = E_k + W^k O_k, W = exp(-2 pi i / P1)
     for (int it = tid; it < RB * (L + 1); it += 256) {
         const int rb = it / (L + 1), k = it - (it / (L + 1)) * (L + 1);
-        const int row = row0 + rb;
-        if (row >= rows) continue;
-        const int y = row % N2, z = row / N2;
+        if (rb >= nrows) continue;
+        const int y = y0 + rb;
         const float2 w = twiddle<-1>(tw, k * (kTwN / (2 * L)));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -90,7 +99,8 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__restrict__ tw,
-       int N1, int N2, int N3, int P2, int K1, const Ctrl *__restrict__ ctrl) {
+       int N1, int N2, int N3, int P2, int K1, const float *__restrict__ wc,
+       const float *__restrict__ wstat, int src_mode, const Ctrl *__restrict__ ctrl) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
@@ -131,11 +141,18 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
         const int y = row % N2, z = row / N2;
         const long long cb = ((long long)z * N2 + y) * N1;
         const int x0 = 2 * n;
+        float w0 = 1.f, w1 = 1.f;
+        if (src_mode > 0) {
+            if (x0 < N1) w0 = wc[cb + x0];
+            if (x0 + 1 < N1) w1 = wc[cb + x0 + 1];
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float2 v = s[(c * RB + rb) * L + n];
-            if (x0 < N1) hd[c * nc + cb + x0] = v.x;
-            if (x0 + 1 < N1) hd[c * nc + cb + x0 + 1] = v.y;
+            if (x0 < N1)
+                hd[c * nc + cb + x0] = src_mode == 2 ? w0 * v.x + wstat[c * nc + cb + x0] : w0 * v.x;
+            if (x0 + 1 < N1)
+                hd[c * nc + cb + x0 + 1] = src_mode == 2 ? w1 * v.y + wstat[c * nc + cb + x0 + 1] : w1 * v.y;
         }
     }
 }
@@ -294,41 +311,36 @@ __host__ __device__ constexpr int tb_triple(int L) { return L <= 16 ? 64 : 1024 
 template <int L>
 static void launch_x_fwd(nm_mesh *m, const float *mag, const float2 *tw, const Ctrl *ctrl) {
     constexpr int RB = x_rows_per_block(L);
-    const int rows = m->N2 * m->N3;
-    ProfScope ps(m, NM_PROF_XFWD);
-    hipLaunchKernelGGL((k_xfwd<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->stream, mag,
-                       m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->P2, m->K1, ctrl);
+    const unsigned shmem = (unsigned)(sizeof(float) * 6 * (RB + 1) * (m->N1 + 1));
+    NM_LAUNCH(m, NM_PROF_XFWD, (k_xfwd<L>), dim3((m->N2 + RB - 1) / RB, m->N3), dim3(256), shmem, mag,
+              m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->P2, m->K1, ctrl);
 }
 template <int L>
-static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl, int src_mode) {
     constexpr int RB = x_rows_per_block(L);
     const int rows = m->N2 * m->N3;
-    ProfScope ps(m, NM_PROF_XINV);
-    hipLaunchKernelGGL((k_xinv<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->stream, m->spec,
-                       m->hd, tw, m->N1, m->N2, m->N3, m->P2, m->K1, ctrl);
+    NM_LAUNCH(m, NM_PROF_XINV, (k_xinv<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->spec, m->hd,
+              tw, m->N1, m->N2, m->N3, m->P2, m->K1, m->wc, m->wstat, src_mode, ctrl);
 }
 template <int L, int DIR>
 static void launch_y(nm_mesh *m, const float2 *tw, int n_in, int n_out, const Ctrl *ctrl) {
     constexpr int TB = tb_single(L);
     const int ncols = m->N3 * m->K1;
-    ProfScope ps(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV);
-    hipLaunchKernelGGL((k_ypass<L, DIR, TB>), dim3((ncols + TB - 1) / TB, 3), dim3(256), 0,
-                       m->stream, m->spec, tw, m->N3, m->K1, n_in, n_out, ctrl);
+    NM_LAUNCH(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV, (k_ypass<L, DIR, TB>),
+              dim3((ncols + TB - 1) / TB, 3), dim3(256), 0, m->spec, tw, m->N3, m->K1, n_in, n_out, ctrl);
 }
 template <int L>
 static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     constexpr int TB = tb_triple(L);
     const int ncols = m->P2 * m->K1;
-    ProfScope ps(m, NM_PROF_CONV);
-    hipLaunchKernelGGL((k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->stream,
-                       m->spec, m->tensor, tw, m->N3, m->P2, m->K1, m->P2h, m->P3h, ctrl);
+    NM_LAUNCH(m, NM_PROF_CONV, (k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->spec,
+              m->tensor, tw, m->N3, m->P2, m->K1, m->P2h, m->P3h, ctrl);
 }
 template <int L>
 static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     constexpr int TB = tb_triple(L);
-    ProfScope ps(m, NM_PROF_CONV);
-    hipLaunchKernelGGL((k_yconv<L, TB>), dim3((m->K1 + TB - 1) / TB), dim3(256), 0, m->stream,
-                       m->spec, m->tensor, tw, m->N2, m->K1, m->P2h, ctrl);
+    NM_LAUNCH(m, NM_PROF_CONV, (k_yconv<L, TB>), dim3((m->K1 + TB - 1) / TB), dim3(256), 0, m->spec,
+              m->tensor, tw, m->N2, m->K1, m->P2h, ctrl);
 }
 
 #define NM_DISPATCH_POW2(LEN, FN, ...)                       \
@@ -355,7 +367,7 @@ static void launch_y_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     launch_y<L, 1>(m, tw, L, m->N2, ctrl);
 }
 
-static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl) {
+static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl, int src_mode) {
     const float2 *tw = twiddles(m->device);
     if (!tw) return hipErrorOutOfMemory;
     const int L1 = m->P1 / 2;
@@ -368,16 +380,17 @@ static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl)
     } else {
         NM_DISPATCH_POW2(m->P2, launch_yconv, m, tw, ctrl);
     }
-    NM_DISPATCH_POW2(L1, launch_x_inv, m, tw, ctrl);
+    NM_DISPATCH_POW2(L1, launch_x_inv, m, tw, ctrl, src_mode);
     return hipGetLastError();
 }
 
-hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag) {
-    return demag_pipeline(m, mag, nullptr);
+hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode) {
+    return demag_pipeline(m, mag, nullptr, src_mode);
 }
 
-hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl) {
-    return demag_pipeline(m, mag, ctrl);
+hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl,
+                                           int src_mode) {
+    return demag_pipeline(m, mag, ctrl, src_mode);
 }
 
 }  // namespace nm

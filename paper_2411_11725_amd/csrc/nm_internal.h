@@ -1,6 +1,7 @@
 // Internal declarations of the MI355X nodal finite-difference library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -53,6 +54,9 @@ struct nm_mesh {
     // owned material copies (cell arrays) and derived quantities
     float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;
     float *wc;               // mu0 Ms_c V / 8: weight of a cell-constant field
+    float4 *cellA, *cellB;   // packed per cell: {2A, Ku e}, {e, mu0 Ms V/8}
+    float *wstat;            // 3 x nc: mu0 Ms V/8 (h_uniform + h_cell)
+    float *wdrive;           // mu0 Ms V/8 * drive mask (when a drive is set)
     float h_uniform[3], drive_amp[3];
     double drive_freq, drive_phase;
     bool has_anis, has_hcell, has_drive;
@@ -77,28 +81,45 @@ struct nm_mesh {
     double *ered;            // energy block partials [4][n_eblocks]
     int n_eblocks;
     nm::ProfState *prof;     // non-null while profiling is enabled
+
+    // captured stepping graph (one batch of attempts / steps), launched on
+    // `stream`; captured on the private `cap_stream`
+    hipStream_t cap_stream;
+    hipGraphExec_t gexec;
+    int g_method;
+    unsigned g_terms;
+    float *g_mag;
 };
 
 namespace nm {
 
 void set_error(const std::string &msg);
 
-// event pair around one kernel launch when the mesh is being profiled
-void prof_begin(nm_mesh *m, int slot);
-void prof_end(nm_mesh *m, int slot);
+// Kernel launch on the mesh stream.  While the mesh is being profiled the
+// launch carries a start / stop event pair (recorded by the dispatch itself,
+// so the pair brackets exactly the kernel's execution) accumulated in `slot`.
+void prof_pair(nm_mesh *m, int slot, hipEvent_t *start, hipEvent_t *stop);
 void prof_free(nm_mesh *m);
-struct ProfScope {
-    nm_mesh *m;
-    int slot;
-    ProfScope(nm_mesh *mm, int s) : m(mm), slot(s) { if (m->prof) prof_begin(m, s); }
-    ~ProfScope() { if (m->prof) prof_end(m, slot); }
-};
-const float2 *twiddles(int device);   // per-device table (created on first use)
+#define NM_LAUNCH(mesh, slot, kernel, grid, block, shmem, ...)                                   \
+    do {                                                                                          \
+        hipEvent_t ev_a_ = nullptr, ev_b_ = nullptr;                                              \
+        if ((mesh)->prof) prof_pair((mesh), (slot), &ev_a_, &ev_b_);                              \
+        if (ev_a_ && ev_b_)                                                                       \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, (mesh)->stream, ev_a_, ev_b_, 0,    \
+                                  __VA_ARGS__);                                                   \
+        else                                                                                      \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, (mesh)->stream, __VA_ARGS__);          \
+    } while (0)
+
+const float2 *twiddles(int device);   // per-device table (built at mesh creation)
 
 // demag FFT pipeline: m (nodal, stage input) -> mesh->hd (cell field); the
 // ctrl variant skips its kernels once the device controller reports done
-hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag);
-hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl);
+// src_mode 0: hd = H_d (cell field); 1: hd = mu0 Ms V/8 H_d; 2: hd = mu0 Ms V/8
+// (H_d + h_uniform + h_cell), the weighted source the node kernel gathers
+hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode);
+hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl,
+                                           int src_mode);
 
 // tensor set-up: octant in float64 and the k-space transform
 hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], double *out,
@@ -115,17 +136,16 @@ struct StageSpec {
     float *out;              // field / rhs output (modes 0, 1)
     float *y_next;           // next stage input
     float *mstate;           // state at the start of the step (stepping modes)
-    double t0;               // time when ctrl is null
-    double c;                // stage time = t + c dt
-    double a[7];             // coefficients of y_{s+1} = m + dt sum_j a_j k_j
-    double e[7];             // DP45 error weights b_j - b*_j
-    bool use_ctrl;
+    double t0;               // time when ctrl is null (field / rhs modes)
+    bool use_ctrl;           // stepping modes: t, dt from the device controller
 };
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp);
+dim3 stencil_grid(const nm_mesh *m);   // blocks of the fused node kernel
 hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]);
 hipError_t launch_dp45_control(nm_mesh *m);
-hipError_t launch_dp45_finish(nm_mesh *m, float *mstate, double a21);
+hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
+hipError_t launch_cell_pack(nm_mesh *m);   // cellA, cellB, wstat, wdrive from the raw copies
 hipError_t launch_rk4_advance(nm_mesh *m);
 
 }  // namespace nm

@@ -5,11 +5,14 @@
 
 namespace nm {
 
+// timing-only events: no system-scope fence (cache write-back) at record time,
+// which would otherwise inflate and perturb the kernels being measured
+constexpr unsigned kProfEventFlags = hipEventDisableSystemFence;
+
 struct ProfState {
     std::vector<hipEvent_t> pool;                 // free events
     std::vector<int> slot;                        // pending launches
     std::vector<hipEvent_t> start, stop;
-    hipEvent_t open[NM_PROF_SLOTS] = {};
     double ms[NM_PROF_SLOTS] = {};
     long long count[NM_PROF_SLOTS] = {};
 };
@@ -17,7 +20,7 @@ struct ProfState {
 static hipEvent_t take(ProfState *p) {
     if (p->pool.empty()) {
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&e, kProfEventFlags) != hipSuccess) return nullptr;
         return e;
     }
     hipEvent_t e = p->pool.back();
@@ -25,25 +28,20 @@ static hipEvent_t take(ProfState *p) {
     return e;
 }
 
-void prof_begin(nm_mesh *m, int s) {
+void prof_pair(nm_mesh *m, int s, hipEvent_t *start, hipEvent_t *stop) {
     ProfState *p = m->prof;
-    hipEvent_t e = take(p);
-    if (e && hipEventRecord(e, m->stream) == hipSuccess) p->open[s] = e;
-}
-
-void prof_end(nm_mesh *m, int s) {
-    ProfState *p = m->prof;
-    hipEvent_t b = p->open[s];
-    p->open[s] = nullptr;
-    if (!b) return;
-    hipEvent_t e = take(p);
-    if (!e || hipEventRecord(e, m->stream) != hipSuccess) {
-        p->pool.push_back(b);
+    hipEvent_t a = take(p);
+    hipEvent_t b = a ? take(p) : nullptr;
+    if (!a || !b) {
+        if (a) p->pool.push_back(a);
+        *start = *stop = nullptr;
         return;
     }
     p->slot.push_back(s);
-    p->start.push_back(b);
-    p->stop.push_back(e);
+    p->start.push_back(a);
+    p->stop.push_back(b);
+    *start = a;
+    *stop = b;
 }
 
 static void drain(ProfState *p) {
@@ -87,7 +85,7 @@ extern "C" nm_status nm_profile_enable(nm_mesh *m, int on) {
     m->prof = new ProfState();
     for (int i = 0; i < 4096; ++i) {
         hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) break;
+        if (hipEventCreateWithFlags(&e, kProfEventFlags) != hipSuccess) break;
         m->prof->pool.push_back(e);
     }
     return NM_OK;

@@ -22,6 +22,11 @@ struct StencilParams {
     int N1, N2, N3, NX, NY, NZ;
     long long nn, nc;
     float Kp[8], Mp[8];
+    // node kernel: packed cell data and the pre-weighted cell-field source
+    const float4 *cellA, *cellB;   // {2A, Ku e} and {e, mu0 Ms V/8}
+    const float *src;              // 3 x nc: mu0 Ms V/8 (H_d [+ static H_ext]) or NULL
+    const float *wdrive;           // mu0 Ms V/8 * drive mask, or NULL
+    // energy kernel: raw cell data
     const float *wc, *A2, *Ku, *easy, *hcell, *dmask, *hd;
     float hu[3], damp[3];
     double dfreq, dphase;
@@ -35,120 +40,34 @@ struct StageArgs {
     float *k[7];
     const Ctrl *ctrl;
     ErrPartial *partials;
-    double t0, c;
-    double a[7], e[7];
-    int stage;
+    double t0;
 };
 
-__device__ __forceinline__ void node_field(const StencilParams &P, const float *__restrict__ m,
-                                           long long n, double t, float mn[3], float H[3]) {
-    const int x = (int)(n % P.NX);
-    const long long r = n / P.NX;
-    const int y = (int)(r % P.NY);
-    const int z = (int)(r / P.NY);
-    const long long nn = P.nn, nc = P.nc;
-    mn[0] = m[n];
-    mn[1] = m[nn + n];
-    mn[2] = m[2 * nn + n];
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f;   // dE/dm of exchange + anisotropy
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;   // sum_c mu0 Ms_c V/8 (H_ext + H_d)_c
-    const bool ex = P.terms & NM_T_EXCHANGE;
-    const bool an = (P.terms & NM_T_ANIS) && P.Ku;
-    const bool ze = P.terms & NM_T_ZEEMAN;
-    const bool dm = (P.terms & NM_T_DEMAG) && P.hd;
-    float sdrive = 0.f;
-    if (ze && P.dmask) sdrive = (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
-#pragma unroll
-    for (int i3 = 0; i3 < 2; ++i3) {
-        const int cz = z - i3;
-        if (cz < 0 || cz >= P.N3) continue;
-#pragma unroll
-        for (int i2 = 0; i2 < 2; ++i2) {
-            const int cy = y - i2;
-            if (cy < 0 || cy >= P.N2) continue;
-#pragma unroll
-            for (int i1 = 0; i1 < 2; ++i1) {
-                const int cx = x - i1;
-                if (cx < 0 || cx >= P.N1) continue;
-                const long long c = ((long long)cz * P.N2 + cy) * P.N1 + cx;
-                if (ex || an) {
-                    const float a2 = ex ? P.A2[c] : 0.f;
-                    float e0 = 0.f, e1 = 0.f, e2 = 0.f, ku = 0.f, sp = 0.f;
-                    if (an) {
-                        ku = P.Ku[c];
-                        e0 = P.easy[c];
-                        e1 = P.easy[nc + c];
-                        e2 = P.easy[2 * nc + c];
-                    }
-#pragma unroll
-                    for (int b3 = 0; b3 < 2; ++b3)
-#pragma unroll
-                        for (int b2 = 0; b2 < 2; ++b2)
-#pragma unroll
-                            for (int b1 = 0; b1 < 2; ++b1) {
-                                const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
-                                float v0, v1, v2;
-                                if (mask == 0) {
-                                    v0 = mn[0];
-                                    v1 = mn[1];
-                                    v2 = mn[2];
-                                } else {
-                                    const long long nb = ((long long)(cz + b3) * P.NY + (cy + b2)) * P.NX + (cx + b1);
-                                    v0 = m[nb];
-                                    v1 = m[nn + nb];
-                                    v2 = m[2 * nn + nb];
-                                    if (ex) {
-                                        const float w = a2 * P.Kp[mask];
-                                        g0 += w * (v0 - mn[0]);
-                                        g1 += w * (v1 - mn[1]);
-                                        g2 += w * (v2 - mn[2]);
-                                    }
-                                }
-                                if (an) sp += P.Mp[mask] * (v0 * e0 + v1 * e1 + v2 * e2);
-                            }
-                    if (an) {
-                        const float k2 = -2.f * ku * sp;
-                        g0 += k2 * e0;
-                        g1 += k2 * e1;
-                        g2 += k2 * e2;
-                    }
-                }
-                if (ze || dm) {
-                    const float w = P.wc[c];
-                    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
-                    if (ze) {
-                        h0 = P.hu[0];
-                        h1 = P.hu[1];
-                        h2 = P.hu[2];
-                        if (P.hcell) {
-                            h0 += P.hcell[c];
-                            h1 += P.hcell[nc + c];
-                            h2 += P.hcell[2 * nc + c];
-                        }
-                        if (P.dmask) {
-                            const float d = P.dmask[c] * sdrive;
-                            h0 += d * P.damp[0];
-                            h1 += d * P.damp[1];
-                            h2 += d * P.damp[2];
-                        }
-                    }
-                    if (dm) {
-                        h0 += P.hd[c];
-                        h1 += P.hd[nc + c];
-                        h2 += P.hd[2 * nc + c];
-                    }
-                    s0 += w * h0;
-                    s1 += w * h1;
-                    s2 += w * h2;
-                }
-            }
-        }
-    }
-    const float im = P.inv_mass[n];
-    H[0] = (s0 - g0) * im;
-    H[1] = (s1 - g1) * im;
-    H[2] = (s2 - g2) * im;
+// Dormand & Prince (1980) RK5(4)7FM: y_{s+1} = m + dt sum_{j<=s} a_{s+1,j} k_j
+__host__ __device__ constexpr double dp_c(int s) {  // stage s (1-based) time fraction
+    return s == 1 ? 0.0 : s == 2 ? 1.0 / 5 : s == 3 ? 3.0 / 10 : s == 4 ? 4.0 / 5 : s == 5 ? 8.0 / 9 : 1.0;
 }
+__host__ __device__ constexpr double dp_a(int r, int j) {  // a_{r,j}, 1-based
+    return r == 2 ? (j == 1 ? 1.0 / 5 : 0.0)
+         : r == 3 ? (j == 1 ? 3.0 / 40 : j == 2 ? 9.0 / 40 : 0.0)
+         : r == 4 ? (j == 1 ? 44.0 / 45 : j == 2 ? -56.0 / 15 : j == 3 ? 32.0 / 9 : 0.0)
+         : r == 5 ? (j == 1 ? 19372.0 / 6561 : j == 2 ? -25360.0 / 2187 : j == 3 ? 64448.0 / 6561
+                     : j == 4 ? -212.0 / 729 : 0.0)
+         : r == 6 ? (j == 1 ? 9017.0 / 3168 : j == 2 ? -355.0 / 33 : j == 3 ? 46732.0 / 5247
+                     : j == 4 ? 49.0 / 176 : j == 5 ? -5103.0 / 18656 : 0.0)
+         : r == 7 ? (j == 1 ? 35.0 / 384 : j == 2 ? 0.0 : j == 3 ? 500.0 / 1113 : j == 4 ? 125.0 / 192
+                     : j == 5 ? -2187.0 / 6784 : j == 6 ? 11.0 / 84 : 0.0)
+         : 0.0;
+}
+// embedded error weights b_j - b*_j
+__host__ __device__ constexpr double dp_e(int j) {
+    return j == 1 ? 35.0 / 384 - 5179.0 / 57600 : j == 2 ? 0.0 : j == 3 ? 500.0 / 1113 - 7571.0 / 16695
+         : j == 4 ? 125.0 / 192 - 393.0 / 640 : j == 5 ? -2187.0 / 6784 + 92097.0 / 339200
+         : j == 6 ? 11.0 / 84 - 187.0 / 2100 : j == 7 ? -1.0 / 40 : 0.0;
+}
+// weight of k_j in the epilogue of DP45 stage S (next stage input, or the error at S = 7)
+__host__ __device__ constexpr double dp_w(int S, int j) { return S == 7 ? dp_e(j) : dp_a(S + 1, j); }
+__host__ __device__ constexpr double rk4_c(int s) { return s == 1 ? 0.0 : s == 4 ? 1.0 : 0.5; }
 
 __device__ __forceinline__ void llg_rhs(const float m[3], const float H[3], float gp, float al,
                                         float f[3]) {
@@ -183,84 +102,176 @@ __device__ __forceinline__ void reduce_partial(double sq, float mf, int nf, ErrP
         __syncthreads();
     }
     if (t == 0) {
-        out[blockIdx.x].sumsq = s_sq[0];
-        out[blockIdx.x].maxf = s_mf[0];
-        out[blockIdx.x].nonfinite = s_nf[0];
+        out->sumsq = s_sq[0];
+        out->maxf = s_mf[0];
+        out->nonfinite = s_nf[0];
     }
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_stencil(StencilParams P, StageArgs S) {
+// One thread per node (consecutive nodes along x): the 27 neighbouring m
+// values are loaded once into registers, the 8 cells' packed data once per
+// cell, and the operands of the stage epilogue are fetched before the field
+// so that their latency overlaps the arithmetic.  The stage is a template
+// parameter so every tableau coefficient is a compile-time constant.
+template <int MODE, int STAGE>
+__global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
+    constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE) : MODE == kModeRK4 ? rk4_c(STAGE) : 0.0;
     if (C) {
         if (C->done) return;
         dt = C->dt;
-        t = C->t + S.c * dt;
+        t = C->t + cst * dt;
     }
     const long long nn = P.nn;
     const bool valid = n < nn;
-    float mn[3] = {0.f, 0.f, 0.f}, H[3] = {0.f, 0.f, 0.f}, f[3] = {0.f, 0.f, 0.f};
+    constexpr int NK = MODE == kModeDP45 ? (STAGE > 1 ? STAGE - 1 : 1) : 1;
+    float ms[3] = {0.f, 0.f, 0.f}, ac[3] = {0.f, 0.f, 0.f}, kk[NK][3];
+    double sq = 0.0;
+    float mf = 0.f;
+    int nf = 0;
     if (valid) {
-        node_field(P, S.in, n, t, mn, H);
-        if (MODE != kModeField) llg_rhs(mn, H, P.gp_n[n], P.alpha_n[n], f);
-    }
-    if (MODE == kModeField) {
-        if (valid)
-            for (int c = 0; c < 3; ++c) S.out[c * nn + n] = H[c];
-    } else if (MODE == kModeRhs) {
-        if (valid)
-            for (int c = 0; c < 3; ++c) S.out[c * nn + n] = f[c];
-    } else if (MODE == kModeRK4) {
-        if (!valid) return;
-        const int s = S.stage;
-        const float wacc = s == 1 ? 1.f : 2.f;
-        const float cy = (float)(dt * (s == 3 ? 1.0 : 0.5));
-        const float c6 = (float)(dt / 6.0);
-        for (int c = 0; c < 3; ++c) {
-            const long long i = c * nn + n;
-            const float ms = S.mstate[i];
-            if (s == 4) {
-                S.mstate[i] = ms + c6 * (S.acc[i] + f[c]);
-            } else {
-                S.acc[i] = s == 1 ? f[c] : S.acc[i] + wacc * f[c];
-                S.y_next[i] = ms + cy * f[c];
-            }
+        // ---- epilogue operands first
+        if (MODE == kModeRK4 || MODE == kModeDP45) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ms[c] = S.mstate[c * nn + n];
         }
-    } else {  // DP45 stage s: store k_s, form y_{s+1}, or the error norm at s = 7
-        const int s = S.stage;
-        double sq = 0.0;
-        float mf = 0.f;
-        int nf = 0;
-        if (valid) {
-            const bool active = P.inv_mass[n] > 0.f;
-            float a[7];
-            for (int j = 0; j < 7; ++j) a[j] = (float)(dt * (s < 7 ? S.a[j] : S.e[j]));
-            float fn2 = 0.f;
+        if (MODE == kModeRK4 && STAGE > 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ac[c] = S.acc[c * nn + n];
+        }
+        if (MODE == kModeDP45) {
+#pragma unroll
+            for (int j = 0; j < NK; ++j)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    kk[j][c] = (j < STAGE - 1 && dp_w(STAGE, j + 1) != 0.0) ? S.k[j][c * nn + n] : 0.f;
+        }
+        // ---- neighbourhood of m
+        const int x = (int)(n % P.NX);
+        const long long r = n / P.NX;
+        const int y = (int)(r % P.NY);
+        const int z = (int)(r / P.NY);
+        const long long sy = P.NX, sz = (long long)P.NX * P.NY;
+        const float *__restrict__ in = S.in;
+        float v[27][3];
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int k = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    const bool ok = x + dx >= 0 && x + dx < P.NX && y + dy >= 0 && y + dy < P.NY &&
+                                    z + dz >= 0 && z + dz < P.NZ;
+                    const long long nb = n + dz * sz + dy * sy + dx;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) v[k][c] = ok ? in[c * nn + nb] : 0.f;
+                }
+        const float mn[3] = {v[13][0], v[13][1], v[13][2]};
+        const bool ex = P.terms & NM_T_EXCHANGE;
+        const bool an = (P.terms & NM_T_ANIS) != 0;
+        float sdrive = 0.f;
+        if (P.wdrive) sdrive = (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f;
+#pragma unroll
+        for (int i3 = 0; i3 < 2; ++i3)
+#pragma unroll
+            for (int i2 = 0; i2 < 2; ++i2)
+#pragma unroll
+                for (int i1 = 0; i1 < 2; ++i1) {
+                    const int cx = x - i1, cy = y - i2, cz = z - i3;
+                    if (cx < 0 || cx >= P.N1 || cy < 0 || cy >= P.N2 || cz < 0 || cz >= P.N3) continue;
+                    const long long c = ((long long)cz * P.N2 + cy) * P.N1 + cx;
+                    if (P.src) {
+                        r0 += P.src[c];
+                        r1 += P.src[P.nc + c];
+                        r2 += P.src[2 * P.nc + c];
+                    }
+                    if (P.wdrive) {
+                        const float d = P.wdrive[c] * sdrive;
+                        r0 += d * P.damp[0];
+                        r1 += d * P.damp[1];
+                        r2 += d * P.damp[2];
+                    }
+                    if (!(ex || an)) continue;
+                    const float4 A = P.cellA[c];   // {2A, Ku e}
+                    const float4 E = P.cellB[c];   // {e, w}
+                    float sp = 0.f;
+#pragma unroll
+                    for (int b3 = 0; b3 < 2; ++b3)
+#pragma unroll
+                        for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+                            for (int b1 = 0; b1 < 2; ++b1) {
+                                const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
+                                const int k = (b3 - i3 + 1) * 9 + (b2 - i2 + 1) * 3 + (b1 - i1 + 1);
+                                if (ex && mask != 0) {
+                                    const float w = A.x * P.Kp[mask];
+                                    g0 += w * (v[k][0] - mn[0]);
+                                    g1 += w * (v[k][1] - mn[1]);
+                                    g2 += w * (v[k][2] - mn[2]);
+                                }
+                                if (an) sp += P.Mp[mask] * (v[k][0] * E.x + v[k][1] * E.y + v[k][2] * E.z);
+                            }
+                    if (an) {
+                        g0 -= 2.f * sp * A.y;
+                        g1 -= 2.f * sp * A.z;
+                        g2 -= 2.f * sp * A.w;
+                    }
+                }
+        const float im = P.inv_mass[n];
+        const float H[3] = {(r0 - g0) * im, (r1 - g1) * im, (r2 - g2) * im};
+        float f[3] = {0.f, 0.f, 0.f};
+        if (MODE != kModeField) llg_rhs(mn, H, P.gp_n[n], P.alpha_n[n], f);
+        if (MODE == kModeField) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.out[c * nn + n] = H[c];
+        } else if (MODE == kModeRhs) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) S.out[c * nn + n] = f[c];
+        } else if (MODE == kModeRK4) {
+            const float cy = (float)(dt * (STAGE == 3 ? 1.0 : 0.5));
+            const float c6 = (float)(dt / 6.0);
+#pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const long long i = c * nn + n;
-                S.k[s - 1][i] = f[c];
-                float acc = a[s - 1] * f[c];
-                for (int j = 0; j < s - 1; ++j)
-                    if (a[j] != 0.f) acc += a[j] * S.k[j][i];
-                const float ms = S.mstate[i];
-                if (s < 7) {
-                    S.y_next[i] = ms + acc;
+                if (STAGE == 4) {
+                    S.mstate[i] = ms[c] + c6 * (ac[c] + f[c]);
                 } else {
-                    const float yn = S.in[i];
-                    const double sc = C->atol + C->rtol * fmax(fabs((double)ms), fabs((double)yn));
-                    const double r = (double)acc / sc;
-                    if (active) sq += r * r;
+                    S.acc[i] = STAGE == 1 ? f[c] : ac[c] + 2.f * f[c];
+                    S.y_next[i] = ms[c] + cy * f[c];
+                }
+            }
+        } else {  // DP45: store k_s, then y_{s+1} or (s = 7) the scaled error
+            float fn2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const long long i = c * nn + n;
+                S.k[STAGE - 1][i] = f[c];
+                float acc = (float)(dt * dp_w(STAGE, STAGE)) * f[c];
+#pragma unroll
+                for (int j = 0; j < STAGE - 1; ++j)
+                    if (dp_w(STAGE, j + 1) != 0.0) acc += (float)(dt * dp_w(STAGE, j + 1)) * kk[j][c];
+                if (STAGE < 7) {
+                    S.y_next[i] = ms[c] + acc;
+                } else {
+                    const float yn = mn[c];
+                    const double sct = C->atol + C->rtol * fmax(fabs((double)ms[c]), fabs((double)yn));
+                    const double rr = (double)acc / sct;
+                    if (im > 0.f) sq += rr * rr;
                     if (!isfinite(acc) || !isfinite(yn)) nf = 1;
                     fn2 += f[c] * f[c];
                 }
             }
-            if (s == 7 && active) mf = sqrtf(fn2);
+            if (STAGE == 7 && im > 0.f) mf = sqrtf(fn2);
         }
-        if (s == 7) reduce_partial(sq, mf, nf, S.partials);
     }
+    if (MODE == kModeDP45 && STAGE == 7) reduce_partial(sq, mf, nf, S.partials + blockIdx.x);
 }
+
+dim3 stencil_grid(const nm_mesh *m) { return dim3((unsigned)((m->n_nodes + 255) / 256)); }
 
 // ---------------------------------------------------------------- energies
 __global__ void __launch_bounds__(256) k_energy_cells(StencilParams P, const float *__restrict__ m,
@@ -469,6 +480,12 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
         P.Kp[i] = m->Kp[i];
         P.Mp[i] = m->Mp[i];
     }
+    P.cellA = m->cellA;
+    P.cellB = m->cellB;
+    // source of the node kernel: the demag pass writes mu0 Ms V/8 (H_d [+ static
+    // H_ext]) into hd; without demag the static Zeeman part is read directly
+    P.src = (terms & NM_T_DEMAG) ? m->hd : ((terms & NM_T_ZEEMAN) ? m->wstat : nullptr);
+    P.wdrive = ((terms & NM_T_ZEEMAN) && m->has_drive) ? m->wdrive : nullptr;
     P.wc = m->wc;
     P.A2 = m->A2;
     P.Ku = m->has_anis ? m->Ku : nullptr;
@@ -489,39 +506,47 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     return P;
 }
 
+template <int MODE, int STAGE>
+static void launch_node(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
+    NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE>), grid, dim3(256), 0, P, S);
+}
+
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
     StencilParams P = make_params(m, terms);
     StageArgs S{};
     S.in = sp.in;
     S.out = sp.out;
     S.y_next = sp.y_next;
+    S.mstate = sp.mstate;
+    S.acc = m->acc;
     S.t0 = sp.t0;
-    S.c = sp.c;
-    S.stage = sp.stage;
     S.ctrl = sp.use_ctrl ? m->ctrl : nullptr;
     S.partials = m->partials;
-    for (int j = 0; j < 7; ++j) {
-        S.a[j] = sp.a[j];
-        S.e[j] = sp.e[j];
-        S.k[j] = m->k[j];
-    }
-    S.acc = m->acc;
-    S.mstate = sp.mstate;
-    const unsigned grid = (unsigned)((m->n_nodes + 255) / 256);
-    ProfScope ps(m, NM_PROF_STENCIL);
-    switch (sp.mode) {
-        case kModeField:
-            hipLaunchKernelGGL((k_stencil<kModeField>), dim3(grid), dim3(256), 0, m->stream, P, S);
-            break;
-        case kModeRhs:
-            hipLaunchKernelGGL((k_stencil<kModeRhs>), dim3(grid), dim3(256), 0, m->stream, P, S);
-            break;
-        case kModeRK4:
-            hipLaunchKernelGGL((k_stencil<kModeRK4>), dim3(grid), dim3(256), 0, m->stream, P, S);
-            break;
-        default:
-            hipLaunchKernelGGL((k_stencil<kModeDP45>), dim3(grid), dim3(256), 0, m->stream, P, S);
-            break;
+    for (int j = 0; j < 7; ++j) S.k[j] = m->k[j];
+    const dim3 g = stencil_grid(m);
+    if (sp.mode == kModeField) {
+        launch_node<kModeField, 0>(m, g, P, S);
+    } else if (sp.mode == kModeRhs) {
+        launch_node<kModeRhs, 0>(m, g, P, S);
+    } else if (sp.mode == kModeRK4) {
+        switch (sp.stage) {
+            case 1: launch_node<kModeRK4, 1>(m, g, P, S); break;
+            case 2: launch_node<kModeRK4, 2>(m, g, P, S); break;
+            case 3: launch_node<kModeRK4, 3>(m, g, P, S); break;
+            case 4: launch_node<kModeRK4, 4>(m, g, P, S); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (sp.stage) {
+            case 1: launch_node<kModeDP45, 1>(m, g, P, S); break;
+            case 2: launch_node<kModeDP45, 2>(m, g, P, S); break;
+            case 3: launch_node<kModeDP45, 3>(m, g, P, S); break;
+            case 4: launch_node<kModeDP45, 4>(m, g, P, S); break;
+            case 5: launch_node<kModeDP45, 5>(m, g, P, S); break;
+            case 6: launch_node<kModeDP45, 6>(m, g, P, S); break;
+            case 7: launch_node<kModeDP45, 7>(m, g, P, S); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
@@ -546,23 +571,61 @@ hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t,
 }
 
 hipError_t launch_dp45_control(nm_mesh *m) {
-    const int np = (int)((m->n_nodes + 255) / 256);
-    ProfScope ps(m, NM_PROF_CONTROL);
-    hipLaunchKernelGGL(k_dp45_control, dim3(1), dim3(256), 0, m->stream, m->ctrl, m->partials, np);
+    const int np = (int)stencil_grid(m).x;
+    NM_LAUNCH(m, NM_PROF_CONTROL, k_dp45_control, dim3(1), dim3(256), 0, m->ctrl, m->partials, np);
     return hipGetLastError();
 }
 
-hipError_t launch_dp45_finish(nm_mesh *m, float *mstate, double a21) {
+hipError_t launch_dp45_finish(nm_mesh *m, float *mstate) {
+    const double a21 = dp_a(2, 1);
     const long long n3 = 3 * m->n_nodes;
-    ProfScope ps(m, NM_PROF_CONTROL);
-    hipLaunchKernelGGL(k_dp45_finish, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, m->stream,
-                       m->ctrl, mstate, m->y[1], m->k[0], m->k[6], m->y[0], n3, a21);
+    NM_LAUNCH(m, NM_PROF_CONTROL, k_dp45_finish, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0,
+              m->ctrl, mstate, m->y[1], m->k[0], m->k[6], m->y[0], n3, a21);
+    return hipGetLastError();
+}
+
+// packed node-kernel data from the raw cell copies (mesh creation, new field map)
+__global__ void k_cell_pack(const float *__restrict__ A2, const float *__restrict__ Ku,
+                            const float *__restrict__ easy, const float *__restrict__ wc,
+                            const float *__restrict__ hcell, const float *__restrict__ dmask,
+                            float hu0, float hu1, float hu2, float4 *__restrict__ cellA,
+                            float4 *__restrict__ cellB, float *__restrict__ wstat,
+                            float *__restrict__ wdrive, long long nc) {
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nc) return;
+    float e0 = 0.f, e1 = 0.f, e2 = 0.f, k = 0.f;
+    if (Ku) {
+        k = Ku[c];
+        e0 = easy[c];
+        e1 = easy[nc + c];
+        e2 = easy[2 * nc + c];
+    }
+    const float w = wc[c];
+    cellA[c] = make_float4(A2[c], k * e0, k * e1, k * e2);
+    cellB[c] = make_float4(e0, e1, e2, w);
+    float h0 = hu0, h1 = hu1, h2 = hu2;
+    if (hcell) {
+        h0 += hcell[c];
+        h1 += hcell[nc + c];
+        h2 += hcell[2 * nc + c];
+    }
+    wstat[c] = w * h0;
+    wstat[nc + c] = w * h1;
+    wstat[2 * nc + c] = w * h2;
+    if (dmask) wdrive[c] = w * dmask[c];
+}
+
+hipError_t launch_cell_pack(nm_mesh *m) {
+    const long long nc = m->n_cells;
+    hipLaunchKernelGGL(k_cell_pack, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, m->stream, m->A2,
+                       m->has_anis ? m->Ku : nullptr, m->easy, m->wc, m->has_hcell ? m->h_cell : nullptr,
+                       m->has_drive ? m->drive_mask : nullptr, m->h_uniform[0], m->h_uniform[1],
+                       m->h_uniform[2], m->cellA, m->cellB, m->wstat, m->wdrive, nc);
     return hipGetLastError();
 }
 
 hipError_t launch_rk4_advance(nm_mesh *m) {
-    ProfScope ps(m, NM_PROF_CONTROL);
-    hipLaunchKernelGGL(k_rk4_advance, dim3(1), dim3(1), 0, m->stream, m->ctrl);
+    NM_LAUNCH(m, NM_PROF_CONTROL, k_rk4_advance, dim3(1), dim3(1), 0, m->ctrl);
     return hipGetLastError();
 }
 

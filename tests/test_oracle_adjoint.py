@@ -1,0 +1,124 @@
+"""Pins of the oracle's discrete adjoint: every transpose is checked against
+central finite differences of the forward map it transposes (dot-product
+tests), and the field-map gradient against finite differences of the loss."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.adjoint import (cell_gather, llg_vjp, region_mz2_loss, rhs_vjp, rk4_gradient,
+                            rk4_step_adjoint)
+from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, EXCHANGE, ZEEMAN
+
+from helpers import to_oracle
+from paper_2411_11725_amd import synth
+
+
+def _llg(m, H, alpha_n, gp):
+    mxh = np.cross(m, H, axis=0)
+    return -gp * mxh - alpha_n * gp * np.cross(m, mxh, axis=0)
+
+
+def _problem(n=(4, 3, 2), seed=51):
+    p = synth.small_random(n, (2e-9, 2.5e-9, 3e-9), seed=seed)
+    return to_oracle(p)
+
+
+def test_llg_vjp_against_finite_differences():
+    rng = np.random.default_rng(1)
+    shape = (3, 2, 3, 4)
+    m = rng.standard_normal(shape)
+    H = 1e5 * rng.standard_normal(shape)
+    w = rng.standard_normal(shape)
+    a = rng.uniform(0.01, 1.0, shape[1:])
+    gp = 2.211e5 / (1 + a ** 2)
+    dm_t, u = llg_vjp(m, H, w, a, gp)
+    d = rng.standard_normal(shape)
+    eps = 1e-5
+    jd = (_llg(m + eps * d, H, a, gp) - _llg(m - eps * d, H, a, gp)) / (2 * eps)
+    assert abs(np.sum(jd * w) - np.sum(d * dm_t)) <= 1e-8 * abs(np.sum(d * dm_t))
+    dH = 1e4 * rng.standard_normal(shape)
+    jh = _llg(m, H + dH, a, gp) - _llg(m, H, a, gp)       # linear in H
+    assert abs(np.sum(jh * w) - np.sum(dH * u)) <= 1e-10 * abs(np.sum(dH * u))
+
+
+def test_linear_field_operator_is_self_adjoint_in_the_mass_metric():
+    """M H_lin is the negative Hessian of the quadratic energies: symmetric."""
+    mesh, mat, _ = _problem()
+    M = oracle.lumped_mass(mesh, mat)
+    rng = np.random.default_rng(2)
+    a = rng.standard_normal((3,) + mesh.node_shape)
+    b = rng.standard_normal((3,) + mesh.node_shape)
+    lin = EXCHANGE | ANISOTROPY | DEMAG
+    lhs = np.sum(M * oracle.heff(mesh, mat, a, lin) * b)
+    rhs = np.sum(a * M * oracle.heff(mesh, mat, b, lin))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("terms", [ALL_TERMS, EXCHANGE | DEMAG])
+def test_rhs_vjp_dot_product(terms):
+    mesh, mat, m = _problem()
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(m.shape)
+    v = rng.standard_normal(m.shape)
+    jt, _ = rhs_vjp(mesh, mat, m, 0.0, w, terms)
+    eps = 1e-6
+    jv = (oracle.llg_rhs(mesh, mat, m + eps * v, 0.0, terms)
+          - oracle.llg_rhs(mesh, mat, m - eps * v, 0.0, terms)) / (2 * eps)
+    assert abs(np.sum(jv * w) - np.sum(v * jt)) <= 1e-7 * abs(np.sum(v * jt))
+
+
+def test_rk4_step_adjoint_dot_product():
+    mesh, mat, m = _problem(seed=52)
+    rng = np.random.default_rng(4)
+    lam = rng.standard_normal(m.shape)
+    v = rng.standard_normal(m.shape)
+    dt = 2e-14
+    lam0, _ = rk4_step_adjoint(mesh, mat, m, 0.0, dt, lam, ALL_TERMS)
+    eps = 1e-6
+    jv = (oracle.rk4_step(mesh, mat, m + eps * v, 0.0, dt)
+          - oracle.rk4_step(mesh, mat, m - eps * v, 0.0, dt)) / (2 * eps)
+    assert abs(np.sum(jv * lam) - np.sum(v * lam0)) <= 1e-8 * abs(np.sum(v * lam0))
+
+
+def test_field_map_gradient_against_finite_differences():
+    """Magnonic-strip style objective over a short trajectory: the adjoint
+    gradient wrt the per-cell field map equals central differences of L."""
+    p = synth.magnonic(n=(24, 8, 1))
+    mesh, mat, m0 = to_oracle(p)
+    nsteps, dt = 12, 5e-14
+    region = np.zeros(mesh.node_shape, dtype=bool)
+    region[:, 2:6, 14:20] = True
+    loss, dloss = region_mz2_loss(mesh, region, nsteps)
+
+    def L(mat_):
+        m = m0.copy()
+        tot = 0.0
+        for k in range(nsteps):
+            m = oracle.rk4_step(mesh, mat_, m, k * dt, dt)
+            tot += loss(m)
+        return tot
+
+    _, dth, _ = rk4_gradient(mesh, mat, m0, dt, nsteps, dloss, ALL_TERMS)
+    h = 0.7958  # 1e-3 mT in A/m
+    for (j, c3, c2, c1) in [(0, 0, 3, 17), (1, 0, 4, 15), (2, 0, 2, 18), (2, 0, 5, 10)]:
+        hp = mat.h_cell.copy()
+        hm = mat.h_cell.copy()
+        hp[j, c3, c2, c1] += h
+        hm[j, c3, c2, c1] -= h
+        mp = oracle.Material(**{**mat.__dict__, "h_cell": hp})
+        mm = oracle.Material(**{**mat.__dict__, "h_cell": hm})
+        fd = (L(mp) - L(mm)) / (2 * h)
+        g = dth[j, c3, c2, c1]
+        assert abs(g - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(dth).max()), (j, g, fd)
+
+
+def test_cell_gather_is_transpose_of_field_map():
+    """<H_ext(theta), M u'> summed over nodes == <theta, gather(u')>."""
+    mesh, mat, _ = _problem()
+    rng = np.random.default_rng(5)
+    theta = rng.standard_normal((3,) + mesh.cell_shape)
+    v = rng.standard_normal((3,) + mesh.node_shape)
+    M = oracle.lumped_mass(mesh, mat)
+    mat2 = oracle.Material(**{**mat.__dict__, "h_cell": theta, "h_uniform": np.zeros(3)})
+    Hz = oracle.heff(mesh, mat2, np.zeros_like(v), ZEEMAN)
+    assert abs(np.sum(Hz * M * v) - np.sum(theta * cell_gather(mesh, mat2, v))) <= 1e-12 * np.sum(np.abs(Hz * M * v))
