@@ -45,6 +45,7 @@ typedef enum {
     NM_ENOTREADY = -4,     /* result not available yet */
     NM_ENONFINITE = -5,    /* the state or the step error became NaN/Inf */
     NM_ESTEPSIZE = -6,     /* adaptive step fell below dt_min */
+    NM_EBUDGET = -7,       /* a solve can never fit in the server's memory budget */
     NM_EUNSUPPORTED = -8   /* valid request this build does not handle */
 } nm_status;
 
@@ -161,6 +162,89 @@ nm_status nm_energy(nm_mesh *mesh, const float *m, unsigned terms, double t, dou
  * DP45 controller fails; m then holds the last accepted state. */
 nm_status nm_llg_step(nm_mesh *mesh, float *m, nm_clock *clk, const nm_integrator *integ,
                       double t_end, long max_steps);
+
+/* Discrete adjoint of nsteps fixed RK4 steps of size dt from the checkpoint
+ * m0 (device, 3 * n_nodes) at time t0, for the inverse problems of Sec. 4
+ * (gradient of a trajectory objective, Eqs. adjoint_forward and
+ * adjoint_objective, taken on the discrete map rather than by reverse
+ * integration of the continuous adjoint system).  The forward states of the
+ * segment are recomputed into `work`, then the exact reverse recurrence of
+ * the four stages runs back to m0.
+ *   terms       field terms of the forward run (NM_T_*)
+ *   dl_dm       optional device array of per-step loss gradients: entry i
+ *               (3 * n_nodes floats) is dl/dm at the state after step
+ *               (i + 1) * dl_every of this segment; NULL for none
+ *   lambda      device, in: dL/dm at the segment end (from later segments);
+ *               out: dL/dm0
+ *   grad_hcell  optional device array (3 * n_cells) to which dL/d(per-cell
+ *               applied field map) is ADDED; needs NM_T_ZEEMAN
+ *   work        device workspace of nm_adjoint_workspace_bytes(mesh, nsteps)
+ *               bytes, owned by the caller
+ * Asynchronous on the mesh stream; returns NM_EINVAL on bad arguments. */
+nm_status nm_adjoint_step(nm_mesh *mesh, const float *m0, double t0, double dt, int nsteps,
+                          unsigned terms, const float *dl_dm, int dl_every, float *lambda,
+                          float *grad_hcell, float *work);
+
+/* Workspace bytes nm_adjoint_step needs for a segment of nsteps steps. */
+size_t nm_adjoint_workspace_bytes(const nm_mesh *mesh, int nsteps);
+
+/* ------------------------------------------------------------------------
+ * Solve server: continuous batching of independent LLG solves of uneven
+ * size.  Requests wait in a FIFO queue; a scheduler thread admits them while
+ * the device memory of admitted solves (nm_mesh_footprint_bytes plus the
+ * state) stays within hbm_budget and fewer than max_active run.  Admitted
+ * solves stay resident on the device and advance by replays of their own
+ * captured DP45 graph on a pool of streams, so many solves' kernels are in
+ * flight at once; finished solves leave and waiting ones join between
+ * replays.  Each solve runs the same kernels on its own buffers, so results
+ * do not depend on the mix.  max_active = 1 is the plain one-at-a-time loop.
+ * A server may be used from any thread.
+ * ---------------------------------------------------------------------- */
+typedef struct nm_server nm_server;
+
+typedef struct {
+    size_t hbm_budget;        /* device bytes admitted solves may hold (0: 80% of free) */
+    int max_active;           /* most solves admitted at once (>= 1) */
+    int n_streams;            /* HIP streams the solves are spread over (1..16) */
+    int attempts_per_launch;  /* DP45 attempts per graph replay (1..64) */
+} nm_server_desc;
+
+/* One solve: DP45 from t = 0 to t_end; all pointers are HOST memory, copied
+ * by nm_serve_submit (the caller may free them on return). */
+typedef struct {
+    int n[3];
+    double h[3];
+    double gamma;
+    const float *Ms, *A, *alpha;   /* cell arrays, N floats each */
+    const float *m0;               /* nodal initial state, 3 * n_nodes floats */
+    float h_uniform[3];            /* uniform applied field (A/m) */
+    unsigned terms;                /* NM_T_* */
+    double rtol, atol, dt0, t_end;
+} nm_solve_request;
+
+typedef struct {
+    int status;                    /* NM_OK, NM_ENOTREADY or the solve's error */
+    double t;                      /* time reached */
+    long accepted, rejected, rhs_evals;
+    double t_submit, t_admit, t_done;  /* nm_server_clock() seconds */
+} nm_solve_result;
+
+nm_status nm_server_create(const nm_server_desc *desc, nm_server **out);
+
+/* Stop the scheduler, release every solve (waiting, running or unpolled). */
+nm_status nm_server_destroy(nm_server *server);
+
+/* Queue a request (non-blocking); *ticket identifies it for nm_serve_poll. */
+nm_status nm_serve_submit(nm_server *server, const nm_solve_request *req, uint64_t *ticket);
+
+/* Wait up to timeout_ms for the solve: NM_OK fills *res (and the host array
+ * m_out, 3 * n_nodes floats, when not NULL) and forgets the ticket;
+ * NM_ENOTREADY if still running; NM_EINVAL for an unknown ticket. */
+nm_status nm_serve_poll(nm_server *server, uint64_t ticket, nm_solve_result *res, float *m_out,
+                        int timeout_ms);
+
+/* Seconds on the server clock (steady, process-wide). */
+double nm_server_clock(void);
 
 /* Per-kernel timing (measurement only).  While enabled, every kernel the
  * mesh launches is bracketed by a pair of HIP events on the mesh stream and

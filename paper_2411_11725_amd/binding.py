@@ -12,7 +12,7 @@ from ctypes import POINTER, c_double, c_float, c_int, c_int64, c_long, c_uint, c
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnm.so")
 
 NM_OK, NM_EINVAL, NM_ENOMEM, NM_EHIP, NM_ENOTREADY = 0, -1, -2, -3, -4
-NM_ENONFINITE, NM_ESTEPSIZE, NM_EUNSUPPORTED = -5, -6, -8
+NM_ENONFINITE, NM_ESTEPSIZE, NM_EBUDGET, NM_EUNSUPPORTED = -5, -6, -7, -8
 NM_T_EXCHANGE, NM_T_DEMAG, NM_T_ANIS, NM_T_ZEEMAN, NM_T_ALL = 1, 2, 4, 8, 15
 NM_RK4, NM_DP45 = 1, 2
 
@@ -20,7 +20,9 @@ NM_RK4, NM_DP45 = 1, 2
 EXPORTS = [
     "nm_mesh_create", "nm_mesh_destroy", "nm_mesh_info", "nm_mesh_footprint_bytes",
     "nm_mesh_set_field", "nm_demag_tensor_init", "nm_newell_octant", "nm_heff",
-    "nm_demag_cell_field", "nm_llg_rhs", "nm_energy", "nm_llg_step", "nm_profile_enable",
+    "nm_demag_cell_field", "nm_llg_rhs", "nm_energy", "nm_llg_step", "nm_adjoint_step",
+    "nm_adjoint_workspace_bytes", "nm_server_create", "nm_server_destroy", "nm_serve_submit",
+    "nm_serve_poll", "nm_server_clock", "nm_profile_enable",
     "nm_profile_read", "nm_last_error",
 ]
 PROF_SLOTS = ["xfwd", "yfwd", "conv", "yinv", "xinv", "stencil", "control", "other"]
@@ -46,6 +48,24 @@ class nm_integrator(ctypes.Structure):
 class nm_clock(ctypes.Structure):
     _fields_ = [("t", c_double), ("dt", c_double), ("accepted", c_long), ("rejected", c_long),
                 ("rhs_evals", c_long), ("max_torque", c_double)]
+
+
+class nm_server_desc(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", c_int), ("n_streams", c_int),
+                ("attempts_per_launch", c_int)]
+
+
+class nm_solve_request(ctypes.Structure):
+    _fields_ = [("n", c_int * 3), ("h", c_double * 3), ("gamma", c_double), ("Ms", c_void_p),
+                ("A", c_void_p), ("alpha", c_void_p), ("m0", c_void_p), ("h_uniform", c_float * 3),
+                ("terms", c_uint), ("rtol", c_double), ("atol", c_double), ("dt0", c_double),
+                ("t_end", c_double)]
+
+
+class nm_solve_result(ctypes.Structure):
+    _fields_ = [("status", c_int), ("t", c_double), ("accepted", c_long), ("rejected", c_long),
+                ("rhs_evals", c_long), ("t_submit", c_double), ("t_admit", c_double),
+                ("t_done", c_double)]
 
 
 class NMError(RuntimeError):
@@ -78,6 +98,13 @@ def lib():
             "nm_llg_rhs": ([P, P, P, c_uint, c_double], c_int),
             "nm_energy": ([P, P, c_uint, c_double, POINTER(c_double)], c_int),
             "nm_llg_step": ([P, P, POINTER(nm_clock), POINTER(nm_integrator), c_double, c_long], c_int),
+            "nm_adjoint_step": ([P, P, c_double, c_double, c_int, c_uint, P, c_int, P, P, P], c_int),
+            "nm_adjoint_workspace_bytes": ([P, c_int], ctypes.c_size_t),
+            "nm_server_create": ([POINTER(nm_server_desc), POINTER(c_void_p)], c_int),
+            "nm_server_destroy": ([P], c_int),
+            "nm_serve_submit": ([P, POINTER(nm_solve_request), POINTER(ctypes.c_uint64)], c_int),
+            "nm_serve_poll": ([P, ctypes.c_uint64, POINTER(nm_solve_result), P, c_int], c_int),
+            "nm_server_clock": ([], c_double),
             "nm_profile_enable": ([P, c_int], c_int),
             "nm_profile_read": ([P, POINTER(c_double), POINTER(ctypes.c_longlong)], c_int),
             "nm_last_error": ([], ctypes.c_char_p),
@@ -174,6 +201,63 @@ def nm_llg_step(mesh, m, clock, method=NM_RK4, terms=NM_T_ALL, t_end=0.0, max_st
     _check(lib().nm_llg_step(mesh, _ptr(m), ctypes.byref(clock), ctypes.byref(integ),
                              float(t_end), int(max_steps)))
     return clock
+
+
+def nm_adjoint_workspace_bytes(mesh, nsteps):
+    return lib().nm_adjoint_workspace_bytes(mesh, int(nsteps))
+
+
+def nm_adjoint_step(mesh, m0, t0, dt, nsteps, terms, lam, dl_dm=None, dl_every=1, grad_hcell=None,
+                    work=None):
+    """Reverse sweep over one checkpointed RK4 segment; lam (in/out) and
+    grad_hcell (accumulated) are device tensors."""
+    if work is None:
+        import torch
+        work = torch.empty(nm_adjoint_workspace_bytes(mesh, nsteps) // 4, dtype=torch.float32,
+                           device=lam.device)
+    _check(lib().nm_adjoint_step(mesh, _ptr(m0), float(t0), float(dt), int(nsteps), int(terms),
+                                 _ptr(dl_dm), int(dl_every), _ptr(lam), _ptr(grad_hcell), _ptr(work)))
+    return work
+
+
+def nm_server_create(max_active=64, n_streams=4, attempts_per_launch=8, hbm_budget=0):
+    desc = nm_server_desc(int(hbm_budget), int(max_active), int(n_streams), int(attempts_per_launch))
+    out = c_void_p()
+    _check(lib().nm_server_create(ctypes.byref(desc), ctypes.byref(out)))
+    return out
+
+
+def nm_server_destroy(server):
+    _check(lib().nm_server_destroy(server))
+
+
+def nm_serve_submit(server, p, terms=NM_T_ALL, rtol=1e-5, atol=1e-5, dt0=1e-14, t_end=0.2e-9):
+    """Submit a problem dict (see synth.make_problem; host float32 arrays)."""
+    import numpy as np
+    keep = [np.ascontiguousarray(p[k], dtype=np.float32) for k in ("Ms", "A", "alpha", "m0")]
+    ptr = [c_void_p(a.ctypes.data) for a in keep]
+    req = nm_solve_request((c_int * 3)(*p["n"]), (c_double * 3)(*p["h"]), float(p["gamma"]),
+                           ptr[0], ptr[1], ptr[2], ptr[3],
+                           (c_float * 3)(*[float(v) for v in p["h_uniform"]]), int(terms),
+                           float(rtol), float(atol), float(dt0), float(t_end))
+    t = ctypes.c_uint64()
+    _check(lib().nm_serve_submit(server, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def nm_serve_poll(server, ticket, timeout_ms=0, m_out=None):
+    """Result struct, or None while the solve is still running."""
+    res = nm_solve_result()
+    st = lib().nm_serve_poll(server, ctypes.c_uint64(ticket), ctypes.byref(res),
+                             None if m_out is None else c_void_p(m_out.ctypes.data), int(timeout_ms))
+    if st == NM_ENOTREADY:
+        return None
+    _check(st)
+    return res
+
+
+def nm_server_clock():
+    return lib().nm_server_clock()
 
 
 def nm_profile_enable(mesh, on=True):

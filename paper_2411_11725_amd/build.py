@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnm.so")
-SOURCES = ["api.hip", "demag.hip", "newell.hip", "profile.hip", "stencil.hip"]
+SOURCES = ["adjoint.hip", "api.hip", "demag.hip", "newell.hip", "profile.hip", "serve.hip",
+           "stencil.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -32,7 +32,7 @@ const float2 *twiddles(int device) {
     float2 *dev = nullptr;
     if (hipMalloc(&dev, sizeof(float2) * kTwN) != hipSuccess) return nullptr;
     if (hipMemcpy(dev, host.data(), sizeof(float2) * kTwN, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(dev);
+        (void)hipFree(dev);
         return nullptr;
     }
     g_tw[device] = dev;
@@ -140,26 +140,27 @@ static size_t footprint(const Sizes &s) {
 }
 
 static void drop_graph(nm_mesh *m) {
-    if (m->gexec) hipGraphExecDestroy(m->gexec);
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
     m->gexec = nullptr;
     m->g_method = 0;
     m->g_terms = 0;
     m->g_mag = nullptr;
+    m->g_batch = 0;
 }
 
 static void free_mesh(nm_mesh *m) {
     if (!m) return;
     prof_free(m);
     drop_graph(m);
-    if (m->cap_stream) hipStreamDestroy(m->cap_stream);
+    if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
                     m->ctrl, m->partials, m->ered, m->cellA, m->cellB, m->wstat, m->wdrive};
     for (void *p : ptrs)
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     for (int j = 0; j < 7; ++j)
-        if (m->k[j]) hipFree(m->k[j]);
-    if (m->ctrl_host) hipHostFree(m->ctrl_host);
+        if (m->k[j]) (void)hipFree(m->k[j]);
+    if (m->ctrl_host) (void)hipHostFree(m->ctrl_host);
     delete m;
 }
 
@@ -310,7 +311,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
 
 extern "C" nm_status nm_mesh_destroy(nm_mesh *m) {
     if (!m) return NM_OK;
-    hipStreamSynchronize(m->stream);
+    (void)hipStreamSynchronize(m->stream);
     free_mesh(m);
     return NM_OK;
 }
@@ -448,8 +449,13 @@ hipError_t rk4_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *
 
 }  // namespace
 
-extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm_integrator *in,
-                                 double t_end, long max_steps) {
+namespace nm {
+
+// Validate, upload the controller state (asynchronously, from the pinned
+// mirror) and, for DP45, launch the first stage.  *batch gets the number of
+// steps / attempts one replay of the stepping graph covers.
+nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integrator *in,
+                     double t_end, long max_steps, int *batch) {
     NM_REQUIRE(m && mag && clk && in, NM_EINVAL, "nm_llg_step: NULL argument");
     NM_REQUIRE(in->method == NM_RK4 || in->method == NM_DP45, NM_EINVAL, "nm_llg_step: unknown method");
     NM_REQUIRE(std::isfinite(clk->t) && std::isfinite(t_end) && t_end >= clk->t, NM_EINVAL,
@@ -461,9 +467,7 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
     NM_REQUIRE(!in->log || in->log_capacity >= 0, NM_EINVAL, "nm_llg_step: bad log capacity");
     nm_status st = check_terms(m, in->terms, "nm_llg_step");
     if (st != NM_OK) return st;
-    if (t_end == clk->t) return NM_OK;
     NM_REQUIRE(m->n_active > 0, NM_EINVAL, "nm_llg_step: the mesh has no magnetic node");
-
     Ctrl *C = m->ctrl_host;
     std::memset(C, 0, sizeof(Ctrl));
     C->t = clk->t;
@@ -479,17 +483,30 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
     C->max_accepted = max_steps;
     C->log = in->log;
     C->log_cap = in->log ? in->log_capacity : 0;
+    C->done = t_end == clk->t ? 1 : 0;
     NM_HIP(hipMemcpyAsync(m->ctrl, C, sizeof(Ctrl), hipMemcpyHostToDevice, m->stream), "nm_llg_step");
-    NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
-    const unsigned terms = in->terms;
+    // RK4 knows its step count: never capture more steps than the call needs
+    int b = 16;
+    if (in->method == NM_RK4) {
+        const double span = (t_end - clk->t) / clk->dt;
+        long need = (long)std::ceil(span * (1.0 - 1e-12));
+        if (need > max_steps) need = max_steps;
+        b = need < 8 ? (int)std::max(need, 1L) : 8;
+    }
+    *batch = b;
+    // first DP45 stage (FSAL keeps k1 for every later attempt)
+    if (in->method == NM_DP45) NM_HIP(dp45_stage(m, in->terms, 1, mag, mag), "nm_llg_step");
+    return NM_OK;
+}
 
-    // one batch of steps / attempts, either launched directly (profiling)
-    // or captured once into a graph and replayed
-    const int batch = in->method == NM_RK4 ? 8 : 16;
+// One batch of steps / attempts: launched directly while profiling, else
+// captured once into a graph (keyed on method, terms, state pointer and
+// batch) and replayed on the mesh stream.
+hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int batch) {
     auto enqueue_batch = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
         for (int q = 0; q < batch && e == hipSuccess; ++q) {
-            if (in->method == NM_RK4) {
+            if (method == NM_RK4) {
                 if (e == hipSuccess) e = rk4_stage(m, terms, 1, mag, m->y[0], mag);
                 if (e == hipSuccess) e = rk4_stage(m, terms, 2, m->y[0], m->y[1], mag);
                 if (e == hipSuccess) e = rk4_stage(m, terms, 3, m->y[1], m->y[0], mag);
@@ -503,8 +520,8 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         }
         return e;
     };
-    const bool use_graph = m->prof == nullptr;
-    if (use_graph && !(m->gexec && m->g_method == in->method && m->g_terms == terms && m->g_mag == mag)) {
+    if (m->prof) return enqueue_batch();
+    if (!(m->gexec && m->g_method == method && m->g_terms == terms && m->g_mag == mag && m->g_batch == batch)) {
         drop_graph(m);
         hipStream_t user = m->stream;
         m->stream = m->cap_stream;
@@ -515,45 +532,29 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         m->stream = user;
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec, graph, nullptr, nullptr, 0);
-        if (graph) hipGraphDestroy(graph);
-        NM_HIP(e, "nm_llg_step: graph capture");
-        m->g_method = in->method;
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return e;
+        m->g_method = method;
         m->g_terms = terms;
         m->g_mag = mag;
+        m->g_batch = batch;
     }
-    auto run_batch = [&]() -> hipError_t {
-        return use_graph ? hipGraphLaunch(m->gexec, m->stream) : enqueue_batch();
-    };
+    return hipGraphLaunch(m->gexec, m->stream);
+}
 
-    if (in->method == NM_RK4) {
-        const double span = (t_end - clk->t) / clk->dt;
-        long nsteps = (long)std::ceil(span * (1.0 - 1e-12));
-        if (nsteps < 1) nsteps = 1;
-        if (nsteps > max_steps) nsteps = max_steps;
-        for (long k = 0; k < nsteps; k += batch) NM_HIP(run_batch(), "nm_llg_step");
-        NM_HIP(hipMemcpyAsync(C, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream), "nm_llg_step");
-        NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
-    } else {
-        // first stage (FSAL keeps k1 for every later attempt)
-        NM_HIP(dp45_stage(m, terms, 1, mag, mag), "nm_llg_step");
-        long long seen = -1;
-        for (;;) {
-            NM_HIP(run_batch(), "nm_llg_step");
-            NM_HIP(hipMemcpyAsync(C, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream), "nm_llg_step");
-            NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
-            if (C->done) break;
-            // every attempt either advances t or shrinks dt towards dt_min, so
-            // the controller must make progress; anything else is a bug
-            NM_REQUIRE(C->attempts > seen, NM_EHIP, "nm_llg_step: controller made no progress");
-            seen = C->attempts;
-        }
-        C->rhs_evals += 1;
-    }
+// asynchronous copy of the device controller into the pinned mirror
+hipError_t ctrl_readback(nm_mesh *m) {
+    return hipMemcpyAsync(m->ctrl_host, m->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, m->stream);
+}
+
+// fold the controller's counters into the caller's clock; map its status
+nm_status step_finish(nm_mesh *m, int method, nm_clock *clk) {
+    const Ctrl *C = m->ctrl_host;
     clk->t = C->t;
-    clk->dt = in->method == NM_RK4 ? clk->dt : C->dt_prop;
+    if (method == NM_DP45) clk->dt = C->dt_prop;
     clk->accepted += C->accepted;
     clk->rejected += C->rejected;
-    clk->rhs_evals += C->rhs_evals;
+    clk->rhs_evals += C->rhs_evals + (method == NM_DP45 ? 1 : 0);
     clk->max_torque = C->max_torque;
     if (C->status == NM_ENONFINITE) {
         set_error("nm_llg_step: non-finite error norm or state");
@@ -564,6 +565,39 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         return NM_ESTEPSIZE;
     }
     return NM_OK;
+}
+
+}  // namespace nm
+
+extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm_integrator *in,
+                                 double t_end, long max_steps) {
+    int batch = 1;
+    nm_status st = step_begin(m, mag, clk, in, t_end, max_steps, &batch);
+    if (st != NM_OK) return st;
+    if (t_end == clk->t) return NM_OK;
+    const unsigned terms = in->terms;
+    if (in->method == NM_RK4) {
+        const double span = (t_end - clk->t) / clk->dt;
+        long nsteps = (long)std::ceil(span * (1.0 - 1e-12));
+        if (nsteps < 1) nsteps = 1;
+        if (nsteps > max_steps) nsteps = max_steps;
+        for (long k = 0; k < nsteps; k += batch) NM_HIP(step_batch(m, mag, NM_RK4, terms, batch), "nm_llg_step");
+        NM_HIP(ctrl_readback(m), "nm_llg_step");
+        NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
+    } else {
+        long long seen = -1;
+        for (;;) {
+            NM_HIP(step_batch(m, mag, NM_DP45, terms, batch), "nm_llg_step");
+            NM_HIP(ctrl_readback(m), "nm_llg_step");
+            NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
+            if (m->ctrl_host->done) break;
+            // every attempt either advances t or shrinks dt towards dt_min, so
+            // the controller must make progress; anything else is a bug
+            NM_REQUIRE(m->ctrl_host->attempts > seen, NM_EHIP, "nm_llg_step: controller made no progress");
+            seen = m->ctrl_host->attempts;
+        }
+    }
+    return step_finish(m, in->method, clk);
 }
 
 extern "C" const char *nm_last_error(void) { return g_error.c_str(); }

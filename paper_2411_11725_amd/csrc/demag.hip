@@ -192,19 +192,28 @@ k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1
 }
 
 // ------------------------------------------- k-space product of one element
-__device__ __forceinline__ void tensor_apply(const float *__restrict__ T, long long tstride,
-                                             long long tidx, float sy, float sz, bool full3d,
-                                             float2 &mx, float2 &my, float2 &mz) {
-    const float xx = T[tidx], yy = T[tstride + tidx], zz = T[2 * tstride + tidx];
-    const float xy = sy * T[3 * tstride + tidx];
-    float xz = 0.f, yz = 0.f;
-    if (full3d) {
-        xz = sz * T[4 * tstride + tidx];
-        yz = sy * sz * T[5 * tstride + tidx];
-    }
-    const float2 hx = make_float2(-(xx * mx.x + xy * my.x + xz * mz.x), -(xx * mx.y + xy * my.y + xz * mz.y));
-    const float2 hy = make_float2(-(xy * mx.x + yy * my.x + yz * mz.x), -(xy * mx.y + yy * my.y + yz * mz.y));
-    const float2 hz = make_float2(-(xz * mx.x + yz * my.x + zz * mz.x), -(xz * mx.y + yz * my.y + zz * mz.y));
+struct Tensor6 {
+    float xx, yy, zz, xy, xz, yz;
+};
+
+__device__ __forceinline__ Tensor6 tensor_load(const float *__restrict__ T, long long tstride,
+                                               long long tidx, float sy, bool full3d) {
+    Tensor6 N;
+    N.xx = T[tidx];
+    N.yy = T[tstride + tidx];
+    N.zz = T[2 * tstride + tidx];
+    N.xy = sy * T[3 * tstride + tidx];
+    N.xz = full3d ? T[4 * tstride + tidx] : 0.f;
+    N.yz = full3d ? sy * T[5 * tstride + tidx] : 0.f;
+    return N;
+}
+
+// H^ = -N^ M^ in place; sz flips the components odd along the fused axis
+__device__ __forceinline__ void tensor_apply(const Tensor6 &N, float sz, float2 &mx, float2 &my, float2 &mz) {
+    const float xz = sz * N.xz, yz = sz * N.yz;
+    const float2 hx = make_float2(-(N.xx * mx.x + N.xy * my.x + xz * mz.x), -(N.xx * mx.y + N.xy * my.y + xz * mz.y));
+    const float2 hy = make_float2(-(N.xy * mx.x + N.yy * my.x + yz * mz.x), -(N.xy * mx.y + N.yy * my.y + yz * mz.y));
+    const float2 hz = make_float2(-(xz * mx.x + yz * my.x + N.zz * mz.x), -(xz * mx.y + yz * my.y + N.zz * mz.y));
     mx = hx;
     my = hy;
     mz = hz;
@@ -233,20 +242,27 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     }
     __syncthreads();
     lds_fft<L, -1, NP, 256, true>(s, tw, tid);
+    // kz and L - kz share the stored tensor entry (xz, yz flip sign): one read
+    // serves both
     const long long tstride = (long long)P3h * P2h * K1;
-    for (int it = tid; it < L * TB; it += 256) {
-        const int b = it % TB, kz = it / TB;
+    for (int it = tid; it < (L / 2 + 1) * TB; it += 256) {
+        const int b = it % TB, kzr = it / TB;
         const int col = col0 + b;
         if (col >= ncols) continue;
         const int ky = col / K1, kx = col - (col / K1) * K1;
-        const bool fy = ky > P2 / 2, fz = kz > L / 2;
-        const int kyr = fy ? P2 - ky : ky, kzr = fz ? L - kz : kz;
-        const long long tidx = ((long long)kzr * P2h + kyr) * K1 + kx;
-        float2 mx = s[kz * NP + b], my = s[kz * NP + TB + b], mz = s[kz * NP + 2 * TB + b];
-        tensor_apply(T, tstride, tidx, fy ? -1.f : 1.f, fz ? -1.f : 1.f, true, mx, my, mz);
-        s[kz * NP + b] = mx;
-        s[kz * NP + TB + b] = my;
-        s[kz * NP + 2 * TB + b] = mz;
+        const bool fy = ky > P2 / 2;
+        const int kyr = fy ? P2 - ky : ky;
+        const Tensor6 N = tensor_load(T, tstride, ((long long)kzr * P2h + kyr) * K1 + kx, fy ? -1.f : 1.f, true);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kz = h == 0 ? kzr : L - kzr;
+            if (h == 1 && (kzr == 0 || kzr == L / 2)) break;
+            float2 mx = s[kz * NP + b], my = s[kz * NP + TB + b], mz = s[kz * NP + 2 * TB + b];
+            tensor_apply(N, h == 0 ? 1.f : -1.f, mx, my, mz);
+            s[kz * NP + b] = mx;
+            s[kz * NP + TB + b] = my;
+            s[kz * NP + 2 * TB + b] = mz;
+        }
     }
     __syncthreads();
     lds_fft<L, 1, NP, 256, true>(s, tw, tid);
@@ -279,18 +295,25 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     }
     __syncthreads();
     lds_fft<L, -1, NP, 256, true>(s, tw, tid);
+    // ky and L - ky share the stored tensor entry (xy flips sign)
     const long long tstride = (long long)P2h * K1;
-    for (int it = tid; it < L * TB; it += 256) {
-        const int b = it % TB, ky = it / TB;
+    for (int it = tid; it < (L / 2 + 1) * TB; it += 256) {
+        const int b = it % TB, kyr = it / TB;
         const int col = col0 + b;
         if (col >= K1) continue;
-        const bool fy = ky > L / 2;
-        const int kyr = fy ? L - ky : ky;
-        float2 mx = s[ky * NP + b], my = s[ky * NP + TB + b], mz = s[ky * NP + 2 * TB + b];
-        tensor_apply(T, tstride, (long long)kyr * K1 + col, fy ? -1.f : 1.f, 1.f, false, mx, my, mz);
-        s[ky * NP + b] = mx;
-        s[ky * NP + TB + b] = my;
-        s[ky * NP + 2 * TB + b] = mz;
+        const Tensor6 N = tensor_load(T, tstride, (long long)kyr * K1 + col, 1.f, false);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ky = h == 0 ? kyr : L - kyr;
+            if (h == 1 && (kyr == 0 || kyr == L / 2)) break;
+            Tensor6 Nh = N;
+            if (h == 1) Nh.xy = -N.xy;
+            float2 mx = s[ky * NP + b], my = s[ky * NP + TB + b], mz = s[ky * NP + 2 * TB + b];
+            tensor_apply(Nh, 1.f, mx, my, mz);
+            s[ky * NP + b] = mx;
+            s[ky * NP + TB + b] = my;
+            s[ky * NP + 2 * TB + b] = mz;
+        }
     }
     __syncthreads();
     lds_fft<L, 1, NP, 256, true>(s, tw, tid);

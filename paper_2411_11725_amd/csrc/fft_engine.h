@@ -110,9 +110,26 @@ __device__ __forceinline__ void fft_pass(float2 *s, const float2 *__restrict__ t
             const int j = EM ? job / NP : job % J;
             const int k = j % NS;
             if constexpr (NS > 1) {
+                // w^r, r < R, from the table entries w, w^2, w^4 (one extra
+                // rounding at most for the products)
                 constexpr int stride = kTwN / (NS * R);
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], twiddle<DIR>(tw, r * k * stride));
+                const float2 w1 = twiddle<DIR>(tw, k * stride);
+                if constexpr (R == 2) {
+                    v[q][1] = cmul(v[q][1], w1);
+                } else {
+                    const float2 w2 = twiddle<DIR>(tw, 2 * k * stride);
+                    const float2 w3 = cmul(w1, w2);
+                    v[q][1] = cmul(v[q][1], w1);
+                    v[q][2] = cmul(v[q][2], w2);
+                    v[q][3] = cmul(v[q][3], w3);
+                    if constexpr (R == 8) {
+                        const float2 w4 = twiddle<DIR>(tw, 4 * k * stride);
+                        v[q][4] = cmul(v[q][4], w4);
+                        v[q][5] = cmul(v[q][5], cmul(w1, w4));
+                        v[q][6] = cmul(v[q][6], cmul(w2, w4));
+                        v[q][7] = cmul(v[q][7], cmul(w3, w4));
+                    }
+                }
             }
             dft_small<R, DIR>(v[q]);
             const int base = (j / NS) * NS * R + k;

@@ -251,7 +251,7 @@ hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], doubl
                        n1, n2, n3, hs[0], hs[1], hs[2], rules, out);
     e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(stream);
-    hipFree(rules);
+    (void)hipFree(rules);
     return e != hipSuccess ? e : e2;
 }
 
@@ -303,12 +303,12 @@ hipError_t build_kspace_tensor(nm_mesh *m) {
         hipError_t e2 = hipStreamSynchronize(m->stream);
         if (e == hipSuccess) e = e2;
     }
-    hipFree(octd);
-    hipFree(A);
-    hipFree(B);
-    hipFree(c1);
-    hipFree(c2);
-    hipFree(c3);
+    (void)hipFree(octd);
+    (void)hipFree(A);
+    (void)hipFree(B);
+    (void)hipFree(c1);
+    (void)hipFree(c2);
+    (void)hipFree(c3);
     return e;
 }
 

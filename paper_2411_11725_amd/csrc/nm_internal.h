@@ -89,6 +89,7 @@ struct nm_mesh {
     int g_method;
     unsigned g_terms;
     float *g_mag;
+    int g_batch;
 };
 
 namespace nm {
@@ -127,7 +128,8 @@ hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], doubl
 hipError_t build_kspace_tensor(nm_mesh *m);
 
 // stencil / LLG / stage kernels
-enum StencilMode { kModeField = 0, kModeRhs = 1, kModeRK4 = 2, kModeDP45 = 3 };
+// kModeAdjFwd: store H(y_s) and form the next RK4 stage input (adjoint recompute)
+enum StencilMode { kModeField = 0, kModeRhs = 1, kModeRK4 = 2, kModeDP45 = 3, kModeAdjFwd = 4 };
 
 struct StageSpec {
     int mode;
@@ -136,7 +138,8 @@ struct StageSpec {
     float *out;              // field / rhs output (modes 0, 1)
     float *y_next;           // next stage input
     float *mstate;           // state at the start of the step (stepping modes)
-    double t0;               // time when ctrl is null (field / rhs modes)
+    double t0;               // start-of-step time when ctrl is null
+    double dt0;              // step when ctrl is null (RK4 / adjoint recompute)
     bool use_ctrl;           // stepping modes: t, dt from the device controller
 };
 
@@ -147,5 +150,12 @@ hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
 hipError_t launch_cell_pack(nm_mesh *m);   // cellA, cellB, wstat, wdrive from the raw copies
 hipError_t launch_rk4_advance(nm_mesh *m);
+
+// stepping building blocks shared by nm_llg_step and the solve server
+nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integrator *in,
+                     double t_end, long max_steps, int *batch);
+hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int batch);
+hipError_t ctrl_readback(nm_mesh *m);
+nm_status step_finish(nm_mesh *m, int method, nm_clock *clk);
 
 }  // namespace nm

@@ -61,9 +61,9 @@ static void drain(ProfState *p) {
 
 void prof_free(nm_mesh *m) {
     if (!m->prof) return;
-    hipStreamSynchronize(m->stream);
+    (void)hipStreamSynchronize(m->stream);
     drain(m->prof);
-    for (hipEvent_t e : m->prof->pool) hipEventDestroy(e);
+    for (hipEvent_t e : m->prof->pool) (void)hipEventDestroy(e);
     delete m->prof;
     m->prof = nullptr;
 }

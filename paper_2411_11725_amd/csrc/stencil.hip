@@ -40,7 +40,7 @@ struct StageArgs {
     float *k[7];
     const Ctrl *ctrl;
     ErrPartial *partials;
-    double t0;
+    double t0, dt0;
 };
 
 // Dormand & Prince (1980) RK5(4)7FM: y_{s+1} = m + dt sum_{j<=s} a_{s+1,j} k_j
@@ -118,11 +118,15 @@ __global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
-    constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE) : MODE == kModeRK4 ? rk4_c(STAGE) : 0.0;
+    constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE)
+                         : (MODE == kModeRK4 || MODE == kModeAdjFwd) ? rk4_c(STAGE) : 0.0;
     if (C) {
         if (C->done) return;
         dt = C->dt;
         t = C->t + cst * dt;
+    } else {
+        dt = S.dt0;
+        t = S.t0 + cst * dt;
     }
     const long long nn = P.nn;
     const bool valid = n < nn;
@@ -133,7 +137,7 @@ __global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
     int nf = 0;
     if (valid) {
         // ---- epilogue operands first
-        if (MODE == kModeRK4 || MODE == kModeDP45) {
+        if (MODE == kModeRK4 || MODE == kModeDP45 || (MODE == kModeAdjFwd && STAGE < 4)) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) ms[c] = S.mstate[c * nn + n];
         }
@@ -228,6 +232,14 @@ __global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
         if (MODE == kModeField) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) S.out[c * nn + n] = H[c];
+        } else if (MODE == kModeAdjFwd) {
+            // H(y_s) for the reverse sweep, y_{s+1} = m + c_{s+1} dt f_s
+            const float cy = (float)(dt * (STAGE == 3 ? 1.0 : 0.5));
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                S.out[c * nn + n] = H[c];
+                if (STAGE < 4) S.y_next[c * nn + n] = ms[c] + cy * f[c];
+            }
         } else if (MODE == kModeRhs) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) S.out[c * nn + n] = f[c];
@@ -520,6 +532,7 @@ hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
     S.mstate = sp.mstate;
     S.acc = m->acc;
     S.t0 = sp.t0;
+    S.dt0 = sp.dt0;
     S.ctrl = sp.use_ctrl ? m->ctrl : nullptr;
     S.partials = m->partials;
     for (int j = 0; j < 7; ++j) S.k[j] = m->k[j];
@@ -528,6 +541,14 @@ hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
         launch_node<kModeField, 0>(m, g, P, S);
     } else if (sp.mode == kModeRhs) {
         launch_node<kModeRhs, 0>(m, g, P, S);
+    } else if (sp.mode == kModeAdjFwd) {
+        switch (sp.stage) {
+            case 1: launch_node<kModeAdjFwd, 1>(m, g, P, S); break;
+            case 2: launch_node<kModeAdjFwd, 2>(m, g, P, S); break;
+            case 3: launch_node<kModeAdjFwd, 3>(m, g, P, S); break;
+            case 4: launch_node<kModeAdjFwd, 4>(m, g, P, S); break;
+            default: return hipErrorInvalidValue;
+        }
     } else if (sp.mode == kModeRK4) {
         switch (sp.stage) {
             case 1: launch_node<kModeRK4, 1>(m, g, P, S); break;

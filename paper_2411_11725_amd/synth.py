@@ -138,3 +138,26 @@ def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
                         Ku=("uniform", 0.0, 5e5) if anis else None,
                         easy="random", h_uniform=(1e4, -2e4, 3e4) if field else (0, 0, 0),
                         h_cell=hc)
+
+
+def serving_requests(count, seed=104, rate=200.0, nmin=32, nmax=512, nzmax=8, h=3e-9):
+    """Poisson stream of solve requests: exponential inter-arrival gaps at
+    `rate` per second; nx, ny rounded from log-uniform [nmin, nmax], nz uniform
+    in 1..nzmax; cubic h cells; Ms ~ U[4e5, 1.2e6]; alpha log-uniform in
+    [0.005, 0.5]; A = 1.3e-11; random unit m0 per node.  Returns a list of
+    (arrival time in s, problem dict)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(count):
+        if i:
+            t += rng.exponential(1.0 / rate)
+        nx = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        ny = int(round(math.exp(rng.uniform(math.log(nmin), math.log(nmax)))))
+        nz = int(rng.integers(1, nzmax + 1))
+        Ms = rng.uniform(4e5, 1.2e6)
+        alpha = math.exp(rng.uniform(math.log(0.005), math.log(0.5)))
+        p = make_problem((nx, ny, nz), (h, h, h), Ms, 1.3e-11, alpha,
+                         seed=int(rng.integers(1 << 31)))
+        out.append((t, p))
+    return out

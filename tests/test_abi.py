@@ -66,3 +66,21 @@ def test_null_arguments_are_rejected_before_any_gpu_work():
     n = (ctypes.c_int * 3)(0, 1, 1)
     h = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
     assert L.nm_newell_octant(n, h, ctypes.c_void_p(1), None) == binding.NM_EINVAL
+
+
+@needs_lib
+def test_adjoint_and_server_reject_bad_arguments_on_the_host():
+    L = binding.lib()
+    P = ctypes.c_void_p
+    assert L.nm_adjoint_step(None, None, 0.0, 1e-14, 1, 15, None, 1, None, None, None) == binding.NM_EINVAL
+    assert L.nm_adjoint_workspace_bytes(None, 4) == 0
+    out = ctypes.c_void_p()
+    for bad in [(0, 0, 1, 4), (0, 2, 0, 4), (0, 2, 17, 4), (0, 2, 4, 0), (0, 2, 4, 65)]:
+        d = binding.nm_server_desc(*bad)
+        assert L.nm_server_create(ctypes.byref(d), ctypes.byref(out)) == binding.NM_EINVAL
+    assert L.nm_server_create(None, ctypes.byref(out)) == binding.NM_EINVAL
+    assert L.nm_serve_submit(None, None, None) == binding.NM_EINVAL
+    res = binding.nm_solve_result()
+    assert L.nm_serve_poll(None, ctypes.c_uint64(1), ctypes.byref(res), None, 0) == binding.NM_EINVAL
+    assert L.nm_server_destroy(None) == binding.NM_OK
+    assert L.nm_profile_enable(None, 1) == binding.NM_EINVAL

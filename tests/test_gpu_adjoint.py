@@ -1,0 +1,107 @@
+"""GPU discrete adjoint (float32, through the C ABI) against the float64 oracle
+adjoint and against float64 central finite differences of the objective."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle.adjoint import region_mz2_loss, rk4_gradient, rk4_step_adjoint
+from oracle.field import ALL_TERMS
+from helpers import rel_l2, to_oracle
+from paper_2411_11725_amd import binding as B
+from paper_2411_11725_amd import synth
+from paper_2411_11725_amd.adjoint import LLGTrajectory
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    B.lib()
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("n,h", [((6, 5, 3), (2e-9, 2.5e-9, 3e-9)), ((20, 9, 1), (4e-9, 4e-9, 5e-9))])
+def test_adjoint_segment_matches_oracle(n, h):
+    """lambda and the field-map gradient after a 3-step segment, all terms."""
+    p = synth.small_random(n, h, seed=61)
+    mesh = B.mesh_from_problem(p)
+    om, omat, m0 = to_oracle(p)
+    rng = np.random.default_rng(3)
+    lam0 = rng.standard_normal(m0.shape)
+    dt, ns = 2e-14, 3
+    try:
+        lam = _dev(lam0)
+        gth = torch.zeros((3,) + om.cell_shape, device="cuda")
+        B.nm_adjoint_step(mesh, _dev(p["m0"]), 0.0, dt, ns, B.NM_T_ALL, lam, grad_hcell=gth)
+        torch.cuda.synchronize()
+        gl, gt = lam.cpu().numpy().astype(np.float64), gth.cpu().numpy().astype(np.float64)
+    finally:
+        B.nm_mesh_destroy(mesh)
+    states = [m0]
+    for k in range(ns):
+        states.append(oracle.rk4_step(om, omat, states[-1], k * dt, dt))
+    ol, ot = lam0, np.zeros_like(gt)
+    for k in range(ns, 0, -1):
+        ol, th = rk4_step_adjoint(om, omat, states[k - 1], (k - 1) * dt, dt, ol, ALL_TERMS)
+        ot += th
+    assert rel_l2(gl, ol) <= 1e-5
+    assert rel_l2(gt, ot) <= 1e-5
+
+
+def _magnonic_small():
+    p = synth.magnonic(n=(24, 8, 1))
+    om, omat, m0 = to_oracle(p)
+    region = np.zeros(om.node_shape, dtype=bool)
+    region[:, 2:6, 14:20] = True
+    return p, om, omat, m0, region
+
+
+def test_autograd_gradient_against_fp64_finite_differences():
+    """Field-map gradient of L = -(1/K) sum_k mean_region m_z(t_k)^2 through
+    LLGTrajectory (checkpointed segments) vs float64 central differences of
+    the oracle's objective (h = 1e-3 mT), relative error <= 1e-4."""
+    p, om, omat, m0, region = _magnonic_small()
+    nsteps, dt = 24, 5e-14
+    mesh = B.mesh_from_problem(p)
+    try:
+        theta = torch.zeros((3,) + om.cell_shape, device="cuda", requires_grad=True)
+        m0t = _dev(p["m0"]).requires_grad_(True)
+        traj = LLGTrajectory.apply(theta, m0t, mesh, dt, nsteps, 8, 1, B.NM_T_ALL)
+        reg = torch.as_tensor(region, device="cuda")
+        L = -(traj[:, 2][:, reg] ** 2).mean(dim=1).mean()
+        L.backward()
+        g = theta.grad.cpu().numpy().astype(np.float64)
+        gm0 = m0t.grad.cpu().numpy().astype(np.float64)
+    finally:
+        B.nm_mesh_destroy(mesh)
+    loss, dloss = region_mz2_loss(om, region, nsteps)
+    lam_o, dth_o, _ = rk4_gradient(om, omat, m0, dt, nsteps, dloss, ALL_TERMS)
+    assert rel_l2(g, dth_o) <= 1e-4
+    assert rel_l2(gm0, lam_o) <= 1e-4
+
+    def Lfd(mat_):
+        m = m0.copy()
+        tot = 0.0
+        for k in range(nsteps):
+            m = oracle.rk4_step(om, mat_, m, k * dt, dt)
+            tot += loss(m)
+        return tot
+
+    h = 0.7958
+    rng = np.random.default_rng(105)
+    cells = [(int(rng.integers(3)), 0, int(rng.integers(8)), int(rng.integers(10, 24))) for _ in range(6)]
+    gmax = np.abs(dth_o).max()
+    for (j, c3, c2, c1) in cells:
+        hp, hm = omat.h_cell.copy(), omat.h_cell.copy()
+        hp[j, c3, c2, c1] += h
+        hm[j, c3, c2, c1] -= h
+        fd = (Lfd(oracle.Material(**{**omat.__dict__, "h_cell": hp}))
+              - Lfd(oracle.Material(**{**omat.__dict__, "h_cell": hm}))) / (2 * h)
+        assert abs(g[j, c3, c2, c1] - fd) <= 1e-4 * max(abs(fd), 1e-3 * gmax), (j, c2, c1, g[j, c3, c2, c1], fd)

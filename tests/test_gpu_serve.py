@@ -1,0 +1,124 @@
+"""Solve server (continuous batching) on the GPU: each result is the same alone
+and in the mix, admission respects the memory budget, request semantics, and
+the batched server beats the one-at-a-time loop on the same kernels."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from helpers import to_oracle
+from paper_2411_11725_amd import binding as B
+from paper_2411_11725_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+T_END = 4e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU visible")
+    B.lib()
+
+
+def _nn(p):
+    n1, n2, n3 = p["n"]
+    return (n1 + 1) * (n2 + 1) * (n3 + 1)
+
+
+def _serve(reqs, max_active, budget=0, t_end=T_END):
+    srv = B.nm_server_create(max_active=max_active, n_streams=4, attempts_per_launch=8, hbm_budget=budget)
+    try:
+        tickets = [B.nm_serve_submit(srv, p, t_end=t_end) for p in reqs]
+        outs, results = [], []
+        for tk, p in zip(tickets, reqs):
+            m = np.empty(3 * _nn(p), dtype=np.float32)
+            r = B.nm_serve_poll(srv, tk, timeout_ms=120000, m_out=m)
+            assert r is not None and r.status == B.NM_OK
+            outs.append(m)
+            results.append(r)
+    finally:
+        B.nm_server_destroy(srv)
+    return outs, results
+
+
+def _small_stream(count, seed=7):
+    return [p for _, p in synth.serving_requests(count, seed=seed, nmin=8, nmax=40, nzmax=3)]
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix():
+    reqs = _small_stream(6)
+    mix, _ = _serve(reqs, max_active=6)
+    alone, _ = _serve(reqs, max_active=1)
+    for a, b in zip(mix, alone):
+        assert np.array_equal(a, b)
+
+
+def test_served_solve_matches_the_oracle():
+    p = synth.make_problem((10, 7, 2), (3e-9,) * 3, 8e5, 1.3e-11, 0.1, seed=3)
+    (m,), (r,) = _serve([p], max_active=1, t_end=T_END)
+    om, omat, m0 = to_oracle(p)
+    want, _ = oracle.dp45_solve(om, omat, m0, 0.0, T_END, 1e-14, rtol=1e-5, atol=1e-5)
+    g = m.reshape(want.shape).astype(np.float64)
+    assert abs(r.t - T_END) < 1e-24
+    assert np.abs(g.mean(axis=(1, 2, 3)) - want.mean(axis=(1, 2, 3))).max() <= 1e-4
+
+
+def test_admission_respects_the_memory_budget():
+    p = synth.make_problem((24, 24, 2), (3e-9,) * 3, 8e5, 1.3e-11, 0.1, seed=4)
+    reqs = [dict(p, m0=synth.make_problem((24, 24, 2), (3e-9,) * 3, 8e5, 1.3e-11, 0.1, seed=10 + i)["m0"])
+            for i in range(6)]
+    fp = B.nm_mesh_footprint_bytes(p["n"], p["h"]) + 4 * (3 * _nn(p) + 3 * 24 * 24 * 2)
+    _, res = _serve(reqs, max_active=6, budget=int(2.5 * fp))
+    events = sorted([(r.t_admit, 1) for r in res] + [(r.t_done, -1) for r in res])
+    live = peak = 0
+    for _, d in events:
+        live += d
+        peak = max(peak, live)
+    assert peak <= 2
+
+
+def test_request_that_never_fits_is_refused():
+    p = _small_stream(1)[0]
+    srv = B.nm_server_create(max_active=4, hbm_budget=1024)
+    try:
+        tk = B.nm_serve_submit(srv, p, t_end=T_END)
+        r = B.nm_serve_poll(srv, tk, timeout_ms=60000)
+        assert r is not None and r.status == B.NM_EBUDGET and r.accepted == 0
+    finally:
+        B.nm_server_destroy(srv)
+
+
+def test_poll_semantics():
+    srv = B.nm_server_create(max_active=2)
+    try:
+        with pytest.raises(B.NMError) as ei:
+            B.nm_serve_poll(srv, 12345)
+        assert ei.value.status == B.NM_EINVAL
+        p = _small_stream(1, seed=9)[0]
+        tk = B.nm_serve_submit(srv, p, t_end=T_END)
+        r = None
+        t0 = time.time()
+        while r is None and time.time() - t0 < 120:
+            r = B.nm_serve_poll(srv, tk, timeout_ms=50)
+        assert r is not None and r.status == B.NM_OK and r.accepted > 0
+        assert r.t_submit <= r.t_admit <= r.t_done
+        with pytest.raises(B.NMError):
+            B.nm_serve_poll(srv, tk)   # a polled ticket is forgotten
+    finally:
+        B.nm_server_destroy(srv)
+
+
+def test_batched_server_beats_the_plain_loop():
+    reqs = _small_stream(16, seed=11)
+    t0 = time.perf_counter()
+    _serve(reqs, max_active=16)
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _serve(reqs, max_active=1)
+    t_plain = time.perf_counter() - t0
+    assert t_batch < t_plain
