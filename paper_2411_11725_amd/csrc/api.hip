@@ -104,7 +104,7 @@ static int pad_len(int n) {
 }
 
 struct Sizes {
-    int P1, P2, P3, K1, P2h, P3h;
+    int P1, P2, P3, K1, KP, P2h, P3h;
     long long nn, nc, spec, tensor, partials, eblocks;
 };
 
@@ -116,12 +116,13 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
     s->P3 = pad_len(n3);
     if (s->P1 > kMaxFFT || s->P2 > kMaxFFT || s->P3 > kMaxFFT) return false;
     s->K1 = s->P1 / 2 + 1;
+    s->KP = (s->K1 + 15) / 16 * 16;
     s->P2h = s->P2 / 2 + 1;
     s->P3h = s->P3 / 2 + 1;
     s->nn = (long long)(n1 + 1) * (n2 + 1) * (n3 + 1);
     s->nc = (long long)n1 * n2 * n3;
-    s->spec = 3LL * n3 * s->P2 * s->K1;
-    s->tensor = 6LL * s->P3h * s->P2h * s->K1;
+    s->spec = 3LL * n3 * s->P2 * s->KP;
+    s->tensor = 6LL * s->P3h * s->P2h * s->KP;
     s->partials = (s->nn + 255) / 256;   // one DP45 error partial per node block
     s->eblocks = (s->nc + 255) / 256;
     return true;
@@ -130,7 +131,7 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
 static size_t footprint(const Sizes &s) {
     size_t b = 0;
     b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive
-    b += sizeof(float) * s.nc * (4 + 4 + 3 + 1);              // cellA, cellB, wstat, wdrive
+    b += sizeof(float) * s.nc * (4 + 3 + 1);                  // cellP, wstat, wdrive
     b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
     b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
     b += sizeof(float) * 3 * s.nc;                              // demag cell field
@@ -155,7 +156,7 @@ static void free_mesh(nm_mesh *m) {
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
-                    m->ctrl, m->partials, m->ered, m->cellA, m->cellB, m->wstat, m->wdrive};
+                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat, m->wdrive};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (int j = 0; j < 7; ++j)
@@ -203,6 +204,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     m->P2 = s.P2;
     m->P3 = s.P3;
     m->K1 = s.K1;
+    m->KP = s.KP;
     m->P2h = s.P2h;
     m->P3h = s.P3h;
     for (int k = 0; k < 3; ++k) m->h[k] = d->h[k];
@@ -243,8 +245,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess) e = dalloc(&m->A2, nc);
     if (e == hipSuccess) e = dalloc(&m->wc, nc);
     if (e == hipSuccess) e = dalloc(&m->h_cell, 3 * nc);
-    if (e == hipSuccess) e = dalloc(&m->cellA, nc);
-    if (e == hipSuccess) e = dalloc(&m->cellB, nc);
+    if (e == hipSuccess) e = dalloc(&m->cellP, nc);
     if (e == hipSuccess) e = dalloc(&m->wstat, 3 * nc);
     if (e == hipSuccess && m->has_drive) e = dalloc(&m->wdrive, nc);
     if (e == hipSuccess && m->has_anis) e = dalloc(&m->Ku, nc);

@@ -12,7 +12,9 @@
 //            films (N3 = 1) the same fusion happens along y instead;
 //   y pass   inverse along y, keeping the N2 rows (3D);
 //   x pass   complex-to-real along x, keeping the N1 cells -> cell field H_c.
-// The spectrum lives in one workspace spec[3][N3][P2][K1] (K1 = P1/2 + 1):
+// The spectrum lives in one workspace spec[3][N3][P2][KP] holding K1 = P1/2 + 1
+// x frequencies per row, the row pitch KP rounded up to 16 complex (128 B) so
+// that column tiles start on cache-line boundaries:
 // every pass reads and writes whole column tiles in place, so no transposes
 // are needed and loads / stores of a tile are contiguous along x.
 // The tensor carries the 1/(P1 P2 P3) normalisation of the inverse transform.
@@ -23,50 +25,42 @@ namespace nm {
 __host__ __device__ constexpr int x_rows_per_block(int L) { return L >= 512 ? 1 : 512 / L; }
 
 // ---------------------------------------------------------------- x forward
-// block (by, z): the RB cell rows y0 <= y < y0 + RB of plane z.  The node rows
-// they touch (y0 .. y0 + RB at z and z + 1) are staged in LDS once, so every
-// node value is fetched once per block rather than once per adjacent cell.
+// block (by, z): the RB cell rows y0 <= y < y0 + RB of plane z.  The 8 corners
+// of each cell are gathered straight from HBM; adjacent rows of the block share
+// node rows, which the L1 / L2 serve.
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
-       const float2 *__restrict__ tw, int N1, int N2, int N3, int P2, int K1,
+       const float2 *__restrict__ tw, int N1, int N2, int N3, int P2, int KP,
        const Ctrl *__restrict__ ctrl) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
-    extern __shared__ float nodes[];  // [3][2][RB + 1][NX]
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int y0 = blockIdx.x * RB, z = blockIdx.y;
     const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
     const long long nn = (long long)NX * NY * (N3 + 1);
-    const int per = (RB + 1) * NX;
-    for (int i = tid; i < 6 * per; i += 256) {
-        const int c = i / (2 * per);
-        const int rem = i - c * 2 * per;
-        const int zz = rem / per;
-        const int rr = rem - zz * per;
-        const int yy = rr / NX, xx = rr - (rr / NX) * NX;
-        const int gy = y0 + yy;
-        nodes[i] = gy < NY ? mag[c * nn + ((long long)(z + zz) * NY + gy) * NX + xx] : 0.f;
-    }
-    __syncthreads();
     for (int it = tid; it < RB * L; it += 256) {
         const int rb = it / L, n = it - (it / L) * L;
         float2 v[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
         if (rb < nrows) {
+            const int y = y0 + rb;
 #pragma unroll
             for (int hh = 0; hh < 2; ++hh) {
                 const int x = 2 * n + hh;
                 if (x < N1) {
-                    const float ms = 0.125f * Ms[((long long)z * N2 + y0 + rb) * N1 + x];
+                    const float ms = 0.125f * Ms[((long long)z * N2 + y) * N1 + x];
+                    const long long b00 = ((long long)z * NY + y) * NX + x;
+                    const long long b01 = b00 + NX;
+                    const long long b10 = b00 + (long long)NX * NY;
+                    const long long b11 = b10 + NX;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const float *b0 = nodes + (c * 2 + 0) * per + rb * NX + x;  // (z, y)
-                        const float *b1 = nodes + (c * 2 + 1) * per + rb * NX + x;  // (z + 1, y)
-                        const float sum = ((b0[0] + b0[1]) + (b0[NX] + b0[NX + 1]))
-                                        + ((b1[0] + b1[1]) + (b1[NX] + b1[NX + 1]));
+                        const float *mc = mag + c * nn;
+                        const float sum = ((mc[b00] + mc[b00 + 1]) + (mc[b01] + mc[b01 + 1]))
+                                        + ((mc[b10] + mc[b10 + 1]) + (mc[b11] + mc[b11 + 1]));
                         if (hh == 0) v[c].x = ms * sum; else v[c].y = ms * sum;
                     }
                 }
@@ -90,7 +84,7 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
             const float2 e = cscale(cadd(zk, zc), 0.5f);
             const float2 d = cscale(csub(zk, zc), 0.5f);
             const float2 o = make_float2(d.y, -d.x);  // -i d
-            spec[(((long long)c * N3 + z) * P2 + y) * K1 + k] = cadd(e, cmul(w, o));
+            spec[(((long long)c * N3 + z) * P2 + y) * KP + k] = cadd(e, cmul(w, o));
         }
     }
 }
@@ -99,7 +93,7 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__restrict__ tw,
-       int N1, int N2, int N3, int P2, int K1, const float *__restrict__ wc,
+       int N1, int N2, int N3, int P2, int KP, const float *__restrict__ wc,
        const float *__restrict__ wstat, int src_mode, const Ctrl *__restrict__ ctrl) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
@@ -120,7 +114,7 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
             const float2 wi = twiddle<1>(tw, k * (kTwN / (2 * L)));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float2 *rowp = spec + (((long long)c * N3 + z) * P2 + y) * K1;
+                const float2 *rowp = spec + (((long long)c * N3 + z) * P2 + y) * KP;
                 const float2 xk = rowp[k];
                 const float2 xc = cconj(rowp[L - k]);
                 const float2 e = cadd(xk, xc);
@@ -158,37 +152,34 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
 }
 
 // ------------------------------------------------------- y pass (3D, 1 comp)
-// columns (z < N3, kx < K1); elements along y at stride K1
+// columns (z < N3, kx < K1) at pitch KP; elements along y at stride KP
 template <int L, int DIR, int TB>
 __global__ void __launch_bounds__(256)
-k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1, int n_in,
+k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1, int KP, int n_in,
         int n_out, const Ctrl *__restrict__ ctrl) {
     __shared__ float2 s[L * TB];
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
-    const int ncols = N3 * K1;
+    const int ncols = N3 * KP;
     const int col0 = blockIdx.x * TB;
-    float2 *base = spec + (long long)blockIdx.y * N3 * L * K1;
-    for (int it = tid; it < L * TB; it += 256) {
-        const int b = it % TB, e = it / TB;
-        const int col = col0 + b;
+    float2 *base = spec + (long long)blockIdx.y * N3 * L * KP;
+    // 256 is a multiple of TB: every thread keeps one column
+    static_assert(256 % TB == 0, "tile width must divide the block");
+    const int b = tid % TB, e0 = tid / TB;
+    constexpr int ESTEP = 256 / TB;
+    const int col = col0 + b;
+    const int zc = col / KP, kx = col - zc * KP;
+    const bool cok = col < ncols && kx < K1;   // pad columns are never touched
+    float2 *cbase = base + (long long)zc * L * KP + kx;
+    for (int e = e0; e < L; e += ESTEP) {
         float2 v = make_float2(0.f, 0.f);
-        if (col < ncols && e < n_in) {
-            const int z = col / K1, kx = col - (col / K1) * K1;
-            v = base[((long long)z * L + e) * K1 + kx];
-        }
+        if (cok && e < n_in) v = cbase[(long long)e * KP];
         s[e * TB + b] = v;
     }
     __syncthreads();
     lds_fft<L, DIR, TB, 256, true>(s, tw, tid);
-    for (int it = tid; it < n_out * TB; it += 256) {
-        const int b = it % TB, e = it / TB;
-        const int col = col0 + b;
-        if (col < ncols) {
-            const int z = col / K1, kx = col - (col / K1) * K1;
-            base[((long long)z * L + e) * K1 + kx] = s[e * TB + b];
-        }
-    }
+    if (cok)
+        for (int e = e0; e < n_out; e += ESTEP) cbase[(long long)e * KP] = s[e * TB + b];
 }
 
 // ------------------------------------------- k-space product of one element
@@ -220,39 +211,46 @@ __device__ __forceinline__ void tensor_apply(const Tensor6 &N, float sz, float2 
 }
 
 // ------------------------------------------- z forward + product + z inverse
-// columns (ky < P2, kx < K1) are contiguous; elements along z at stride P2 K1
+// columns (ky < P2, kx < K1) at pitch KP are contiguous; elements along z at stride P2 KP
 template <int L, int TB>
 __global__ void __launch_bounds__(256)
 k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
-        int N3, int P2, int K1, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
+        int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
     constexpr int NP = 3 * TB;
     __shared__ float2 s[L * NP];
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
-    const long long plane = (long long)P2 * K1;
-    const int ncols = P2 * K1;
+    const long long plane = (long long)P2 * KP;
+    const int ncols = P2 * KP;
     const int col0 = blockIdx.x * TB;
+    // tiles of <= 16 columns never cross a ky row (KP is a multiple of 16)
+    const int kx0 = col0 % KP;
+    auto valid = [&](int b) {
+        const int col = col0 + b;
+        const int kx = TB <= 16 ? kx0 + b : col % KP;
+        return col < ncols && kx < K1;
+    };
     for (int it = tid; it < L * NP; it += 256) {
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
         float2 v = make_float2(0.f, 0.f);
-        if (col < ncols && e < N3) v = spec[((long long)c * N3 + e) * plane + col];
+        if (e < N3 && valid(b)) v = spec[((long long)c * N3 + e) * plane + col];
         s[e * NP + p] = v;
     }
     __syncthreads();
     lds_fft<L, -1, NP, 256, true>(s, tw, tid);
     // kz and L - kz share the stored tensor entry (xz, yz flip sign): one read
     // serves both
-    const long long tstride = (long long)P3h * P2h * K1;
+    const long long tstride = (long long)P3h * P2h * KP;
     for (int it = tid; it < (L / 2 + 1) * TB; it += 256) {
         const int b = it % TB, kzr = it / TB;
         const int col = col0 + b;
-        if (col >= ncols) continue;
-        const int ky = col / K1, kx = col - (col / K1) * K1;
+        if (!valid(b)) continue;
+        const int ky = col / KP, kx = col - (col / KP) * KP;
         const bool fy = ky > P2 / 2;
         const int kyr = fy ? P2 - ky : ky;
-        const Tensor6 N = tensor_load(T, tstride, ((long long)kzr * P2h + kyr) * K1 + kx, fy ? -1.f : 1.f, true);
+        const Tensor6 N = tensor_load(T, tstride, ((long long)kzr * P2h + kyr) * KP + kx, fy ? -1.f : 1.f, true);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int kz = h == 0 ? kzr : L - kzr;
@@ -270,7 +268,7 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
-        if (col < ncols) spec[((long long)c * N3 + e) * plane + col] = s[e * NP + p];
+        if (valid(b)) spec[((long long)c * N3 + e) * plane + col] = s[e * NP + p];
     }
 }
 
@@ -278,30 +276,30 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
 template <int L, int TB>
 __global__ void __launch_bounds__(256)
 k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
-        int N2, int K1, int P2h, const Ctrl *__restrict__ ctrl) {
+        int N2, int K1, int KP, int P2h, const Ctrl *__restrict__ ctrl) {
     constexpr int NP = 3 * TB;
     __shared__ float2 s[L * NP];
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
-    const long long cstride = (long long)L * K1;
+    const long long cstride = (long long)L * KP;
     const int col0 = blockIdx.x * TB;
     for (int it = tid; it < L * NP; it += 256) {
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
         float2 v = make_float2(0.f, 0.f);
-        if (col < K1 && e < N2) v = spec[c * cstride + (long long)e * K1 + col];
+        if (col < K1 && e < N2) v = spec[c * cstride + (long long)e * KP + col];
         s[e * NP + p] = v;
     }
     __syncthreads();
     lds_fft<L, -1, NP, 256, true>(s, tw, tid);
     // ky and L - ky share the stored tensor entry (xy flips sign)
-    const long long tstride = (long long)P2h * K1;
+    const long long tstride = (long long)P2h * KP;
     for (int it = tid; it < (L / 2 + 1) * TB; it += 256) {
         const int b = it % TB, kyr = it / TB;
         const int col = col0 + b;
         if (col >= K1) continue;
-        const Tensor6 N = tensor_load(T, tstride, (long long)kyr * K1 + col, 1.f, false);
+        const Tensor6 N = tensor_load(T, tstride, (long long)kyr * KP + col, 1.f, false);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int ky = h == 0 ? kyr : L - kyr;
@@ -321,7 +319,7 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
-        if (col < K1) spec[c * cstride + (long long)e * K1 + col] = s[e * NP + p];
+        if (col < K1) spec[c * cstride + (long long)e * KP + col] = s[e * NP + p];
     }
 }
 
@@ -334,36 +332,36 @@ __host__ __device__ constexpr int tb_triple(int L) { return L <= 16 ? 64 : 1024 
 template <int L>
 static void launch_x_fwd(nm_mesh *m, const float *mag, const float2 *tw, const Ctrl *ctrl) {
     constexpr int RB = x_rows_per_block(L);
-    const unsigned shmem = (unsigned)(sizeof(float) * 6 * (RB + 1) * (m->N1 + 1));
-    NM_LAUNCH(m, NM_PROF_XFWD, (k_xfwd<L>), dim3((m->N2 + RB - 1) / RB, m->N3), dim3(256), shmem, mag,
-              m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->P2, m->K1, ctrl);
+    NM_LAUNCH(m, NM_PROF_XFWD, (k_xfwd<L>), dim3((m->N2 + RB - 1) / RB, m->N3), dim3(256), 0, mag,
+              m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->P2, m->KP, ctrl);
 }
 template <int L>
 static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl, int src_mode) {
     constexpr int RB = x_rows_per_block(L);
     const int rows = m->N2 * m->N3;
     NM_LAUNCH(m, NM_PROF_XINV, (k_xinv<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->spec, m->hd,
-              tw, m->N1, m->N2, m->N3, m->P2, m->K1, m->wc, m->wstat, src_mode, ctrl);
+              tw, m->N1, m->N2, m->N3, m->P2, m->KP, m->wc, m->wstat, src_mode, ctrl);
 }
 template <int L, int DIR>
 static void launch_y(nm_mesh *m, const float2 *tw, int n_in, int n_out, const Ctrl *ctrl) {
     constexpr int TB = tb_single(L);
-    const int ncols = m->N3 * m->K1;
+    const int ncols = m->N3 * m->KP;
     NM_LAUNCH(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV, (k_ypass<L, DIR, TB>),
-              dim3((ncols + TB - 1) / TB, 3), dim3(256), 0, m->spec, tw, m->N3, m->K1, n_in, n_out, ctrl);
+              dim3((ncols + TB - 1) / TB, 3), dim3(256), 0, m->spec, tw, m->N3, m->K1, m->KP, n_in, n_out,
+              ctrl);
 }
 template <int L>
 static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     constexpr int TB = tb_triple(L);
-    const int ncols = m->P2 * m->K1;
+    const int ncols = m->P2 * m->KP;
     NM_LAUNCH(m, NM_PROF_CONV, (k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->spec,
-              m->tensor, tw, m->N3, m->P2, m->K1, m->P2h, m->P3h, ctrl);
+              m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
 }
 template <int L>
 static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     constexpr int TB = tb_triple(L);
     NM_LAUNCH(m, NM_PROF_CONV, (k_yconv<L, TB>), dim3((m->K1 + TB - 1) / TB), dim3(256), 0, m->spec,
-              m->tensor, tw, m->N2, m->K1, m->P2h, ctrl);
+              m->tensor, tw, m->N2, m->K1, m->KP, m->P2h, ctrl);
 }
 
 #define NM_DISPATCH_POW2(LEN, FN, ...)                       \

@@ -272,8 +272,9 @@ static hipError_t upload_phases(int P, double2 **dev, hipStream_t stream) {
 hipError_t build_kspace_tensor(nm_mesh *m) {
     const int n1 = m->N1, n2 = m->N2, n3 = m->N3;
     const long long oct = (long long)n1 * n2 * n3;
-    const long long sa = 6LL * n3 * n2 * m->K1;
-    const long long sb = 6LL * n3 * m->P2h * m->K1;
+    // x frequencies stored at the padded pitch KP (entries past K1 unused)
+    const long long sa = 6LL * n3 * n2 * m->KP;
+    const long long sb = 6LL * n3 * m->P2h * m->KP;
     double *octd = nullptr, *A = nullptr, *B = nullptr;
     double2 *c1 = nullptr, *c2 = nullptr, *c3 = nullptr;
     hipError_t e = hipMalloc(&octd, sizeof(double) * 6 * oct);
@@ -285,19 +286,19 @@ hipError_t build_kspace_tensor(nm_mesh *m) {
     if (e == hipSuccess) e = launch_newell_octant(n1, n2, n3, m->h, octd, m->stream);
     if (e == hipSuccess) {
         const int th = 128;
-        // x: [6][n3][n2][n1] -> [6][n3][n2][K1]
+        // x: [6][n3][n2][n1] -> [6][n3][n2][KP]
         long long tot = sa;
         hipLaunchKernelGGL((k_axis_transform<double>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
-                           0, m->stream, octd, A, 0, 1, n1, m->K1, n3 * n2, m->P1, c1, 0.0);
-        // y: [6][n3][n2][K1] -> [6][n3][P2h][K1]
+                           0, m->stream, octd, A, 0, 1, n1, m->KP, n3 * n2, m->P1, c1, 0.0);
+        // y: [6][n3][n2][KP] -> [6][n3][P2h][KP]
         tot = sb;
         hipLaunchKernelGGL((k_axis_transform<double>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
-                           0, m->stream, A, B, 1, m->K1, n2, m->P2h, n3, m->P2, c2, 0.0);
-        // z: [6][n3][P2h][K1] -> [6][P3h][P2h][K1], sign and 1/(P1 P2 P3)
-        tot = 6LL * m->P3h * m->P2h * m->K1;
+                           0, m->stream, A, B, 1, m->KP, n2, m->P2h, n3, m->P2, c2, 0.0);
+        // z: [6][n3][P2h][KP] -> [6][P3h][P2h][KP], sign and 1/(P1 P2 P3)
+        tot = 6LL * m->P3h * m->P2h * m->KP;
         const double scale = 1.0 / ((double)m->P1 * m->P2 * m->P3);
         hipLaunchKernelGGL((k_axis_transform<float>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
-                           0, m->stream, B, m->tensor, 2, m->P2h * m->K1, n3, m->P3h, 1, m->P3, c3,
+                           0, m->stream, B, m->tensor, 2, m->P2h * m->KP, n3, m->P3h, 1, m->P3, c3,
                            scale);
         e = hipGetLastError();
         hipError_t e2 = hipStreamSynchronize(m->stream);

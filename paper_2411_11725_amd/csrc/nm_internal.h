@@ -45,6 +45,7 @@ struct nm_mesh {
     int NX, NY, NZ;          // nodes per axis (N + 1)
     int P1, P2, P3;          // padded FFT lengths (powers of two)
     int K1;                  // P1 / 2 + 1 complex x-frequencies
+    int KP;                  // row pitch of spectrum and tensor: K1 rounded up to 16
     int P2h, P3h;            // P2 / 2 + 1, P3 / 2 + 1 stored tensor frequencies
     double h[3], V, gamma;
     int64_t n_nodes, n_cells;
@@ -54,7 +55,7 @@ struct nm_mesh {
     // owned material copies (cell arrays) and derived quantities
     float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;
     float *wc;               // mu0 Ms_c V / 8: weight of a cell-constant field
-    float4 *cellA, *cellB;   // packed per cell: {2A, Ku e}, {e, mu0 Ms V/8}
+    float4 *cellP;           // packed per cell: {2A with the sign of Ku, sqrt|Ku| e}
     float *wstat;            // 3 x nc: mu0 Ms V/8 (h_uniform + h_cell)
     float *wdrive;           // mu0 Ms V/8 * drive mask (when a drive is set)
     float h_uniform[3], drive_amp[3];
@@ -66,8 +67,8 @@ struct nm_mesh {
     float *inv_mass, *alpha_n, *gp_n;
 
     // demagnetisation
-    float2 *spec;            // [3][N3][P2][K1] complex workspace
-    float *tensor;           // [6][P3h][P2h][K1] real k-space tensor / (P1 P2 P3)
+    float2 *spec;            // [3][N3][P2][KP] complex workspace
+    float *tensor;           // [6][P3h][P2h][KP] real k-space tensor / (P1 P2 P3)
     float *hd;               // [3][n_cells] demag cell field
     bool tensor_ready;
 
@@ -148,7 +149,7 @@ dim3 stencil_grid(const nm_mesh *m);   // blocks of the fused node kernel
 hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]);
 hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
-hipError_t launch_cell_pack(nm_mesh *m);   // cellA, cellB, wstat, wdrive from the raw copies
+hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat, wdrive from the raw copies
 hipError_t launch_rk4_advance(nm_mesh *m);
 
 // stepping building blocks shared by nm_llg_step and the solve server

@@ -23,7 +23,7 @@ struct StencilParams {
     long long nn, nc;
     float Kp[8], Mp[8];
     // node kernel: packed cell data and the pre-weighted cell-field source
-    const float4 *cellA, *cellB;   // {2A, Ku e} and {e, mu0 Ms V/8}
+    const float4 *cellP;           // {2A with the sign bit of Ku, sqrt|Ku| e}
     const float *src;              // 3 x nc: mu0 Ms V/8 (H_d [+ static H_ext]) or NULL
     const float *wdrive;           // mu0 Ms V/8 * drive mask, or NULL
     // energy kernel: raw cell data
@@ -114,7 +114,7 @@ __device__ __forceinline__ void reduce_partial(double sq, float mf, int nf, ErrP
 // so that their latency overlaps the arithmetic.  The stage is a template
 // parameter so every tableau coefficient is a compile-time constant.
 template <int MODE, int STAGE>
-__global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_node(StencilParams P, StageArgs S) {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
@@ -152,6 +152,13 @@ __global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
                 for (int c = 0; c < 3; ++c)
                     kk[j][c] = (j < STAGE - 1 && dp_w(STAGE, j + 1) != 0.0) ? S.k[j][c * nn + n] : 0.f;
         }
+        // ---- per-node coefficients
+        const float im = P.inv_mass[n];
+        float gp = 0.f, al = 0.f;
+        if (MODE != kModeField) {
+            gp = P.gp_n[n];
+            al = P.alpha_n[n];
+        }
         // ---- neighbourhood of m
         const int x = (int)(n % P.NX);
         const long long r = n / P.NX;
@@ -173,62 +180,79 @@ __global__ void __launch_bounds__(256) k_node(StencilParams P, StageArgs S) {
 #pragma unroll
                     for (int c = 0; c < 3; ++c) v[k][c] = ok ? in[c * nn + nb] : 0.f;
                 }
+        // ---- the 8 cells around the node, q = i1 + 2 i2 + 4 i3 for the cell
+        // (x - i1, y - i2, z - i3).  A cell outside the mesh is read at a
+        // clamped index and weighted by zero: no branch separates the loads,
+        // so they are all in flight together with the neighbourhood above.
+        long long ci[8];
+        float cw[8];
+        float4 cp[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int cx = x - (q & 1), cy = y - ((q >> 1) & 1), cz = z - (q >> 2);
+            const bool inside = cx >= 0 && cx < P.N1 && cy >= 0 && cy < P.N2 && cz >= 0 && cz < P.N3;
+            ci[q] = ((long long)min(max(cz, 0), P.N3 - 1) * P.N2 + min(max(cy, 0), P.N2 - 1)) * P.N1 +
+                    min(max(cx, 0), P.N1 - 1);
+            cw[q] = inside ? 1.f : 0.f;
+            cp[q] = P.cellP[ci[q]];
+        }
+        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+        if (P.src) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                r0 += cw[q] * P.src[ci[q]];
+                r1 += cw[q] * P.src[P.nc + ci[q]];
+                r2 += cw[q] * P.src[2 * P.nc + ci[q]];
+            }
+        }
+        if (P.wdrive) {
+            const float sdrive = (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
+            float wd = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) wd += cw[q] * P.wdrive[ci[q]];
+            wd *= sdrive;
+            r0 += wd * P.damp[0];
+            r1 += wd * P.damp[1];
+            r2 += wd * P.damp[2];
+        }
         const float mn[3] = {v[13][0], v[13][1], v[13][2]};
         const bool ex = P.terms & NM_T_EXCHANGE;
         const bool an = (P.terms & NM_T_ANIS) != 0;
-        float sdrive = 0.f;
-        if (P.wdrive) sdrive = (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f;
+        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
 #pragma unroll
-        for (int i3 = 0; i3 < 2; ++i3)
+        for (int q = 0; q < 8; ++q) {
+            const int i1 = q & 1, i2 = (q >> 1) & 1, i3 = q >> 2;
+            // cp = {2A carrying the sign of Ku, u = sqrt|Ku| e}
+            const float a2 = cw[q] * fabsf(cp[q].x);
+            const float sg = signbit(cp[q].x) ? -cw[q] : cw[q];
+            float sp = 0.f;
 #pragma unroll
-            for (int i2 = 0; i2 < 2; ++i2)
+            for (int b3 = 0; b3 < 2; ++b3)
 #pragma unroll
-                for (int i1 = 0; i1 < 2; ++i1) {
-                    const int cx = x - i1, cy = y - i2, cz = z - i3;
-                    if (cx < 0 || cx >= P.N1 || cy < 0 || cy >= P.N2 || cz < 0 || cz >= P.N3) continue;
-                    const long long c = ((long long)cz * P.N2 + cy) * P.N1 + cx;
-                    if (P.src) {
-                        r0 += P.src[c];
-                        r1 += P.src[P.nc + c];
-                        r2 += P.src[2 * P.nc + c];
+                for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+                    for (int b1 = 0; b1 < 2; ++b1) {
+                        const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
+                        const int k = (b3 - i3 + 1) * 9 + (b2 - i2 + 1) * 3 + (b1 - i1 + 1);
+                        if (ex && mask != 0) {
+                            const float w = a2 * P.Kp[mask];
+                            g0 += w * (v[k][0] - mn[0]);
+                            g1 += w * (v[k][1] - mn[1]);
+                            g2 += w * (v[k][2] - mn[2]);
+                        }
+                        if (an) sp += P.Mp[mask] * (v[k][0] * cp[q].y + v[k][1] * cp[q].z + v[k][2] * cp[q].w);
                     }
-                    if (P.wdrive) {
-                        const float d = P.wdrive[c] * sdrive;
-                        r0 += d * P.damp[0];
-                        r1 += d * P.damp[1];
-                        r2 += d * P.damp[2];
-                    }
-                    if (!(ex || an)) continue;
-                    const float4 A = P.cellA[c];   // {2A, Ku e}
-                    const float4 E = P.cellB[c];   // {e, w}
-                    float sp = 0.f;
-#pragma unroll
-                    for (int b3 = 0; b3 < 2; ++b3)
-#pragma unroll
-                        for (int b2 = 0; b2 < 2; ++b2)
-#pragma unroll
-                            for (int b1 = 0; b1 < 2; ++b1) {
-                                const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
-                                const int k = (b3 - i3 + 1) * 9 + (b2 - i2 + 1) * 3 + (b1 - i1 + 1);
-                                if (ex && mask != 0) {
-                                    const float w = A.x * P.Kp[mask];
-                                    g0 += w * (v[k][0] - mn[0]);
-                                    g1 += w * (v[k][1] - mn[1]);
-                                    g2 += w * (v[k][2] - mn[2]);
-                                }
-                                if (an) sp += P.Mp[mask] * (v[k][0] * E.x + v[k][1] * E.y + v[k][2] * E.z);
-                            }
-                    if (an) {
-                        g0 -= 2.f * sp * A.y;
-                        g1 -= 2.f * sp * A.z;
-                        g2 -= 2.f * sp * A.w;
-                    }
-                }
-        const float im = P.inv_mass[n];
+            if (an) {
+                // -2 Ku e (sum M m . e) = -2 sign(Ku) u (sum M m . u)
+                const float f2 = 2.f * sg * sp;
+                g0 -= f2 * cp[q].y;
+                g1 -= f2 * cp[q].z;
+                g2 -= f2 * cp[q].w;
+            }
+        }
         const float H[3] = {(r0 - g0) * im, (r1 - g1) * im, (r2 - g2) * im};
         float f[3] = {0.f, 0.f, 0.f};
-        if (MODE != kModeField) llg_rhs(mn, H, P.gp_n[n], P.alpha_n[n], f);
+        if (MODE != kModeField) llg_rhs(mn, H, gp, al, f);
         if (MODE == kModeField) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) S.out[c * nn + n] = H[c];
@@ -492,8 +516,7 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
         P.Kp[i] = m->Kp[i];
         P.Mp[i] = m->Mp[i];
     }
-    P.cellA = m->cellA;
-    P.cellB = m->cellB;
+    P.cellP = m->cellP;
     // source of the node kernel: the demag pass writes mu0 Ms V/8 (H_d [+ static
     // H_ext]) into hd; without demag the static Zeeman part is read directly
     P.src = (terms & NM_T_DEMAG) ? m->hd : ((terms & NM_T_ZEEMAN) ? m->wstat : nullptr);
@@ -609,21 +632,23 @@ hipError_t launch_dp45_finish(nm_mesh *m, float *mstate) {
 __global__ void k_cell_pack(const float *__restrict__ A2, const float *__restrict__ Ku,
                             const float *__restrict__ easy, const float *__restrict__ wc,
                             const float *__restrict__ hcell, const float *__restrict__ dmask,
-                            float hu0, float hu1, float hu2, float4 *__restrict__ cellA,
-                            float4 *__restrict__ cellB, float *__restrict__ wstat,
+                            float hu0, float hu1, float hu2, float4 *__restrict__ cellP,
+                            float *__restrict__ wstat,
                             float *__restrict__ wdrive, long long nc) {
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
     if (c >= nc) return;
-    float e0 = 0.f, e1 = 0.f, e2 = 0.f, k = 0.f;
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f, k = 0.f;
     if (Ku) {
         k = Ku[c];
-        e0 = easy[c];
-        e1 = easy[nc + c];
-        e2 = easy[2 * nc + c];
+        const float r = sqrtf(fabsf(k));
+        u0 = r * easy[c];
+        u1 = r * easy[nc + c];
+        u2 = r * easy[2 * nc + c];
     }
     const float w = wc[c];
-    cellA[c] = make_float4(A2[c], k * e0, k * e1, k * e2);
-    cellB[c] = make_float4(e0, e1, e2, w);
+    // 2A >= 0, so its sign bit is free to carry the sign of Ku (easy axis or
+    // easy plane): Ku e (m . e) = sign(Ku) u (m . u) with u = sqrt|Ku| e
+    cellP[c] = make_float4(copysignf(A2[c], k), u0, u1, u2);
     float h0 = hu0, h1 = hu1, h2 = hu2;
     if (hcell) {
         h0 += hcell[c];
@@ -641,7 +666,7 @@ hipError_t launch_cell_pack(nm_mesh *m) {
     hipLaunchKernelGGL(k_cell_pack, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, m->stream, m->A2,
                        m->has_anis ? m->Ku : nullptr, m->easy, m->wc, m->has_hcell ? m->h_cell : nullptr,
                        m->has_drive ? m->drive_mask : nullptr, m->h_uniform[0], m->h_uniform[1],
-                       m->h_uniform[2], m->cellA, m->cellB, m->wstat, m->wdrive, nc);
+                       m->h_uniform[2], m->cellP, m->wstat, m->wdrive, nc);
     return hipGetLastError();
 }
 

@@ -124,9 +124,10 @@ def magnonic(n=(256, 128, 1), seed=105):
 
 
 def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
-                 hetero=True):
+                 hetero=True, ku_range=(0.0, 5e5)):
     """Small heterogeneous problem used by the parity tests: every term on,
-    per-cell Ms, A, alpha, Ku, easy axes and applied field."""
+    per-cell Ms, A, alpha, Ku ~ U[ku_range] (a negative Ku makes the cell
+    easy-plane), easy axes and applied field."""
     rng = np.random.default_rng(seed)
     n1, n2, n3 = n
     cells = (n3, n2, n1)
@@ -135,7 +136,7 @@ def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
     alpha = rng.uniform(0.01, 0.5, size=cells) if hetero else 0.1
     hc = rng.uniform(-5e4, 5e4, size=(3,) + cells) if field else None
     return make_problem(n, h, Ms, A, alpha, seed=seed + 1,
-                        Ku=("uniform", 0.0, 5e5) if anis else None,
+                        Ku=("uniform",) + tuple(ku_range) if anis else None,
                         easy="random", h_uniform=(1e4, -2e4, 3e4) if field else (0, 0, 0),
                         h_cell=hc)
 

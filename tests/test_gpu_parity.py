@@ -97,6 +97,17 @@ def test_heff_matches_oracle(n, h, terms):
     assert rel_l2(g, want) <= 1e-5
 
 
+@pytest.mark.parametrize("n,h", SHAPES[:3] + SHAPES[4:5])
+def test_anisotropy_of_either_sign_matches_oracle(n, h):
+    """Easy-axis (Ku > 0) and easy-plane (Ku < 0) cells mixed in one mesh."""
+    p = synth.small_random(n, h, seed=48, ku_range=(-5e5, 5e5))
+    assert (p["Ku"] < 0).any() and (p["Ku"] > 0).any()
+    om, omat, om0 = to_oracle(p)
+    for terms in (ANISOTROPY, ALL_TERMS):
+        g = _field(p, terms)
+        assert rel_l2(g, oracle.heff(om, omat, om0, terms)) <= 1e-5
+
+
 @pytest.mark.parametrize("n,h", SHAPES[:4])
 def test_llg_rhs_matches_oracle(n, h):
     p = synth.small_random(n, h, seed=44)
