@@ -24,6 +24,16 @@ namespace nm {
 
 __host__ __device__ constexpr int x_rows_per_block(int L) { return L >= 512 ? 1 : 512 / L; }
 
+// Loads outside the live region are made at clamped addresses (always inside
+// data written by the previous pass, hence finite) and zeroed by a 0/1 factor.
+// A select or branch would let the compiler turn each load into a guarded one
+// that waits for its own memory round trip; the factor keeps all loads of a
+// thread in flight together.
+__device__ __forceinline__ float2 keep(float2 v, bool ok) {
+    const float f = ok ? 1.f : 0.f;
+    return make_float2(v.x * f, v.y * f);
+}
+
 // ---------------------------------------------------------------- x forward
 // block (by, z): the RB cell rows y0 <= y < y0 + RB of plane z.  The 8 corners
 // of each cell are gathered straight from HBM; adjacent rows of the block share
@@ -36,47 +46,54 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
+    __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int y0 = blockIdx.x * RB, z = blockIdx.y;
     const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
     const long long nn = (long long)NX * NY * (N3 + 1);
-    for (int it = tid; it < RB * L; it += 256) {
+    // rows past the plane's end and cells past N1 are read at clamped
+    // addresses and zeroed by a select: a branch around a load would make
+    // every load a separate memory round trip
+    static_assert((RB * L) % 256 == 0, "whole iterations");
+#pragma unroll
+    for (int i = 0; i < RB * L / 256; ++i) {
+        const int it = tid + i * 256;
         const int rb = it / L, n = it - (it / L) * L;
-        float2 v[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        if (rb < nrows) {
-            const int y = y0 + rb;
+        const bool rok = rb < nrows;
+        const int y = y0 + min(rb, nrows - 1);
+        float2 v[3];
 #pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                const int x = 2 * n + hh;
-                if (x < N1) {
-                    const float ms = 0.125f * Ms[((long long)z * N2 + y) * N1 + x];
-                    const long long b00 = ((long long)z * NY + y) * NX + x;
-                    const long long b01 = b00 + NX;
-                    const long long b10 = b00 + (long long)NX * NY;
-                    const long long b11 = b10 + NX;
+        for (int hh = 0; hh < 2; ++hh) {
+            const bool ok = rok && 2 * n + hh < N1;
+            const int x = min(2 * n + hh, N1 - 1);
+            const float ms = 0.125f * Ms[((long long)z * N2 + y) * N1 + x];
+            const long long b00 = ((long long)z * NY + y) * NX + x;
+            const long long b01 = b00 + NX;
+            const long long b10 = b00 + (long long)NX * NY;
+            const long long b11 = b10 + NX;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
-                        const float *mc = mag + c * nn;
-                        const float sum = ((mc[b00] + mc[b00 + 1]) + (mc[b01] + mc[b01 + 1]))
-                                        + ((mc[b10] + mc[b10 + 1]) + (mc[b11] + mc[b11 + 1]));
-                        if (hh == 0) v[c].x = ms * sum; else v[c].y = ms * sum;
-                    }
-                }
+            for (int c = 0; c < 3; ++c) {
+                const float *mc = mag + c * nn;
+                const float sum = ((mc[b00] + mc[b00 + 1]) + (mc[b01] + mc[b01 + 1]))
+                                + ((mc[b10] + mc[b10 + 1]) + (mc[b11] + mc[b11 + 1]));
+                const float val = (ok ? 1.f : 0.f) * (ms * sum);
+                if (hh == 0) v[c].x = val; else v[c].y = val;
             }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) s[(c * RB + rb) * L + n] = v[c];
     }
+    load_twiddles<2 * L, 256>(tl, tw, tid);
     __syncthreads();
-    lds_fft<L, -1, NP, 256, false>(s, tw, tid);
+    lds_fft<L, -1, NP, 256, false, 2 * L>(s, tl, tid);
     // untangle the half-length transform: X_k = E_k + W^k O_k, W = exp(-2 pi i / P1)
     for (int it = tid; it < RB * (L + 1); it += 256) {
         const int rb = it / (L + 1), k = it - (it / (L + 1)) * (L + 1);
         if (rb >= nrows) continue;
         const int y = y0 + rb;
-        const float2 w = twiddle<-1>(tw, k * (kTwN / (2 * L)));
+        const float2 w = twiddle<-1>(tl, k);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float2 zk = s[(c * RB + rb) * L + (k & (L - 1))];
@@ -98,55 +115,73 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
+    __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int rows = N2 * N3;
     const int row0 = blockIdx.x * RB;
     const long long nc = (long long)N1 * N2 * N3;
-    for (int it = tid; it < RB * L; it += 256) {
+    static_assert((RB * L) % 256 == 0, "whole iterations");
+    constexpr int NI = RB * L / 256;
+    // thread i-th item: row rb, frequency k on input, cells 2k, 2k + 1 on output
+    float2 xk[NI][3], xc[NI][3];
+    float wv[NI][2], av[NI][2][3];
+    long long oi[NI][2];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int it = tid + i * 256;
         const int rb = it / L, k = it - (it / L) * L;
         const int row = row0 + rb;
-        if (row < rows) {
-            const int y = row % N2, z = row / N2;
-            // Z_k = E_k + i O_k with E_k = X_k + conj X_{L-k},
-            // O_k = (X_k - conj X_{L-k}) W^-k: the length-L inverse then yields
-            // P1 * (a_2n + i a_2n+1)
-            const float2 wi = twiddle<1>(tw, k * (kTwN / (2 * L)));
+        const bool rok = row < rows;   // rows past the end: clamped read, zeroed
+        const int rc = min(row, rows - 1);
+        const int y = rc % N2, z = rc / N2;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float2 *rowp = spec + (((long long)c * N3 + z) * P2 + y) * KP;
-                const float2 xk = rowp[k];
-                const float2 xc = cconj(rowp[L - k]);
-                const float2 e = cadd(xk, xc);
-                const float2 o = cmul(csub(xk, xc), wi);
-                s[(c * RB + rb) * L + k] = make_float2(e.x - o.y, e.y + o.x);
-            }
-        } else {
+        for (int c = 0; c < 3; ++c) {
+            const float2 *rowp = spec + (((long long)c * N3 + z) * P2 + y) * KP;
+            xk[i][c] = keep(rowp[k], rok);
+            xc[i][c] = keep(cconj(rowp[L - k]), rok);
+        }
+        // output weights and static fields, at clamped cells
+        const long long cb = ((long long)z * N2 + y) * N1;
+        oi[i][0] = cb + min(2 * k, N1 - 1);
+        oi[i][1] = cb + min(2 * k + 1, N1 - 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) s[(c * RB + rb) * L + k] = make_float2(0.f, 0.f);
+        for (int h = 0; h < 2; ++h) {
+            wv[i][h] = src_mode > 0 ? wc[oi[i][h]] : 1.f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) av[i][h][c] = src_mode == 2 ? wstat[c * nc + oi[i][h]] : 0.f;
+        }
+    }
+    load_twiddles<2 * L, 256>(tl, tw, tid);
+    __syncthreads();
+    // Z_k = E_k + i O_k with E_k = X_k + conj X_{L-k},
+    // O_k = (X_k - conj X_{L-k}) W^-k: the length-L inverse then yields
+    // P1 * (a_2n + i a_2n+1)
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int it = tid + i * 256;
+        const int rb = it / L, k = it - (it / L) * L;
+        const float2 wi = twiddle<1>(tl, k);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 e = cadd(xk[i][c], xc[i][c]);
+            const float2 o = cmul(csub(xk[i][c], xc[i][c]), wi);
+            s[(c * RB + rb) * L + k] = make_float2(e.x - o.y, e.y + o.x);
         }
     }
     __syncthreads();
-    lds_fft<L, 1, NP, 256, false>(s, tw, tid);
-    for (int it = tid; it < RB * L; it += 256) {
+    lds_fft<L, 1, NP, 256, false, 2 * L>(s, tl, tid);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int it = tid + i * 256;
         const int rb = it / L, n = it - (it / L) * L;
-        const int row = row0 + rb;
-        if (row >= rows) continue;
-        const int y = row % N2, z = row / N2;
-        const long long cb = ((long long)z * N2 + y) * N1;
+        if (row0 + rb >= rows) continue;
         const int x0 = 2 * n;
-        float w0 = 1.f, w1 = 1.f;
-        if (src_mode > 0) {
-            if (x0 < N1) w0 = wc[cb + x0];
-            if (x0 + 1 < N1) w1 = wc[cb + x0 + 1];
-        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float2 v = s[(c * RB + rb) * L + n];
-            if (x0 < N1)
-                hd[c * nc + cb + x0] = src_mode == 2 ? w0 * v.x + wstat[c * nc + cb + x0] : w0 * v.x;
-            if (x0 + 1 < N1)
-                hd[c * nc + cb + x0 + 1] = src_mode == 2 ? w1 * v.y + wstat[c * nc + cb + x0 + 1] : w1 * v.y;
+            if (x0 < N1) hd[c * nc + oi[i][0]] = wv[i][0] * v.x + av[i][0][c];
+            if (x0 + 1 < N1) hd[c * nc + oi[i][1]] = wv[i][1] * v.y + av[i][1][c];
         }
     }
 }
@@ -158,6 +193,7 @@ __global__ void __launch_bounds__(256)
 k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1, int KP, int n_in,
         int n_out, const Ctrl *__restrict__ ctrl) {
     __shared__ float2 s[L * TB];
+    __shared__ float2 tl[L / 2 + 1];
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int ncols = N3 * KP;
@@ -167,17 +203,27 @@ k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1
     static_assert(256 % TB == 0, "tile width must divide the block");
     const int b = tid % TB, e0 = tid / TB;
     constexpr int ESTEP = 256 / TB;
+    constexpr int NE = L / ESTEP;
+    static_assert(L % ESTEP == 0, "whole columns per thread");
     const int col = col0 + b;
     const int zc = col / KP, kx = col - zc * KP;
-    const bool cok = col < ncols && kx < K1;   // pad columns are never touched
+    const bool cok = col < ncols && kx < K1;   // pad columns are never written
+    // invalid columns and rows past n_in are read at clamped addresses and
+    // zeroed by a select, so all NE loads are in flight together
     float2 *cbase = base + (long long)zc * L * KP + kx;
-    for (int e = e0; e < L; e += ESTEP) {
-        float2 v = make_float2(0.f, 0.f);
-        if (cok && e < n_in) v = cbase[(long long)e * KP];
-        s[e * TB + b] = v;
+    const float2 *lbase = cok ? cbase : base;
+    float2 v[NE];
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int e = e0 + i * ESTEP;
+        const float2 t = lbase[(long long)min(e, n_in - 1) * KP];
+        v[i] = keep(t, cok && e < n_in);
     }
+    load_twiddles<L, 256>(tl, tw, tid);
+#pragma unroll
+    for (int i = 0; i < NE; ++i) s[(e0 + i * ESTEP) * TB + b] = v[i];
     __syncthreads();
-    lds_fft<L, DIR, TB, 256, true>(s, tw, tid);
+    lds_fft<L, DIR, TB, 256, true, L>(s, tl, tid);
     if (cok)
         for (int e = e0; e < n_out; e += ESTEP) cbase[(long long)e * KP] = s[e * TB + b];
 }
@@ -217,7 +263,8 @@ __global__ void __launch_bounds__(256)
 k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
         int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
     constexpr int NP = 3 * TB;
-    __shared__ float2 s[L * NP];
+    __shared__ float2 s[(L + 1) * NP];   // + one spare row for masked lanes
+    __shared__ float2 tl[L / 2 + 1];
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const long long plane = (long long)P2 * KP;
@@ -230,40 +277,64 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
         const int kx = TB <= 16 ? kx0 + b : col % KP;
         return col < ncols && kx < K1;
     };
-    for (int it = tid; it < L * NP; it += 256) {
+    // planes past N3 and pad columns: clamped reads zeroed by a select
+    static_assert((L * NP) % 256 == 0, "whole iterations");
+    constexpr int NI = L * NP / 256;
+    float2 v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int it = tid + i * 256;
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
-        const int col = col0 + b;
-        float2 v = make_float2(0.f, 0.f);
-        if (e < N3 && valid(b)) v = spec[((long long)c * N3 + e) * plane + col];
-        s[e * NP + p] = v;
+        const bool ok = e < N3 && valid(b);
+        const int col = valid(b) ? col0 + b : col0 - kx0;
+        const float2 t = spec[((long long)c * N3 + min(e, N3 - 1)) * plane + col];
+        v[i] = keep(t, ok);
     }
-    __syncthreads();
-    lds_fft<L, -1, NP, 256, true>(s, tw, tid);
-    // kz and L - kz share the stored tensor entry (xz, yz flip sign): one read
-    // serves both
+    // the tensor entries this thread applies after the forward transform,
+    // fetched now so their latency hides behind the FFT
     const long long tstride = (long long)P3h * P2h * KP;
-    for (int it = tid; it < (L / 2 + 1) * TB; it += 256) {
+    constexpr int NT = ((L / 2 + 1) * TB + 255) / 256;
+    Tensor6 Nt[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int it = tid + i * 256;
         const int b = it % TB, kzr = it / TB;
-        const int col = col0 + b;
-        if (!valid(b)) continue;
+        const bool ok = valid(b) && kzr <= L / 2;
+        const int col = ok ? col0 + b : col0 - kx0;
         const int ky = col / KP, kx = col - (col / KP) * KP;
         const bool fy = ky > P2 / 2;
         const int kyr = fy ? P2 - ky : ky;
-        const Tensor6 N = tensor_load(T, tstride, ((long long)kzr * P2h + kyr) * KP + kx, fy ? -1.f : 1.f, true);
+        Nt[i] = tensor_load(T, tstride, ((long long)(ok ? kzr : 0) * P2h + kyr) * KP + kx, fy ? -1.f : 1.f, true);
+    }
+    load_twiddles<L, 256>(tl, tw, tid);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s[tid + i * 256] = v[i];   // = s[e * NP + p]
+    __syncthreads();
+    lds_fft<L, -1, NP, 256, true, L>(s, tl, tid);
+    // kz and L - kz share the stored tensor entry (xz, yz flip sign): one read
+    // serves both.  Branch-free: lanes without a valid (column, kz) use a
+    // clamped entry and write their product into the spare row s[L * NP ..]
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int it = tid + i * 256;
+        const int b = it % TB, kzr = it / TB;
+        const bool ok = valid(b) && kzr <= L / 2;
+        const int kzc = ok ? kzr : 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int kz = h == 0 ? kzr : L - kzr;
-            if (h == 1 && (kzr == 0 || kzr == L / 2)) break;
+            const int kz = h == 0 ? kzc : (L - kzc) & (L - 1);
+            const bool wr = ok && (h == 0 || (kzr != 0 && kzr != L / 2));
+            const int row = wr ? kz * NP : L * NP;
             float2 mx = s[kz * NP + b], my = s[kz * NP + TB + b], mz = s[kz * NP + 2 * TB + b];
-            tensor_apply(N, h == 0 ? 1.f : -1.f, mx, my, mz);
-            s[kz * NP + b] = mx;
-            s[kz * NP + TB + b] = my;
-            s[kz * NP + 2 * TB + b] = mz;
+            tensor_apply(Nt[i], h == 0 ? 1.f : -1.f, mx, my, mz);
+            s[row + b] = mx;
+            s[row + TB + b] = my;
+            s[row + 2 * TB + b] = mz;
         }
     }
     __syncthreads();
-    lds_fft<L, 1, NP, 256, true>(s, tw, tid);
+    lds_fft<L, 1, NP, 256, true, L>(s, tl, tid);
     for (int it = tid; it < N3 * NP; it += 256) {
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
@@ -278,43 +349,62 @@ __global__ void __launch_bounds__(256)
 k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
         int N2, int K1, int KP, int P2h, const Ctrl *__restrict__ ctrl) {
     constexpr int NP = 3 * TB;
-    __shared__ float2 s[L * NP];
+    __shared__ float2 s[(L + 1) * NP];   // + one spare row for masked lanes
+    __shared__ float2 tl[L / 2 + 1];
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const long long cstride = (long long)L * KP;
     const int col0 = blockIdx.x * TB;
-    for (int it = tid; it < L * NP; it += 256) {
+    static_assert((L * NP) % 256 == 0, "whole iterations");
+    constexpr int NI = L * NP / 256;
+    float2 v[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int it = tid + i * 256;
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
-        float2 v = make_float2(0.f, 0.f);
-        if (col < K1 && e < N2) v = spec[c * cstride + (long long)e * KP + col];
-        s[e * NP + p] = v;
+        const float2 t = spec[c * cstride + (long long)min(e, N2 - 1) * KP + min(col, K1 - 1)];
+        v[i] = keep(t, col < K1 && e < N2);
     }
-    __syncthreads();
-    lds_fft<L, -1, NP, 256, true>(s, tw, tid);
-    // ky and L - ky share the stored tensor entry (xy flips sign)
     const long long tstride = (long long)P2h * KP;
-    for (int it = tid; it < (L / 2 + 1) * TB; it += 256) {
+    constexpr int NT = ((L / 2 + 1) * TB + 255) / 256;
+    Tensor6 Nt[NT];   // fetched now, applied after the forward transform
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int it = tid + i * 256;
         const int b = it % TB, kyr = it / TB;
-        const int col = col0 + b;
-        if (col >= K1) continue;
-        const Tensor6 N = tensor_load(T, tstride, (long long)kyr * KP + col, 1.f, false);
+        const bool ok = col0 + b < K1 && kyr <= L / 2;
+        Nt[i] = tensor_load(T, tstride, (long long)(ok ? kyr : 0) * KP + min(col0 + b, K1 - 1), 1.f, false);
+    }
+    load_twiddles<L, 256>(tl, tw, tid);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) s[tid + i * 256] = v[i];
+    __syncthreads();
+    lds_fft<L, -1, NP, 256, true, L>(s, tl, tid);
+    // ky and L - ky share the stored tensor entry (xy flips sign)
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+        const int it = tid + i * 256;
+        const int b = it % TB, kyr = it / TB;
+        const bool ok = col0 + b < K1 && kyr <= L / 2;
+        const int kyc = ok ? kyr : 0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int ky = h == 0 ? kyr : L - kyr;
-            if (h == 1 && (kyr == 0 || kyr == L / 2)) break;
-            Tensor6 Nh = N;
-            if (h == 1) Nh.xy = -N.xy;
+            const int ky = h == 0 ? kyc : (L - kyc) & (L - 1);
+            const bool wr = ok && (h == 0 || (kyr != 0 && kyr != L / 2));
+            const int row = wr ? ky * NP : L * NP;
+            Tensor6 Nh = Nt[i];
+            if (h == 1) Nh.xy = -Nh.xy;
             float2 mx = s[ky * NP + b], my = s[ky * NP + TB + b], mz = s[ky * NP + 2 * TB + b];
             tensor_apply(Nh, 1.f, mx, my, mz);
-            s[ky * NP + b] = mx;
-            s[ky * NP + TB + b] = my;
-            s[ky * NP + 2 * TB + b] = mz;
+            s[row + b] = mx;
+            s[row + TB + b] = my;
+            s[row + 2 * TB + b] = mz;
         }
     }
     __syncthreads();
-    lds_fft<L, 1, NP, 256, true>(s, tw, tid);
+    lds_fft<L, 1, NP, 256, true, L>(s, tl, tid);
     for (int it = tid; it < N2 * NP; it += 256) {
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
@@ -364,9 +454,23 @@ static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
               m->tensor, tw, m->N2, m->K1, m->KP, m->P2h, ctrl);
 }
 
-#define NM_DISPATCH_POW2(LEN, FN, ...)                       \
+// row passes: half lengths 2..512 (P1 = 4..1024); column passes: 4..1024
+// (n >= 2 cells along y, and along z whenever the z pass runs)
+#define NM_DISPATCH_ROW(LEN, FN, ...)                        \
     switch (LEN) {                                           \
         case 2: FN<2>(__VA_ARGS__); break;                   \
+        case 4: FN<4>(__VA_ARGS__); break;                   \
+        case 8: FN<8>(__VA_ARGS__); break;                   \
+        case 16: FN<16>(__VA_ARGS__); break;                 \
+        case 32: FN<32>(__VA_ARGS__); break;                 \
+        case 64: FN<64>(__VA_ARGS__); break;                 \
+        case 128: FN<128>(__VA_ARGS__); break;               \
+        case 256: FN<256>(__VA_ARGS__); break;               \
+        case 512: FN<512>(__VA_ARGS__); break;               \
+        default: return hipErrorInvalidValue;                \
+    }
+#define NM_DISPATCH_COL(LEN, FN, ...)                        \
+    switch (LEN) {                                           \
         case 4: FN<4>(__VA_ARGS__); break;                   \
         case 8: FN<8>(__VA_ARGS__); break;                   \
         case 16: FN<16>(__VA_ARGS__); break;                 \
@@ -392,16 +496,15 @@ static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl,
     const float2 *tw = twiddles(m->device);
     if (!tw) return hipErrorOutOfMemory;
     const int L1 = m->P1 / 2;
-    if (L1 > 512) return hipErrorInvalidValue;
-    NM_DISPATCH_POW2(L1, launch_x_fwd, m, mag, tw, ctrl);
+    NM_DISPATCH_ROW(L1, launch_x_fwd, m, mag, tw, ctrl);
     if (m->N3 > 1) {
-        NM_DISPATCH_POW2(m->P2, launch_y_fwd, m, tw, ctrl);
-        NM_DISPATCH_POW2(m->P3, launch_zconv, m, tw, ctrl);
-        NM_DISPATCH_POW2(m->P2, launch_y_inv, m, tw, ctrl);
+        NM_DISPATCH_COL(m->P2, launch_y_fwd, m, tw, ctrl);
+        NM_DISPATCH_COL(m->P3, launch_zconv, m, tw, ctrl);
+        NM_DISPATCH_COL(m->P2, launch_y_inv, m, tw, ctrl);
     } else {
-        NM_DISPATCH_POW2(m->P2, launch_yconv, m, tw, ctrl);
+        NM_DISPATCH_COL(m->P2, launch_yconv, m, tw, ctrl);
     }
-    NM_DISPATCH_POW2(L1, launch_x_inv, m, tw, ctrl, src_mode);
+    NM_DISPATCH_ROW(L1, launch_x_inv, m, tw, ctrl, src_mode);
     return hipGetLastError();
 }
 

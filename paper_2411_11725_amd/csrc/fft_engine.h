@@ -31,11 +31,22 @@ __device__ __forceinline__ float2 mul_dir_i(float2 v) {
     return DIR < 0 ? make_float2(v.y, -v.x) : make_float2(-v.y, v.x);
 }
 
-// exp(DIR * 2 pi i t / kTwN) from the forward table
+// exp(DIR * 2 pi i t / N) from a forward table of period N (the global table
+// has N = kTwN; kernels copy the entries they need into LDS with a shorter
+// period, see load_twiddles)
 template <int DIR>
 __device__ __forceinline__ float2 twiddle(const float2 *__restrict__ tw, int t) {
     float2 w = tw[t];
     return DIR < 0 ? w : make_float2(w.x, -w.y);
+}
+
+// LDS copy tl[j] = exp(-2 pi i j / TWL), j = 0 .. TWL/2, of the global table.
+// Call after the kernel's data loads are issued: the copy's one memory round
+// trip then overlaps theirs, and every FFT pass reads its twiddles from LDS.
+template <int TWL, int NT>
+__device__ __forceinline__ void load_twiddles(float2 *tl, const float2 *__restrict__ tw, int tid) {
+    static_assert(TWL >= 2 && TWL <= kTwN && kTwN % TWL == 0, "table period");
+    for (int j = tid; j <= TWL / 2; j += NT) tl[j] = tw[j * (kTwN / TWL)];
 }
 
 template <int R, int DIR>
@@ -85,7 +96,7 @@ __device__ __forceinline__ int lds_index(int p, int i) {
     return EM ? i * NP + p : p * L + i;
 }
 
-template <int L, int R, int NS, int DIR, int NP, int NT, bool EM>
+template <int L, int R, int NS, int DIR, int NP, int NT, bool EM, int TWL>
 __device__ __forceinline__ void fft_pass(float2 *s, const float2 *__restrict__ tw, int tid) {
     constexpr int J = L / R;
     constexpr int JOBS = NP * J;
@@ -111,8 +122,9 @@ __device__ __forceinline__ void fft_pass(float2 *s, const float2 *__restrict__ t
             const int k = j % NS;
             if constexpr (NS > 1) {
                 // w^r, r < R, from the table entries w, w^2, w^4 (one extra
-                // rounding at most for the products)
-                constexpr int stride = kTwN / (NS * R);
+                // rounding at most for the products); 4 k stride < TWL / 2
+                static_assert(TWL % (NS * R) == 0, "table period");
+                constexpr int stride = TWL / (NS * R);
                 const float2 w1 = twiddle<DIR>(tw, k * stride);
                 if constexpr (R == 2) {
                     v[q][1] = cmul(v[q][1], w1);
@@ -140,20 +152,23 @@ __device__ __forceinline__ void fft_pass(float2 *s, const float2 *__restrict__ t
     __syncthreads();
 }
 
-template <int L, int NS, int DIR, int NP, int NT, bool EM>
+template <int L, int NS, int DIR, int NP, int NT, bool EM, int TWL>
 __device__ __forceinline__ void fft_passes(float2 *s, const float2 *__restrict__ tw, int tid) {
     if constexpr (NS < L) {
         constexpr int R = radix_for(L / NS);
-        fft_pass<L, R, NS, DIR, NP, NT, EM>(s, tw, tid);
-        fft_passes<L, NS * R, DIR, NP, NT, EM>(s, tw, tid);
+        fft_pass<L, R, NS, DIR, NP, NT, EM, TWL>(s, tw, tid);
+        fft_passes<L, NS * R, DIR, NP, NT, EM, TWL>(s, tw, tid);
     }
 }
 
 // Unnormalised DFT of NP pencils in LDS: X_k = sum_n x_n exp(DIR 2 pi i n k / L).
-// Expects the data written and a barrier passed; ends with a barrier.
-template <int L, int DIR, int NP, int NT, bool EM>
+// tw is a forward twiddle table of period TWL (a multiple of L), e.g. the LDS
+// copy from load_twiddles.  Expects the data written and a barrier passed;
+// ends with a barrier.
+template <int L, int DIR, int NP, int NT, bool EM, int TWL>
 __device__ __forceinline__ void lds_fft(float2 *s, const float2 *__restrict__ tw, int tid) {
-    fft_passes<L, 1, DIR, NP, NT, EM>(s, tw, tid);
+    static_assert(TWL % L == 0, "table period");
+    fft_passes<L, 1, DIR, NP, NT, EM, TWL>(s, tw, tid);
 }
 
 }  // namespace nm

@@ -108,14 +108,41 @@ __device__ __forceinline__ void reduce_partial(double sq, float mf, int nf, ErrP
     }
 }
 
-// One thread per node (consecutive nodes along x): the 27 neighbouring m
-// values are loaded once into registers, the 8 cells' packed data once per
-// cell, and the operands of the stage epilogue are fetched before the field
-// so that their latency overlaps the arithmetic.  The stage is a template
-// parameter so every tableau coefficient is a compile-time constant.
+// Element access by 32-bit byte offset from a uniform base pointer: meshes
+// have at most 512 cells per axis, so every component array is far below
+// 4 GiB and the offsets fit; the loads then take the scalar-base form with one
+// 32-bit offset register shared by the three components.
+template <class T>
+__device__ __forceinline__ T ldo(const T *base, unsigned byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void sto(T *base, unsigned byte_off, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
+// Does the neighbour at offset d (one axis, -1/0/+1) lie in the cell whose
+// corner the node is at local index i (0/1) along that axis?
+__host__ __device__ constexpr bool shares(int d, int i) { return d == 0 || (d == 1 && i == 0) || (d == -1 && i == 1); }
+
+// One thread per node (consecutive nodes along x).  All loads (27 neighbour
+// values per component, one packed float4 and the cell-field source per
+// cell, the epilogue operands) are issued before any arithmetic, at clamped
+// addresses with zero weights for whatever lies outside the mesh, so a thread
+// waits for one memory round trip.  The exchange sum is taken per neighbour:
+// neighbour d of node n is weighted by K^e at the axis-difference pattern of d
+// times the sum of 2A over the cells containing both (4 cells for a face
+// neighbour, 2 for an edge, 1 for a corner), which is the cell-by-cell sum
+// regrouped.  The stage is a template parameter so every tableau coefficient
+// is a compile-time constant.  The kernel is bound by VALU issue; a target of
+// two waves per SIMD (up to 256 VGPRs) keeps the neighbourhood, cell data and
+// epilogue operands in registers with all loads issued at once, where a
+// three-wave target spills and splits the loads (about 25 vs 32 us per launch
+// on a 128 x 128 x 32 block).
 template <int MODE, int STAGE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) k_node(StencilParams P, StageArgs S) {
-    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_node(StencilParams P, StageArgs S) {
+    const unsigned n = blockIdx.x * 256u + threadIdx.x;
     double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
     constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE)
@@ -129,87 +156,93 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         t = S.t0 + cst * dt;
     }
     const long long nn = P.nn;
-    const bool valid = n < nn;
+    const bool valid = n < (unsigned)nn;
+    const unsigned on = n * 4u;   // byte offset of node n in one component
     constexpr int NK = MODE == kModeDP45 ? (STAGE > 1 ? STAGE - 1 : 1) : 1;
     float ms[3] = {0.f, 0.f, 0.f}, ac[3] = {0.f, 0.f, 0.f}, kk[NK][3];
     double sq = 0.0;
     float mf = 0.f;
     int nf = 0;
     if (valid) {
-        // ---- epilogue operands first
+        // ---- epilogue operands
         if (MODE == kModeRK4 || MODE == kModeDP45 || (MODE == kModeAdjFwd && STAGE < 4)) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ms[c] = S.mstate[c * nn + n];
+            for (int c = 0; c < 3; ++c) ms[c] = ldo(S.mstate + c * nn, on);
         }
         if (MODE == kModeRK4 && STAGE > 1) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ac[c] = S.acc[c * nn + n];
+            for (int c = 0; c < 3; ++c) ac[c] = ldo(S.acc + c * nn, on);
         }
         if (MODE == kModeDP45) {
 #pragma unroll
             for (int j = 0; j < NK; ++j)
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    kk[j][c] = (j < STAGE - 1 && dp_w(STAGE, j + 1) != 0.0) ? S.k[j][c * nn + n] : 0.f;
+                    kk[j][c] = (j < STAGE - 1 && dp_w(STAGE, j + 1) != 0.0) ? ldo(S.k[j] + c * nn, on) : 0.f;
         }
         // ---- per-node coefficients
-        const float im = P.inv_mass[n];
+        const float im = ldo(P.inv_mass, on);
         float gp = 0.f, al = 0.f;
         if (MODE != kModeField) {
-            gp = P.gp_n[n];
-            al = P.alpha_n[n];
+            gp = ldo(P.gp_n, on);
+            al = ldo(P.alpha_n, on);
         }
-        // ---- neighbourhood of m
-        const int x = (int)(n % P.NX);
-        const long long r = n / P.NX;
-        const int y = (int)(r % P.NY);
-        const int z = (int)(r / P.NY);
-        const long long sy = P.NX, sz = (long long)P.NX * P.NY;
-        const float *__restrict__ in = S.in;
+        // ---- neighbourhood of m at clamped indices (a neighbour outside the
+        // mesh only enters through cells outside it, whose weight is zero)
+        const int NX = P.NX, NY = P.NY;
+        const int x = (int)(n % (unsigned)NX);
+        const unsigned r = n / (unsigned)NX;
+        const int y = (int)(r % (unsigned)NY);
+        const int z = (int)(r / (unsigned)NY);
+        unsigned xo[3], ro[9];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) xo[d] = 4u * (unsigned)min(max(x + d - 1, 0), NX - 1);
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+                ro[dz * 3 + dy] = 4u * ((unsigned)min(max(z + dz - 1, 0), P.NZ - 1) * (unsigned)NY +
+                                        (unsigned)min(max(y + dy - 1, 0), NY - 1)) * (unsigned)NX;
+        const float *in0 = S.in, *in1 = S.in + nn, *in2 = S.in + 2 * nn;
         float v[27][3];
 #pragma unroll
-        for (int dz = -1; dz <= 1; ++dz)
-#pragma unroll
-            for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int k = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-                    const bool ok = x + dx >= 0 && x + dx < P.NX && y + dy >= 0 && y + dy < P.NY &&
-                                    z + dz >= 0 && z + dz < P.NZ;
-                    const long long nb = n + dz * sz + dy * sy + dx;
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) v[k][c] = ok ? in[c * nn + nb] : 0.f;
-                }
+        for (int k = 0; k < 27; ++k) {
+            const unsigned o = ro[k / 3] + xo[k % 3];
+            v[k][0] = ldo(in0, o);
+            v[k][1] = ldo(in1, o);
+            v[k][2] = ldo(in2, o);
+        }
         // ---- the 8 cells around the node, q = i1 + 2 i2 + 4 i3 for the cell
-        // (x - i1, y - i2, z - i3).  A cell outside the mesh is read at a
-        // clamped index and weighted by zero: no branch separates the loads,
-        // so they are all in flight together with the neighbourhood above.
-        long long ci[8];
+        // (x - i1, y - i2, z - i3), at clamped indices with weight cw = 0
+        // outside the mesh
+        unsigned co[8];
         float cw[8];
         float4 cp[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int cx = x - (q & 1), cy = y - ((q >> 1) & 1), cz = z - (q >> 2);
             const bool inside = cx >= 0 && cx < P.N1 && cy >= 0 && cy < P.N2 && cz >= 0 && cz < P.N3;
-            ci[q] = ((long long)min(max(cz, 0), P.N3 - 1) * P.N2 + min(max(cy, 0), P.N2 - 1)) * P.N1 +
-                    min(max(cx, 0), P.N1 - 1);
+            co[q] = 4u * (((unsigned)min(max(cz, 0), P.N3 - 1) * (unsigned)P.N2 +
+                           (unsigned)min(max(cy, 0), P.N2 - 1)) * (unsigned)P.N1 +
+                          (unsigned)min(max(cx, 0), P.N1 - 1));
             cw[q] = inside ? 1.f : 0.f;
-            cp[q] = P.cellP[ci[q]];
+            cp[q] = ldo(P.cellP, 4u * co[q]);
         }
         float r0 = 0.f, r1 = 0.f, r2 = 0.f;
         if (P.src) {
+            const float *s0 = P.src, *s1 = P.src + P.nc, *s2 = P.src + 2 * P.nc;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                r0 += cw[q] * P.src[ci[q]];
-                r1 += cw[q] * P.src[P.nc + ci[q]];
-                r2 += cw[q] * P.src[2 * P.nc + ci[q]];
+                r0 += cw[q] * ldo(s0, co[q]);
+                r1 += cw[q] * ldo(s1, co[q]);
+                r2 += cw[q] * ldo(s2, co[q]);
             }
         }
         if (P.wdrive) {
             const float sdrive = (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
             float wd = 0.f;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) wd += cw[q] * P.wdrive[ci[q]];
+            for (int q = 0; q < 8; ++q) wd += cw[q] * ldo(P.wdrive, co[q]);
             wd *= sdrive;
             r0 += wd * P.damp[0];
             r1 += wd * P.damp[1];
@@ -219,32 +252,44 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         const bool ex = P.terms & NM_T_EXCHANGE;
         const bool an = (P.terms & NM_T_ANIS) != 0;
         float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+        // cp = {2A carrying the sign of Ku, u = sqrt|Ku| e}
+        float a2[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int i1 = q & 1, i2 = (q >> 1) & 1, i3 = q >> 2;
-            // cp = {2A carrying the sign of Ku, u = sqrt|Ku| e}
-            const float a2 = cw[q] * fabsf(cp[q].x);
-            const float sg = signbit(cp[q].x) ? -cw[q] : cw[q];
-            float sp = 0.f;
+        for (int q = 0; q < 8; ++q) a2[q] = cw[q] * fabsf(cp[q].x);
+        if (ex) {
 #pragma unroll
-            for (int b3 = 0; b3 < 2; ++b3)
+            for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
-                for (int b2 = 0; b2 < 2; ++b2)
+                for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-                    for (int b1 = 0; b1 < 2; ++b1) {
-                        const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
-                        const int k = (b3 - i3 + 1) * 9 + (b2 - i2 + 1) * 3 + (b1 - i1 + 1);
-                        if (ex && mask != 0) {
-                            const float w = a2 * P.Kp[mask];
-                            g0 += w * (v[k][0] - mn[0]);
-                            g1 += w * (v[k][1] - mn[1]);
-                            g2 += w * (v[k][2] - mn[2]);
-                        }
-                        if (an) sp += P.Mp[mask] * (v[k][0] * cp[q].y + v[k][1] * cp[q].z + v[k][2] * cp[q].w);
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        if (dx == 0 && dy == 0 && dz == 0) continue;
+                        float as = 0.f;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            if (shares(dx, q & 1) && shares(dy, (q >> 1) & 1) && shares(dz, q >> 2)) as += a2[q];
+                        const int mask = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2);
+                        const int k = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                        const float w = as * P.Kp[mask];
+                        g0 += w * (v[k][0] - mn[0]);
+                        g1 += w * (v[k][1] - mn[1]);
+                        g2 += w * (v[k][2] - mn[2]);
                     }
-            if (an) {
+        }
+        if (an) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int i1 = q & 1, i2 = (q >> 1) & 1, i3 = q >> 2;
+                float sp = 0.f;
+#pragma unroll
+                for (int b = 0; b < 8; ++b) {
+                    const int b1 = b & 1, b2 = (b >> 1) & 1, b3 = b >> 2;
+                    const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
+                    const int k = (b3 - i3 + 1) * 9 + (b2 - i2 + 1) * 3 + (b1 - i1 + 1);
+                    sp += P.Mp[mask] * (v[k][0] * cp[q].y + v[k][1] * cp[q].z + v[k][2] * cp[q].w);
+                }
                 // -2 Ku e (sum M m . e) = -2 sign(Ku) u (sum M m . u)
-                const float f2 = 2.f * sg * sp;
+                const float f2 = signbit(cp[q].x) ? -2.f * cw[q] * sp : 2.f * cw[q] * sp;
                 g0 -= f2 * cp[q].y;
                 g1 -= f2 * cp[q].z;
                 g2 -= f2 * cp[q].w;
@@ -255,43 +300,41 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (MODE != kModeField) llg_rhs(mn, H, gp, al, f);
         if (MODE == kModeField) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) S.out[c * nn + n] = H[c];
+            for (int c = 0; c < 3; ++c) sto(S.out + c * nn, on, H[c]);
         } else if (MODE == kModeAdjFwd) {
             // H(y_s) for the reverse sweep, y_{s+1} = m + c_{s+1} dt f_s
             const float cy = (float)(dt * (STAGE == 3 ? 1.0 : 0.5));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                S.out[c * nn + n] = H[c];
-                if (STAGE < 4) S.y_next[c * nn + n] = ms[c] + cy * f[c];
+                sto(S.out + c * nn, on, H[c]);
+                if (STAGE < 4) sto(S.y_next + c * nn, on, ms[c] + cy * f[c]);
             }
         } else if (MODE == kModeRhs) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) S.out[c * nn + n] = f[c];
+            for (int c = 0; c < 3; ++c) sto(S.out + c * nn, on, f[c]);
         } else if (MODE == kModeRK4) {
             const float cy = (float)(dt * (STAGE == 3 ? 1.0 : 0.5));
             const float c6 = (float)(dt / 6.0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const long long i = c * nn + n;
                 if (STAGE == 4) {
-                    S.mstate[i] = ms[c] + c6 * (ac[c] + f[c]);
+                    sto(S.mstate + c * nn, on, ms[c] + c6 * (ac[c] + f[c]));
                 } else {
-                    S.acc[i] = STAGE == 1 ? f[c] : ac[c] + 2.f * f[c];
-                    S.y_next[i] = ms[c] + cy * f[c];
+                    sto(S.acc + c * nn, on, STAGE == 1 ? f[c] : ac[c] + 2.f * f[c]);
+                    sto(S.y_next + c * nn, on, ms[c] + cy * f[c]);
                 }
             }
         } else {  // DP45: store k_s, then y_{s+1} or (s = 7) the scaled error
             float fn2 = 0.f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const long long i = c * nn + n;
-                S.k[STAGE - 1][i] = f[c];
+                sto(S.k[STAGE - 1] + c * nn, on, f[c]);
                 float acc = (float)(dt * dp_w(STAGE, STAGE)) * f[c];
 #pragma unroll
                 for (int j = 0; j < STAGE - 1; ++j)
                     if (dp_w(STAGE, j + 1) != 0.0) acc += (float)(dt * dp_w(STAGE, j + 1)) * kk[j][c];
                 if (STAGE < 7) {
-                    S.y_next[i] = ms[c] + acc;
+                    sto(S.y_next + c * nn, on, ms[c] + acc);
                 } else {
                     const float yn = mn[c];
                     const double sct = C->atol + C->rtol * fmax(fabs((double)ms[c]), fabs((double)yn));
