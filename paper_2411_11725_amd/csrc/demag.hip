@@ -18,7 +18,13 @@
 // every pass reads and writes whole column tiles in place, so no transposes
 // are needed and loads / stores of a tile are contiguous along x.
 // The tensor carries the 1/(P1 P2 P3) normalisation of the inverse transform.
+// Transforms: the x passes sweep radix-8/4/2 Stockham passes through LDS
+// (fft_engine.h); the y passes and the z convolution hold their pencils in
+// registers and trade values once through LDS (fft2 in fft_reg.h), the z
+// convolution applying the tensor in registers between its two transforms
+// (P3 >= 512 falls back to the LDS sweep, as does the film convolution).
 #include "fft_engine.h"
+#include "fft_reg.h"
 
 namespace nm {
 
@@ -53,14 +59,14 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
     const long long nn = (long long)NX * NY * (N3 + 1);
-    // rows past the plane's end and cells past N1 are read at clamped
-    // addresses and zeroed by a select: a branch around a load would make
-    // every load a separate memory round trip
-    static_assert((RB * L) % 256 == 0, "whole iterations");
-#pragma unroll
-    for (int i = 0; i < RB * L / 256; ++i) {
-        const int it = tid + i * 256;
-        const int rb = it / L, n = it - (it / L) * L;
+    // Only the first L / 2 complex elements of a row hold cells (N1 <= P1 / 2);
+    // the upper half is zero padding.  One thread per (row, element) of the
+    // data half: RB L / 2 = 256.  Rows past the plane's end and cells past N1
+    // are read at clamped addresses and zeroed by a factor (a branch around a
+    // load would make each load its own memory round trip).
+    static_assert(RB * L / 2 == 256, "one data element per thread");
+    {
+        const int rb = tid / (L / 2), n = tid - (tid / (L / 2)) * (L / 2);
         const bool rok = rb < nrows;
         const int y = y0 + min(rb, nrows - 1);
         float2 v[3];
@@ -83,7 +89,10 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) s[(c * RB + rb) * L + n] = v[c];
+        for (int c = 0; c < 3; ++c) {
+            s[(c * RB + rb) * L + n] = v[c];
+            s[(c * RB + rb) * L + n + L / 2] = make_float2(0.f, 0.f);
+        }
     }
     load_twiddles<2 * L, 256>(tl, tw, tid);
     __syncthreads();
@@ -123,10 +132,8 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
     const long long nc = (long long)N1 * N2 * N3;
     static_assert((RB * L) % 256 == 0, "whole iterations");
     constexpr int NI = RB * L / 256;
-    // thread i-th item: row rb, frequency k on input, cells 2k, 2k + 1 on output
+    // input items (row rb, frequency k): NI per thread
     float2 xk[NI][3], xc[NI][3];
-    float wv[NI][2], av[NI][2][3];
-    long long oi[NI][2];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
         const int it = tid + i * 256;
@@ -141,15 +148,25 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
             xk[i][c] = keep(rowp[k], rok);
             xc[i][c] = keep(cconj(rowp[L - k]), rok);
         }
-        // output weights and static fields, at clamped cells
-        const long long cb = ((long long)z * N2 + y) * N1;
-        oi[i][0] = cb + min(2 * k, N1 - 1);
-        oi[i][1] = cb + min(2 * k + 1, N1 - 1);
+    }
+    // output item (row ro, element no -> cells 2 no, 2 no + 1): only the first
+    // L / 2 elements of a row are cells (N1 <= P1 / 2), one per thread; its
+    // weights and static fields are fetched now, at clamped cells
+    static_assert(RB * L / 2 == 256, "one output element per thread");
+    const int ro = tid / (L / 2), no = tid - (tid / (L / 2)) * (L / 2);
+    const bool ook = row0 + ro < rows;
+    long long oi[2];
+    float wv[2], av[2][3];
+    {
+        const int rc = min(row0 + ro, rows - 1);
+        const long long cb = ((long long)(rc / N2) * N2 + rc % N2) * N1;
+        oi[0] = cb + min(2 * no, N1 - 1);
+        oi[1] = cb + min(2 * no + 1, N1 - 1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            wv[i][h] = src_mode > 0 ? wc[oi[i][h]] : 1.f;
+            wv[h] = src_mode > 0 ? wc[oi[h]] : 1.f;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) av[i][h][c] = src_mode == 2 ? wstat[c * nc + oi[i][h]] : 0.f;
+            for (int c = 0; c < 3; ++c) av[h][c] = src_mode == 2 ? wstat[c * nc + oi[h]] : 0.f;
         }
     }
     load_twiddles<2 * L, 256>(tl, tw, tid);
@@ -171,61 +188,80 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
     }
     __syncthreads();
     lds_fft<L, 1, NP, 256, false, 2 * L>(s, tl, tid);
+    if (!ook) return;
+    const int x0 = 2 * no;
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const int it = tid + i * 256;
-        const int rb = it / L, n = it - (it / L) * L;
-        if (row0 + rb >= rows) continue;
-        const int x0 = 2 * n;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float2 v = s[(c * RB + rb) * L + n];
-            if (x0 < N1) hd[c * nc + oi[i][0]] = wv[i][0] * v.x + av[i][0][c];
-            if (x0 + 1 < N1) hd[c * nc + oi[i][1]] = wv[i][1] * v.y + av[i][1][c];
-        }
+    for (int c = 0; c < 3; ++c) {
+        const float2 v = s[(c * RB + ro) * L + no];
+        if (x0 < N1) hd[c * nc + oi[0]] = wv[0] * v.x + av[0][c];
+        if (x0 + 1 < N1) hd[c * nc + oi[1]] = wv[1] * v.y + av[1][c];
     }
 }
 
-// ------------------------------------------------------- y pass (3D, 1 comp)
-// columns (z < N3, kx < K1) at pitch KP; elements along y at stride KP
-template <int L, int DIR, int TB>
+// ----------------------------------------- y pass, register FFT form
+// NPB columns per block, T threads per column (fft2 split of L).  Forward:
+// the N2 <= L / 2 data rows in, all L rows out.  Inverse: all L rows in, the
+// N2 data rows out.
+template <int L, int DIR>
 __global__ void __launch_bounds__(256)
-k_ypass(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int K1, int KP, int n_in,
-        int n_out, const Ctrl *__restrict__ ctrl) {
-    __shared__ float2 s[L * TB];
-    __shared__ float2 tl[L / 2 + 1];
+k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int N2, int K1, int KP,
+          const Ctrl *__restrict__ ctrl) {
+    constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
+    constexpr int NPB = 256 / TT, E = L / TT;
+    __shared__ float2 sh[TT > 1 ? L * NPB : 1];
+    __shared__ float2 tl[L];
     if (ctrl && ctrl->done) return;
-    const int tid = threadIdx.x;
-    const int ncols = N3 * KP;
-    const int col0 = blockIdx.x * TB;
-    float2 *base = spec + (long long)blockIdx.y * N3 * L * KP;
-    // 256 is a multiple of TB: every thread keeps one column
-    static_assert(256 % TB == 0, "tile width must divide the block");
-    const int b = tid % TB, e0 = tid / TB;
-    constexpr int ESTEP = 256 / TB;
-    constexpr int NE = L / ESTEP;
-    static_assert(L % ESTEP == 0, "whole columns per thread");
-    const int col = col0 + b;
+    const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
+    const int col = blockIdx.x * NPB + b;
     const int zc = col / KP, kx = col - zc * KP;
-    const bool cok = col < ncols && kx < K1;   // pad columns are never written
-    // invalid columns and rows past n_in are read at clamped addresses and
-    // zeroed by a select, so all NE loads are in flight together
-    float2 *cbase = base + (long long)zc * L * KP + kx;
-    const float2 *lbase = cok ? cbase : base;
-    float2 v[NE];
+    const bool valid = col < N3 * KP && kx < K1;
+    float2 *cbase = spec + (long long)blockIdx.y * N3 * L * KP + (long long)zc * L * KP + kx;
+    const float2 *lbase = valid ? cbase : spec + (long long)blockIdx.y * N3 * L * KP;
+    float2 v[1][E];
+    if constexpr (DIR < 0) {
+        // rows (j + T a) + L1 n2; only n2 < L2 / 2 can hold data
+        constexpr int A = L1 / TT;
 #pragma unroll
-    for (int i = 0; i < NE; ++i) {
-        const int e = e0 + i * ESTEP;
-        const float2 t = lbase[(long long)min(e, n_in - 1) * KP];
-        v[i] = keep(t, cok && e < n_in);
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int n2 = 0; n2 < L2; ++n2) {
+                float2 x = make_float2(0.f, 0.f);
+                if (n2 < L2 / 2) {
+                    const int y = j + TT * a + L1 * n2;
+                    x = keep(lbase[(long long)min(y, N2 - 1) * KP], valid && y < N2);
+                }
+                v[0][a * L2 + n2] = x;
+            }
+        load_twiddles_full<L, 256>(tl, tw, tid);
+        fft2<L1, L2, -1, 1, NPB, E>(v, sh, tl, j, b);
+        if (!valid) return;
+        // rows (j + T q) + L2 k1
+        constexpr int Q = L2 / TT;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1) cbase[(long long)(j + TT * q + L2 * k1) * KP] = v[0][q * L1 + k1];
+    } else {
+        // rows (j + T q) + L2 k1 in (the forward output layout)
+        constexpr int Q = L2 / TT;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1)
+                v[0][q * L1 + k1] = keep(lbase[(long long)(j + TT * q + L2 * k1) * KP], valid);
+        load_twiddles_full<L, 256>(tl, tw, tid);
+        fft2<L2, L1, 1, 1, NPB, E>(v, sh, tl, j, b);
+        if (!valid) return;
+        // rows (j + T a) + L1 n2 out; only n2 < L2 / 2 can be data rows
+        constexpr int A = L1 / TT;
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int n2 = 0; n2 < L2 / 2; ++n2) {
+                const int y = j + TT * a + L1 * n2;
+                if (y < N2) cbase[(long long)y * KP] = v[0][a * L2 + n2];
+            }
     }
-    load_twiddles<L, 256>(tl, tw, tid);
-#pragma unroll
-    for (int i = 0; i < NE; ++i) s[(e0 + i * ESTEP) * TB + b] = v[i];
-    __syncthreads();
-    lds_fft<L, DIR, TB, 256, true, L>(s, tl, tid);
-    if (cok)
-        for (int e = e0; e < n_out; e += ESTEP) cbase[(long long)e * KP] = s[e * TB + b];
 }
 
 // ------------------------------------------- k-space product of one element
@@ -343,6 +379,95 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     }
 }
 
+// ----------------------- z forward + product + z inverse, register FFT form
+// NPB columns per block, T threads per column (fft2 split of L), all three
+// components of a column in the same thread, so the product with the tensor
+// happens in registers between the forward and the inverse transform.  Only
+// z < L / 2 can hold data (P3 >= 2 N3), so half of the inputs are known zeros
+// and half of the outputs are never stored.
+template <int L>
+__global__ void __launch_bounds__(256)
+k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
+          int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
+    constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
+    constexpr int NPB = 256 / TT, E = L / TT, A = L1 / TT, Q = L2 / TT;
+    constexpr int NCX = E <= 8 ? 3 : 1;   // components per LDS exchange
+    __shared__ float2 sh[TT > 1 ? NCX * L * NPB : 1];
+    __shared__ float2 tl[L];
+    if (ctrl && ctrl->done) return;
+    const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
+    const int col = blockIdx.x * NPB + b;
+    const bool valid = col < P2 * KP && col % KP < K1;
+    const int colc = valid ? col : 0;   // pad / past-the-end lanes read column 0
+    const long long plane = (long long)P2 * KP;
+    // inputs z = (j + T a) + L1 n2, nonzero only for n2 < L2 / 2
+    float2 v[3][E];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int n2 = 0; n2 < L2; ++n2) {
+                float2 x = make_float2(0.f, 0.f);
+                if (n2 < L2 / 2) {
+                    const int z = j + TT * a + L1 * n2;
+                    x = keep(spec[((long long)c * N3 + min(z, N3 - 1)) * plane + colc], valid && z < N3);
+                }
+                v[c][a * L2 + n2] = x;
+            }
+    // tensor entries of this thread's frequencies kz = (j + T q) + L2 k1
+    // (kz and L - kz share the stored entry, xz and yz change sign)
+    const int ky = colc / KP, kx = colc - ky * KP;
+    const bool fy = ky > P2 / 2;
+    const int kyr = fy ? P2 - ky : ky;
+    const long long tstride = (long long)P3h * P2h * KP;
+    auto tensor_at = [&](int i) {
+        const int kz = j + TT * (i / L1) + L2 * (i % L1);
+        const int kzr = kz <= L / 2 ? kz : L - kz;
+        return tensor_load(T, tstride, ((long long)kzr * P2h + kyr) * KP + kx, fy ? -1.f : 1.f, true);
+    };
+    auto apply = [&](int i, const Tensor6 &N) {
+        const int kz = j + TT * (i / L1) + L2 * (i % L1);
+        tensor_apply(N, kz <= L / 2 ? 1.f : -1.f, v[0][i], v[1][i], v[2][i]);
+    };
+    constexpr bool PREFETCH = E <= 8;   // registers allow holding all E entries
+    Tensor6 Nt[PREFETCH ? E : 1];
+    if constexpr (PREFETCH) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) Nt[i] = tensor_at(i);
+    }
+    load_twiddles_full<L, 256>(tl, tw, tid);
+    if constexpr (NCX == 3) {
+        fft2<L1, L2, -1, 3, NPB, E>(v, sh, tl, j, b);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            fft2<L1, L2, -1, 1, NPB, E>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+        if constexpr (PREFETCH) apply(i, Nt[i]);
+        else apply(i, tensor_at(i));
+    }
+    if constexpr (NCX == 3) {
+        fft2<L2, L1, 1, 3, NPB, E>(v, sh, tl, j, b);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            fft2<L2, L1, 1, 1, NPB, E>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
+    }
+    if (!valid) return;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+            for (int n2 = 0; n2 < L2 / 2; ++n2) {
+                const int z = j + TT * a + L1 * n2;
+                if (z < N3) spec[((long long)c * N3 + z) * plane + col] = v[c][a * L2 + n2];
+            }
+}
+
 // ------------------------------------ y forward + product + y inverse (N3 = 1)
 template <int L, int TB>
 __global__ void __launch_bounds__(256)
@@ -414,9 +539,8 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
 }
 
 // --------------------------------------------------------------- dispatch
-// column tiles: one component per block in the y passes (L * TB = 4096
-// elements), three in the fused passes (3 L TB <= 4096 elements)
-__host__ __device__ constexpr int tb_single(int L) { return L >= 1024 ? 4 : (4096 / L > 64 ? 64 : 4096 / L); }
+// column tiles of the LDS-sweep convolutions: three components per block,
+// 3 L TB <= 4096 elements
 __host__ __device__ constexpr int tb_triple(int L) { return L <= 16 ? 64 : 1024 / L; }
 
 template <int L>
@@ -433,19 +557,24 @@ static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl, int src
               tw, m->N1, m->N2, m->N3, m->P2, m->KP, m->wc, m->wstat, src_mode, ctrl);
 }
 template <int L, int DIR>
-static void launch_y(nm_mesh *m, const float2 *tw, int n_in, int n_out, const Ctrl *ctrl) {
-    constexpr int TB = tb_single(L);
+static void launch_y(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     const int ncols = m->N3 * m->KP;
-    NM_LAUNCH(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV, (k_ypass<L, DIR, TB>),
-              dim3((ncols + TB - 1) / TB, 3), dim3(256), 0, m->spec, tw, m->N3, m->K1, m->KP, n_in, n_out,
-              ctrl);
+    constexpr int NPB = 256 / fft2_threads(L);
+    NM_LAUNCH(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV, (k_ypass_r<L, DIR>), dim3((ncols + NPB - 1) / NPB, 3),
+              dim3(256), 0, m->spec, tw, m->N3, m->N2, m->K1, m->KP, ctrl);
 }
 template <int L>
 static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
-    constexpr int TB = tb_triple(L);
     const int ncols = m->P2 * m->KP;
-    NM_LAUNCH(m, NM_PROF_CONV, (k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->spec,
-              m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
+    if constexpr (L <= 256) {
+        constexpr int NPB = 256 / fft2_threads(L);
+        NM_LAUNCH(m, NM_PROF_CONV, (k_zconv_r<L>), dim3((ncols + NPB - 1) / NPB), dim3(256), 0, m->spec,
+                  m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
+    } else {
+        constexpr int TB = tb_triple(L);
+        NM_LAUNCH(m, NM_PROF_CONV, (k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->spec,
+                  m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
+    }
 }
 template <int L>
 static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
@@ -485,11 +614,11 @@ static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
 
 template <int L>
 static void launch_y_fwd(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
-    launch_y<L, -1>(m, tw, m->N2, L, ctrl);
+    launch_y<L, -1>(m, tw, ctrl);
 }
 template <int L>
 static void launch_y_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
-    launch_y<L, 1>(m, tw, L, m->N2, ctrl);
+    launch_y<L, 1>(m, tw, ctrl);
 }
 
 static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl, int src_mode) {
