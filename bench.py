@@ -114,6 +114,70 @@ def cpu_baseline(p, terms_mask, evals=4):
                       "(numpy, one thread; %.1f s tensor set-up excluded)" % (evals, *p["n"], setup)}
 
 
+def serving_bench(B, synth, count, t_end, nmax, max_active):
+    """Continuous-batching server against a plain one-at-a-time loop on the
+    same Poisson request stream (arrival times honoured by both): solves/s and
+    p50 / p99 latency (completion minus arrival), and the largest difference
+    between the two sets of final states."""
+    import numpy as np
+    import torch
+
+    reqs = synth.serving_requests(count, nmax=nmax)
+    nns = [(q["n"][0] + 1) * (q["n"][1] + 1) * (q["n"][2] + 1) for _, q in reqs]
+    # batched: each request is submitted when it arrives, results polled after
+    srv = B.nm_server_create(max_active=max_active, n_streams=4, attempts_per_launch=8)
+    outs_b, lat_b = [], []
+    try:
+        t0 = B.nm_server_clock()
+        tickets = []
+        for (ta, q) in reqs:
+            while B.nm_server_clock() - t0 < ta:
+                time.sleep(2e-4)
+            tickets.append(B.nm_serve_submit(srv, q, t_end=t_end))
+        t_last = t0
+        for tk, nn in zip(tickets, nns):
+            m = np.empty(3 * nn, dtype=np.float32)
+            r = B.nm_serve_poll(srv, tk, timeout_ms=600000, m_out=m)
+            if r is None or r.status != B.NM_OK:
+                raise RuntimeError("served solve failed: %s" % (None if r is None else r.status))
+            outs_b.append(m)
+            lat_b.append(r.t_done - r.t_submit)
+            t_last = max(t_last, r.t_done)
+        wall_b = t_last - t0
+        print("serving: batched %d solves in %.2f s" % (count, wall_b), file=sys.stderr, flush=True)
+    finally:
+        B.nm_server_destroy(srv)
+    # plain loop: one mesh at a time, created, stepped to t_end and read back
+    lat_p, diff = [], 0.0
+    t0 = time.perf_counter()
+    for (ta, q), mb in zip(reqs, outs_b):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(2e-4)
+        mesh = B.mesh_from_problem(q, device="cuda:0")
+        m = torch.as_tensor(q["m0"], device="cuda:0").contiguous()
+        clk = B.nm_clock(0.0, 1e-14, 0, 0, 0, 0.0)
+        B.nm_llg_step(mesh, m, clk, B.NM_DP45, B.NM_T_ALL, t_end=t_end)
+        mp = m.cpu().numpy().ravel()
+        B.nm_mesh_destroy(mesh)
+        lat_p.append(time.perf_counter() - t0 - ta)
+        diff = max(diff, float(np.abs(mp - mb).max()))
+    wall_p = time.perf_counter() - t0
+    print("serving: plain loop %d solves in %.2f s" % (count, wall_p), file=sys.stderr, flush=True)
+    pct = lambda a, q: float(np.percentile(np.asarray(a), q))
+    cells = [q["n"][0] * q["n"][1] * q["n"][2] for _, q in reqs]
+    return {
+        "stream": "%d solves, Poisson arrivals at 200/s, nx, ny log-uniform in [32, %d], nz in 1..8, "
+                  "3 nm cells, DP45 rtol 1e-5 to t = %.2g s" % (count, nmax, t_end),
+        "cells_mean": float(np.mean(cells)), "max_active": max_active,
+        "batched": {"solves_per_s": count / wall_b, "p50_s": pct(lat_b, 50), "p99_s": pct(lat_b, 99),
+                    "wall_s": wall_b},
+        "plain_loop": {"solves_per_s": count / wall_p, "p50_s": pct(lat_p, 50), "p99_s": pct(lat_p, 99),
+                       "wall_s": wall_p},
+        "speedup": wall_p / wall_b,
+        "max_abs_diff_m": diff,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,7 +185,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="block", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-count", type=int, default=48,
+                    help="solves in the serving stream (0: skip the serving measurement)")
+    ap.add_argument("--serve-nmax", type=int, default=256)
+    ap.add_argument("--serve-tend", type=float, default=0.2e-9)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run 5 plain device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+
+        n = 64 * 1024 * 1024
+        a = torch.ones(n, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: the hot path is a single-GPU build "
               "(multi-GPU sharding is design only); use --gpus 1", file=sys.stderr)
@@ -156,6 +237,7 @@ def main():
     B.nm_llg_step(mesh, m, clk, B.NM_DP45, terms, t_end=t_cap, max_steps=args.steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print("timed region: %.3f s" % elapsed, file=sys.stderr, flush=True)
     rhs = clk.rhs_evals - rhs0
     steps = clk.accepted - acc0
     value = nc * rhs / elapsed
@@ -193,6 +275,8 @@ def main():
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": kernels,
     }
+    if args.serve_count > 0:
+        out["serving"] = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax, 16)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, terms)
     print(json.dumps(out))
