@@ -114,7 +114,7 @@ def cpu_baseline(p, terms_mask, evals=4):
                       "(numpy, one thread; %.1f s tensor set-up excluded)" % (evals, *p["n"], setup)}
 
 
-def serving_bench(B, synth, count, t_end, nmax, max_active):
+def serving_bench(B, synth, count, t_end, nmax, max_active, n_streams=4, attempts=8):
     """Continuous-batching server against a plain one-at-a-time loop on the
     same Poisson request stream (arrival times honoured by both): solves/s and
     p50 / p99 latency (completion minus arrival), and the largest difference
@@ -125,7 +125,7 @@ def serving_bench(B, synth, count, t_end, nmax, max_active):
     reqs = synth.serving_requests(count, nmax=nmax)
     nns = [(q["n"][0] + 1) * (q["n"][1] + 1) * (q["n"][2] + 1) for _, q in reqs]
     # batched: each request is submitted when it arrives, results polled after
-    srv = B.nm_server_create(max_active=max_active, n_streams=4, attempts_per_launch=8)
+    srv = B.nm_server_create(max_active=max_active, n_streams=n_streams, attempts_per_launch=attempts)
     outs_b, lat_b = [], []
     try:
         t0 = B.nm_server_clock()
@@ -168,7 +168,8 @@ def serving_bench(B, synth, count, t_end, nmax, max_active):
     return {
         "stream": "%d solves, Poisson arrivals at 200/s, nx, ny log-uniform in [32, %d], nz in 1..8, "
                   "3 nm cells, DP45 rtol 1e-5 to t = %.2g s" % (count, nmax, t_end),
-        "cells_mean": float(np.mean(cells)), "max_active": max_active,
+        "cells_mean": float(np.mean(cells)), "max_active": max_active, "streams": n_streams,
+        "attempts_per_launch": attempts,
         "batched": {"solves_per_s": count / wall_b, "p50_s": pct(lat_b, 50), "p99_s": pct(lat_b, 99),
                     "wall_s": wall_b},
         "plain_loop": {"solves_per_s": count / wall_p, "p50_s": pct(lat_p, 50), "p99_s": pct(lat_p, 99),
@@ -189,6 +190,10 @@ def main():
                     help="solves in the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serve-nmax", type=int, default=256)
     ap.add_argument("--serve-tend", type=float, default=0.2e-9)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-active", type=int, default=16)
+    ap.add_argument("--serve-attempts", type=int, default=8)
+    ap.add_argument("--serve-only", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 plain device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -213,6 +218,11 @@ def main():
     from paper_2411_11725_amd import binding as B
     from paper_2411_11725_amd import synth
 
+    if args.serve_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
+                                                   args.serve_active, args.serve_streams, args.serve_attempts)}))
+        return
     W = WORKLOADS[args.workload]
     p = getattr(synth, W["make"])()
     tmask = {"exchange": B.NM_T_EXCHANGE, "demag": B.NM_T_DEMAG, "anisotropy": B.NM_T_ANIS,
@@ -276,7 +286,8 @@ def main():
         "kernels": kernels,
     }
     if args.serve_count > 0:
-        out["serving"] = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax, 16)
+        out["serving"] = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
+                                       args.serve_active, args.serve_streams, args.serve_attempts)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, terms)
     print(json.dumps(out))

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnm.so")
-SOURCES = ["adjoint.hip", "api.hip", "demag.hip", "newell.hip", "profile.hip", "serve.hip",
+SOURCES = ["adjoint.hip", "api.hip", "demag.hip", "newell.hip", "pool.hip", "profile.hip", "serve.hip",
            "stencil.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

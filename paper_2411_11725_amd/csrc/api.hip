@@ -157,17 +157,18 @@ static void free_mesh(nm_mesh *m) {
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
                     m->ctrl, m->partials, m->ered, m->cellP, m->wstat, m->wdrive};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
-    for (int j = 0; j < 7; ++j)
-        if (m->k[j]) (void)hipFree(m->k[j]);
-    if (m->ctrl_host) (void)hipHostFree(m->ctrl_host);
+    for (void *p : ptrs) dev_free(p, m->pool);
+    for (int j = 0; j < 7; ++j) dev_free(m->k[j], m->pool);
+    host_free(m->ctrl_host, m->pool);
     delete m;
 }
 
+// release a mesh whose stream work is known to be complete (no stream wait)
+void nm::mesh_release(nm_mesh *m) { free_mesh(m); }
+
 template <typename T>
-static hipError_t dalloc(T **p, long long count) {
-    return hipMalloc((void **)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+static hipError_t dalloc(nm_mesh *m, T **p, long long count) {
+    return dev_alloc((void **)p, sizeof(T) * (size_t)(count > 0 ? count : 1), m->pool);
 }
 
 extern "C" size_t nm_mesh_footprint_bytes(const nm_mesh_desc *desc, int integrator) {
@@ -237,34 +238,35 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
         m->Mp[mask] = (float)(mm[0] * mm[1] * mm[2]);
     }
 
+    m->pool = thread_pool();
     hipError_t e = hipGetDevice(&m->device);
     // the per-device twiddle table is built here, never inside a graph capture
     if (e == hipSuccess && !twiddles(m->device)) e = hipErrorOutOfMemory;
     const long long nc = s.nc, nn = s.nn;
-    if (e == hipSuccess) e = dalloc(&m->Ms, nc);
-    if (e == hipSuccess) e = dalloc(&m->A2, nc);
-    if (e == hipSuccess) e = dalloc(&m->wc, nc);
-    if (e == hipSuccess) e = dalloc(&m->h_cell, 3 * nc);
-    if (e == hipSuccess) e = dalloc(&m->cellP, nc);
-    if (e == hipSuccess) e = dalloc(&m->wstat, 3 * nc);
-    if (e == hipSuccess && m->has_drive) e = dalloc(&m->wdrive, nc);
-    if (e == hipSuccess && m->has_anis) e = dalloc(&m->Ku, nc);
-    if (e == hipSuccess && m->has_anis) e = dalloc(&m->easy, 3 * nc);
-    if (e == hipSuccess && m->has_drive) e = dalloc(&m->drive_mask, nc);
-    if (e == hipSuccess) e = dalloc(&m->inv_mass, nn);
-    if (e == hipSuccess) e = dalloc(&m->alpha_n, nn);
-    if (e == hipSuccess) e = dalloc(&m->gp_n, nn);
-    if (e == hipSuccess) e = dalloc(&m->spec, s.spec);
-    if (e == hipSuccess) e = dalloc(&m->tensor, s.tensor);
-    if (e == hipSuccess) e = dalloc(&m->hd, 3 * nc);
-    if (e == hipSuccess) e = dalloc(&m->y[0], 3 * nn);
-    if (e == hipSuccess) e = dalloc(&m->y[1], 3 * nn);
-    if (e == hipSuccess) e = dalloc(&m->acc, 3 * nn);
-    for (int j = 0; j < 7 && e == hipSuccess; ++j) e = dalloc(&m->k[j], 3 * nn);
-    if (e == hipSuccess) e = dalloc(&m->ctrl, 1);
-    if (e == hipSuccess) e = dalloc(&m->partials, s.partials);
-    if (e == hipSuccess) e = dalloc(&m->ered, 4 * s.eblocks + 4);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&m->ctrl_host, sizeof(Ctrl), hipHostMallocDefault);
+    if (e == hipSuccess) e = dalloc(m, &m->Ms, nc);
+    if (e == hipSuccess) e = dalloc(m, &m->A2, nc);
+    if (e == hipSuccess) e = dalloc(m, &m->wc, nc);
+    if (e == hipSuccess) e = dalloc(m, &m->h_cell, 3 * nc);
+    if (e == hipSuccess) e = dalloc(m, &m->cellP, nc);
+    if (e == hipSuccess) e = dalloc(m, &m->wstat, 3 * nc);
+    if (e == hipSuccess && m->has_drive) e = dalloc(m, &m->wdrive, nc);
+    if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->Ku, nc);
+    if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->easy, 3 * nc);
+    if (e == hipSuccess && m->has_drive) e = dalloc(m, &m->drive_mask, nc);
+    if (e == hipSuccess) e = dalloc(m, &m->inv_mass, nn);
+    if (e == hipSuccess) e = dalloc(m, &m->alpha_n, nn);
+    if (e == hipSuccess) e = dalloc(m, &m->gp_n, nn);
+    if (e == hipSuccess) e = dalloc(m, &m->spec, s.spec);
+    if (e == hipSuccess) e = dalloc(m, &m->tensor, s.tensor);
+    if (e == hipSuccess) e = dalloc(m, &m->hd, 3 * nc);
+    if (e == hipSuccess) e = dalloc(m, &m->y[0], 3 * nn);
+    if (e == hipSuccess) e = dalloc(m, &m->y[1], 3 * nn);
+    if (e == hipSuccess) e = dalloc(m, &m->acc, 3 * nn);
+    for (int j = 0; j < 7 && e == hipSuccess; ++j) e = dalloc(m, &m->k[j], 3 * nn);
+    if (e == hipSuccess) e = dalloc(m, &m->ctrl, 1);
+    if (e == hipSuccess) e = dalloc(m, &m->partials, s.partials);
+    if (e == hipSuccess) e = dalloc(m, &m->ered, 4 * s.eblocks + 4);
+    if (e == hipSuccess) e = host_alloc((void **)&m->ctrl_host, sizeof(Ctrl), m->pool);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         set_error(std::string("nm_mesh_create: allocation failed: ") + hipGetErrorString(e));

@@ -232,7 +232,7 @@ static hipError_t make_rules(const double hs[3], TentRules **dev, hipStream_t st
             }
         }
     }
-    hipError_t e = hipMalloc(dev, sizeof(TentRules));
+    hipError_t e = dev_alloc((void **)dev, sizeof(TentRules), thread_pool());
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(*dev, &host, sizeof(TentRules), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -251,7 +251,7 @@ hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], doubl
                        n1, n2, n3, hs[0], hs[1], hs[2], rules, out);
     e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(stream);
-    (void)hipFree(rules);
+    dev_free(rules, thread_pool());
     return e != hipSuccess ? e : e2;
 }
 
@@ -261,7 +261,7 @@ static hipError_t upload_phases(int P, double2 **dev, hipStream_t stream) {
         const double a = 2.0 * kPi * r / P;
         cs[r] = make_double2(std::cos(a), std::sin(a));
     }
-    hipError_t e = hipMalloc(dev, sizeof(double2) * P);
+    hipError_t e = dev_alloc((void **)dev, sizeof(double2) * P, thread_pool());
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(*dev, cs.data(), sizeof(double2) * P, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -277,9 +277,12 @@ hipError_t build_kspace_tensor(nm_mesh *m) {
     const long long sb = 6LL * n3 * m->P2h * m->KP;
     double *octd = nullptr, *A = nullptr, *B = nullptr;
     double2 *c1 = nullptr, *c2 = nullptr, *c3 = nullptr;
-    hipError_t e = hipMalloc(&octd, sizeof(double) * 6 * oct);
-    if (e == hipSuccess) e = hipMalloc(&A, sizeof(double) * sa);
-    if (e == hipSuccess) e = hipMalloc(&B, sizeof(double) * sb);
+    // temporaries from the calling thread's pool, if it has one (no device-wide
+    // wait when they are given back)
+    DevPool *pool = thread_pool();
+    hipError_t e = dev_alloc((void **)&octd, sizeof(double) * 6 * oct, pool);
+    if (e == hipSuccess) e = dev_alloc((void **)&A, sizeof(double) * sa, pool);
+    if (e == hipSuccess) e = dev_alloc((void **)&B, sizeof(double) * sb, pool);
     if (e == hipSuccess) e = upload_phases(m->P1, &c1, m->stream);
     if (e == hipSuccess) e = upload_phases(m->P2, &c2, m->stream);
     if (e == hipSuccess) e = upload_phases(m->P3, &c3, m->stream);
@@ -304,12 +307,7 @@ hipError_t build_kspace_tensor(nm_mesh *m) {
         hipError_t e2 = hipStreamSynchronize(m->stream);
         if (e == hipSuccess) e = e2;
     }
-    (void)hipFree(octd);
-    (void)hipFree(A);
-    (void)hipFree(B);
-    (void)hipFree(c1);
-    (void)hipFree(c2);
-    (void)hipFree(c3);
+    for (void *p : {(void *)octd, (void *)A, (void *)B, (void *)c1, (void *)c2, (void *)c3}) dev_free(p, pool);
     return e;
 }
 

@@ -38,6 +38,17 @@ struct ErrPartial {
 
 struct ProfState;  // per-kernel event timing (measurement only)
 
+// device memory: hipMalloc / hipFree, or a pool (see pool.hip)
+struct DevPool;
+constexpr size_t kPoolHostBlock = 4096;   // pinned host blocks recycled by a pool
+DevPool *pool_create();
+void pool_destroy(DevPool *P);
+void set_thread_pool(DevPool *P);   // allocations of the calling thread come from P
+DevPool *thread_pool();
+hipError_t dev_alloc(void **p, size_t bytes, DevPool *P);
+void dev_free(void *p, DevPool *P);
+hipError_t host_alloc(void **p, size_t bytes, DevPool *P);
+void host_free(void *p, DevPool *P);
 }  // namespace nm
 
 struct nm_mesh {
@@ -51,6 +62,7 @@ struct nm_mesh {
     int64_t n_nodes, n_cells;
     hipStream_t stream;
     int device;
+    nm::DevPool *pool;       // where the buffers came from (NULL: hipMalloc)
 
     // owned material copies (cell arrays) and derived quantities
     float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;
@@ -150,6 +162,7 @@ hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t,
 hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
 hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat, wdrive from the raw copies
+void mesh_release(nm_mesh *m);             // free a mesh whose stream work has completed
 hipError_t launch_rk4_advance(nm_mesh *m);
 
 // stepping building blocks shared by nm_llg_step and the solve server

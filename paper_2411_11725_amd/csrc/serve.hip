@@ -8,9 +8,11 @@
 // attempts each) on one stream of a pool, so the work of many solves is in
 // flight on the GPU at once.  Solves progress independently: a replay is
 // re-issued as soon as the previous one has finished, finished solves leave
-// (freeing their memory) and waiting requests join between replays.  Every
-// solve runs the same kernels on its own buffers, so its result does not
-// depend on what else is in the mix.
+// and waiting requests join between replays.  Device memory of the solves
+// comes from a pool (pool.hip): a finished solve gives its buffers back
+// without hipFree, which would wait for the whole device.  Every solve runs
+// the same kernels on its own buffers, so its result does not depend on what
+// else is in the mix.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -59,6 +61,7 @@ struct nm_server {
     std::vector<hipStream_t> streams;
     int next_stream = 0;
     int device = 0;
+    DevPool *pool = nullptr;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Solve *> pending;
@@ -86,10 +89,11 @@ size_t solve_footprint(const nm_solve_request &r) {
     return base + sizeof(float) * (3 * nn + 3 * nc);   // state + staged parameters
 }
 
-void release(Solve *s) {
-    if (s->mesh) nm_mesh_destroy(s->mesh);
-    if (s->m_dev) (void)hipFree(s->m_dev);
-    if (s->par_dev) (void)hipFree(s->par_dev);
+// give back the resources of a solve whose stream work has completed
+void release(Solve *s, DevPool *pool) {
+    if (s->mesh) mesh_release(s->mesh);
+    dev_free(s->m_dev, pool);
+    dev_free(s->par_dev, pool);
     if (s->ev) (void)hipEventDestroy(s->ev);
     s->mesh = nullptr;
     s->m_dev = s->par_dev = nullptr;
@@ -97,7 +101,8 @@ void release(Solve *s) {
 }
 
 void fail(nm_server *S, Solve *s, int status) {
-    release(s);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);   // rare path: drain before reuse
+    release(s, S->pool);
     s->res.status = status;
     s->res.t_done = now_s();
     std::lock_guard<std::mutex> lk(S->mu);
@@ -112,8 +117,8 @@ bool admit(nm_server *S, Solve *s) {
     const nm_solve_request &r = s->req;
     s->nc = (long long)r.n[0] * r.n[1] * r.n[2];
     s->nn = (long long)(r.n[0] + 1) * (r.n[1] + 1) * (r.n[2] + 1);
-    if (hipMalloc(&s->par_dev, sizeof(float) * 3 * s->nc) != hipSuccess) return false;
-    if (hipMalloc(&s->m_dev, sizeof(float) * 3 * s->nn) != hipSuccess) return false;
+    if (dev_alloc((void **)&s->par_dev, sizeof(float) * 3 * s->nc, S->pool) != hipSuccess) return false;
+    if (dev_alloc((void **)&s->m_dev, sizeof(float) * 3 * s->nn, S->pool) != hipSuccess) return false;
     if (hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess) return false;
     float *Ms = s->par_dev, *A = s->par_dev + s->nc, *al = s->par_dev + 2 * s->nc;
     const size_t cb = sizeof(float) * s->nc;
@@ -155,13 +160,15 @@ void complete(nm_server *S, Solve *s) {
     s->m_out.resize(3 * s->nn);
     hipError_t e = hipMemcpyAsync(s->m_out.data(), s->m_dev, sizeof(float) * 3 * s->nn,
                                   hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    // wait for this solve's work only (the stream is shared with other solves)
+    if (e == hipSuccess) e = hipEventRecord(s->ev, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(s->ev);
     s->res.status = e != hipSuccess ? NM_EHIP : st;
     s->res.t = s->clk.t;
     s->res.accepted = s->clk.accepted;
     s->res.rejected = s->clk.rejected;
     s->res.rhs_evals = s->clk.rhs_evals;
-    release(s);
+    release(s, S->pool);
     s->res.t_done = now_s();
     std::lock_guard<std::mutex> lk(S->mu);
     S->used -= s->footprint;
@@ -172,6 +179,7 @@ void complete(nm_server *S, Solve *s) {
 
 void run(nm_server *S) {
     (void)hipSetDevice(S->device);
+    set_thread_pool(S->pool);
     for (;;) {
         // admission: FIFO, within the memory budget and the active cap
         for (;;) {
@@ -285,6 +293,7 @@ extern "C" nm_status nm_server_create(const nm_server_desc *desc, nm_server **ou
         }
         S->streams.push_back(st);
     }
+    S->pool = pool_create();
     S->worker = std::thread(run, S);
     *out = S;
     return NM_OK;
@@ -300,12 +309,13 @@ extern "C" nm_status nm_server_destroy(nm_server *S) {
     S->worker.join();
     for (Solve *s : S->active) {
         (void)hipStreamSynchronize(s->stream);
-        release(s);
+        release(s, S->pool);
         delete s;
     }
     for (Solve *s : S->pending) delete s;
     for (auto &kv : S->done) delete kv.second;
     for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+    pool_destroy(S->pool);
     delete S;
     return NM_OK;
 }
