@@ -281,6 +281,19 @@ __device__ __forceinline__ Tensor6 tensor_load(const float *__restrict__ T, long
     return N;
 }
 
+// the same with 32-bit byte offsets from per-component bases (off = 4 tidx)
+__device__ __forceinline__ Tensor6 tensor_load32(const float *__restrict__ T, long long tstride,
+                                                 unsigned off, float sy) {
+    Tensor6 N;
+    N.xx = ldo(T, off);
+    N.yy = ldo(T + tstride, off);
+    N.zz = ldo(T + 2 * tstride, off);
+    N.xy = sy * ldo(T + 3 * tstride, off);
+    N.xz = ldo(T + 4 * tstride, off);
+    N.yz = sy * ldo(T + 5 * tstride, off);
+    return N;
+}
+
 // H^ = -N^ M^ in place; sz flips the components odd along the fused axis
 __device__ __forceinline__ void tensor_apply(const Tensor6 &N, float sz, float2 &mx, float2 &my, float2 &mz) {
     const float xz = sz * N.xz, yz = sz * N.yz;
@@ -400,21 +413,25 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     const bool valid = col < P2 * KP && col % KP < K1;
     const int colc = valid ? col : 0;   // pad / past-the-end lanes read column 0
     const long long plane = (long long)P2 * KP;
-    // inputs z = (j + T a) + L1 n2, nonzero only for n2 < L2 / 2
+    // inputs z = (j + T a) + L1 n2, nonzero only for n2 < L2 / 2; 32-bit byte
+    // offsets within one component (N3 P2 KP complex < 4 GiB)
+    float2 *sp[3] = {spec, spec + (long long)N3 * plane, spec + 2LL * N3 * plane};
     float2 v[3][E];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < A; ++a)
 #pragma unroll
-        for (int a = 0; a < A; ++a)
+        for (int n2 = 0; n2 < L2; ++n2) {
+            if (n2 < L2 / 2) {
+                const int z = j + TT * a + L1 * n2;
+                const unsigned off = 8u * ((unsigned)min(z, N3 - 1) * (unsigned)plane + (unsigned)colc);
+                const bool ok = valid && z < N3;
 #pragma unroll
-            for (int n2 = 0; n2 < L2; ++n2) {
-                float2 x = make_float2(0.f, 0.f);
-                if (n2 < L2 / 2) {
-                    const int z = j + TT * a + L1 * n2;
-                    x = keep(spec[((long long)c * N3 + min(z, N3 - 1)) * plane + colc], valid && z < N3);
-                }
-                v[c][a * L2 + n2] = x;
+                for (int c = 0; c < 3; ++c) v[c][a * L2 + n2] = keep(ldo(sp[c], off), ok);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c][a * L2 + n2] = make_float2(0.f, 0.f);
             }
+        }
     // tensor entries of this thread's frequencies kz = (j + T q) + L2 k1
     // (kz and L - kz share the stored entry, xz and yz change sign)
     const int ky = colc / KP, kx = colc - ky * KP;
@@ -424,7 +441,8 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     auto tensor_at = [&](int i) {
         const int kz = j + TT * (i / L1) + L2 * (i % L1);
         const int kzr = kz <= L / 2 ? kz : L - kz;
-        return tensor_load(T, tstride, ((long long)kzr * P2h + kyr) * KP + kx, fy ? -1.f : 1.f, true);
+        return tensor_load32(T, tstride, 4u * (((unsigned)kzr * (unsigned)P2h + (unsigned)kyr) * (unsigned)KP + (unsigned)kx),
+                             fy ? -1.f : 1.f);
     };
     auto apply = [&](int i, const Tensor6 &N) {
         const int kz = j + TT * (i / L1) + L2 * (i % L1);
@@ -458,14 +476,15 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     }
     if (!valid) return;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < A; ++a)
 #pragma unroll
-        for (int a = 0; a < A; ++a)
+        for (int n2 = 0; n2 < L2 / 2; ++n2) {
+            const int z = j + TT * a + L1 * n2;
+            const unsigned off = 8u * ((unsigned)z * (unsigned)plane + (unsigned)col);
+            if (z < N3)
 #pragma unroll
-            for (int n2 = 0; n2 < L2 / 2; ++n2) {
-                const int z = j + TT * a + L1 * n2;
-                if (z < N3) spec[((long long)c * N3 + z) * plane + col] = v[c][a * L2 + n2];
-            }
+                for (int c = 0; c < 3; ++c) sto(sp[c], off, v[c][a * L2 + n2]);
+        }
 }
 
 // ------------------------------------ y forward + product + y inverse (N3 = 1)

@@ -38,6 +38,19 @@ struct ErrPartial {
 
 struct ProfState;  // per-kernel event timing (measurement only)
 
+// Element access by 32-bit byte offset from a uniform base pointer: the loads
+// and stores then take the scalar-base form with one 32-bit offset register.
+// Callers keep each offset below 4 GiB (a component array of the largest
+// mesh, 512 cells per axis, is well below).
+template <class T>
+__device__ __forceinline__ T ldo(const T *base, unsigned byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void sto(T *base, unsigned byte_off, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+
 // device memory: hipMalloc / hipFree, or a pool (see pool.hip)
 struct DevPool;
 constexpr size_t kPoolHostBlock = 4096;   // pinned host blocks recycled by a pool

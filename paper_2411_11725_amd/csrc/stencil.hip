@@ -108,19 +108,6 @@ __device__ __forceinline__ void reduce_partial(double sq, float mf, int nf, ErrP
     }
 }
 
-// Element access by 32-bit byte offset from a uniform base pointer: meshes
-// have at most 512 cells per axis, so every component array is far below
-// 4 GiB and the offsets fit; the loads then take the scalar-base form with one
-// 32-bit offset register shared by the three components.
-template <class T>
-__device__ __forceinline__ T ldo(const T *base, unsigned byte_off) {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-template <class T>
-__device__ __forceinline__ void sto(T *base, unsigned byte_off, T v) {
-    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
-}
-
 // Does the neighbour at offset d (one axis, -1/0/+1) lie in the cell whose
 // corner the node is at local index i (0/1) along that axis?
 __host__ __device__ constexpr bool shares(int d, int i) { return d == 0 || (d == 1 && i == 0) || (d == -1 && i == 1); }
