@@ -179,6 +179,48 @@ def serving_bench(B, synth, count, t_end, nmax, max_active, n_streams=4, attempt
     }
 
 
+def adjoint_bench(B, synth, nsteps, ckpt):
+    """Inverse-problem workload (the 256x128x1 magnonic strip, RK4 dt 5e-14 s,
+    10 GHz drive, loss = -time average of the mean m_z^2 over a 16x16 output
+    region): forward trajectory with checkpoints, then the adjoint sweep that
+    gives the gradient with respect to the per-cell field map."""
+    import torch
+
+    from paper_2411_11725_amd.adjoint import LLGTrajectory
+
+    p = synth.magnonic()
+    mesh = B.mesh_from_problem(p, device="cuda:0")
+    n1, n2, n3 = p["n"]
+    try:
+        theta = torch.zeros((3, n3, n2, n1), device="cuda:0", requires_grad=True)
+        m0 = torch.as_tensor(p["m0"], device="cuda:0").contiguous()
+        region = torch.zeros((n3 + 1, n2 + 1, n1 + 1), dtype=torch.bool, device="cuda:0")
+        region[:, 56:72, 200:216] = True
+        # warm-up: records the stepping and adjoint-segment graphs
+        w = LLGTrajectory.apply(theta, m0, mesh, 5e-14, ckpt, ckpt, 1, B.NM_T_ALL)
+        (-(w[:, 2][:, region] ** 2).mean()).backward()
+        theta.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        traj = LLGTrajectory.apply(theta, m0, mesh, 5e-14, nsteps, ckpt, 1, B.NM_T_ALL)
+        loss = -(traj[:, 2][:, region] ** 2).mean()
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_bwd = time.perf_counter() - t0
+        gnorm = float(theta.grad.norm())
+    finally:
+        B.nm_mesh_destroy(mesh)
+    cells = n1 * n2 * n3
+    return {"workload": "magnonic strip %dx%dx%d cells, RK4 dt 5e-14 s, %d steps, checkpoint every %d, "
+                        "gradient w.r.t. the per-cell field map" % (n1, n2, n3, nsteps, ckpt),
+            "forward_steps_per_s": nsteps / t_fwd, "backward_steps_per_s": nsteps / t_bwd,
+            "backward_over_forward": t_bwd / t_fwd,
+            "forward_cell_updates_per_s": 4 * cells * nsteps / t_fwd, "grad_norm": gnorm}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +236,8 @@ def main():
     ap.add_argument("--serve-active", type=int, default=16)
     ap.add_argument("--serve-attempts", type=int, default=8)
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=400,
+                    help="RK4 steps of the adjoint measurement (0: skip it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run 5 plain device copies of 256 MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -285,6 +329,9 @@ def main():
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": kernels,
     }
+    if args.adjoint_steps > 0:
+        out["adjoint"] = adjoint_bench(B, synth, args.adjoint_steps, 100)
+        print("adjoint: done", file=sys.stderr, flush=True)
     if args.serve_count > 0:
         out["serving"] = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
                                        args.serve_active, args.serve_streams, args.serve_attempts)

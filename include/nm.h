@@ -158,8 +158,11 @@ nm_status nm_energy(nm_mesh *mesh, const float *m, unsigned terms, double t, dou
 /* Advance m (device, in place) from clk->t to t_end with at most max_steps
  * steps (RK4: steps of clk->dt, the last one shortened to land on t_end;
  * DP45: accepted steps, starting from the proposal clk->dt).  Updates *clk.
- * Synchronises the stream.  Returns NM_ENONFINITE / NM_ESTEPSIZE when the
- * DP45 controller fails; m then holds the last accepted state. */
+ * RK4 returns once the steps are queued on the mesh stream (the clock is
+ * advanced on the host exactly as the device advances it; kernel errors
+ * surface at the next synchronisation).  DP45 synchronises the stream and
+ * returns NM_ENONFINITE / NM_ESTEPSIZE when its controller fails; m then
+ * holds the last accepted state. */
 nm_status nm_llg_step(nm_mesh *mesh, float *m, nm_clock *clk, const nm_integrator *integ,
                       double t_end, long max_steps);
 

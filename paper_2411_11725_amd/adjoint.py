@@ -14,6 +14,26 @@ import torch
 
 from . import binding as B
 
+# adjoint workspaces kept per (mesh, segment length, size): the library
+# records one graph per segment shape and workspace, so reusing the buffer
+# lets later backward passes replay it instead of recording again
+_WORKSPACES = {}
+
+
+def _workspace(mesh, nsteps, device):
+    nbytes = B.nm_adjoint_workspace_bytes(mesh, nsteps)
+    key = (mesh.value, nsteps, nbytes, str(device))
+    w = _WORKSPACES.get(key)
+    if w is None:
+        w = torch.empty(nbytes // 4, dtype=torch.float32, device=device)
+        _WORKSPACES[key] = w
+    return w
+
+
+def release_workspaces():
+    """Drop the cached adjoint workspaces (e.g. after destroying meshes)."""
+    _WORKSPACES.clear()
+
 
 class LLGTrajectory(torch.autograd.Function):
     @staticmethod
@@ -49,12 +69,11 @@ class LLGTrajectory(torch.autograd.Function):
         g = grad_samples.contiguous()
         lam = torch.zeros_like(ckpts[0])
         gth = torch.zeros(ctx.theta_shape, dtype=torch.float32, device=lam.device)
-        work = None
         for si in range(len(ckpts) - 1, -1, -1):
             k0 = si * ckpt_every
             nseg = min(ckpt_every, nsteps - k0)
             dl = g[k0 // sample_every:(k0 + nseg) // sample_every]
-            work = B.nm_adjoint_step(mesh, ckpts[si], t0 + k0 * dt, dt, nseg, terms, lam,
-                                     dl_dm=dl, dl_every=sample_every, grad_hcell=gth,
-                                     work=work if work is not None and nseg == ckpt_every else None)
+            B.nm_adjoint_step(mesh, ckpts[si], t0 + k0 * dt, dt, nseg, terms, lam,
+                              dl_dm=dl, dl_every=sample_every, grad_hcell=gth,
+                              work=_workspace(mesh, nseg, lam.device))
         return gth, lam, None, None, None, None, None, None, None

@@ -82,6 +82,53 @@ k_axpby(float *__restrict__ y, const float *__restrict__ x, float a, const float
     y[i] = a * x[i] + (z ? b * z[i] : 0.f);
 }
 
+// Per-segment inputs of a recorded adjoint segment, read by the kernels of the
+// graph at run time so that one graph serves every segment of the same length
+struct AdjSlots {
+    double t0;          // time of the segment's first state
+    const float *m0;    // checkpoint state
+    const float *dl;    // dL/dm samples of the segment (or NULL)
+};
+
+__global__ void k_adj_slots(AdjSlots *S, double t0, const float *m0, const float *dl) {
+    if (threadIdx.x == 0) {
+        S->t0 = t0;
+        S->m0 = m0;
+        S->dl = dl;
+    }
+}
+
+// controller time of step j: t0 + j dt (read by the stage kernels)
+__global__ void k_adj_time(Ctrl *C, const AdjSlots *S, int j, double dt) {
+    if (threadIdx.x == 0) {
+        C->t = S->t0 + j * dt;
+        C->dt = dt;
+        C->done = 0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_vcopy(float *__restrict__ y, const float *__restrict__ x, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+__global__ void __launch_bounds__(256) k_vzero(float *__restrict__ y, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = 0.f;
+}
+
+__global__ void __launch_bounds__(256) k_copy_m0(float *__restrict__ y, const AdjSlots *__restrict__ S, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = S->m0[i];
+}
+
+// y += dl[off ..]
+__global__ void __launch_bounds__(256) k_add_dl(float *__restrict__ y, const AdjSlots *__restrict__ S,
+                                                long long off, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] += S->dl[off + i];
+}
+
 // grad_c += mu0 Ms_c V/8 sum_{n in c} v_n
 __global__ void __launch_bounds__(256)
 k_cell_gather(const float *__restrict__ v, const float *__restrict__ wc, float *__restrict__ grad,
@@ -123,12 +170,16 @@ using namespace nm;
         }                                                                           \
     } while (0)
 
-// workspace: nsteps states + 14 nodal vectors
-static long long adj_vectors(int nsteps) { return (long long)nsteps + 14; }
+// workspace: nsteps states + 15 nodal vectors, then the segment slots
+static long long adj_vectors(int nsteps) { return (long long)nsteps + 15; }
+static size_t adj_slot_offset(const nm_mesh *m, int nsteps) {
+    const size_t b = sizeof(float) * 3 * (size_t)m->n_nodes * (size_t)adj_vectors(nsteps);
+    return (b + 255) / 256 * 256;
+}
 
 extern "C" size_t nm_adjoint_workspace_bytes(const nm_mesh *m, int nsteps) {
     if (!m || nsteps < 1) return 0;
-    return sizeof(float) * 3 * (size_t)m->n_nodes * (size_t)adj_vectors(nsteps);
+    return adj_slot_offset(m, nsteps) + 256;
 }
 
 namespace {
@@ -148,7 +199,7 @@ hipError_t field_stage(nm_mesh *m, unsigned terms, int mode, int s, const float 
     sp.mstate = mstate;
     sp.t0 = t0;
     sp.dt0 = dt;
-    sp.use_ctrl = false;
+    sp.use_ctrl = true;   // stage time from the controller (k_adj_time)
     return launch_stencil(m, terms, sp);
 }
 
@@ -168,82 +219,129 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
     NM_REQUIRE(!grad_hcell || (terms & NM_T_ZEEMAN), NM_EINVAL,
                "nm_adjoint_step: a field-map gradient needs NM_T_ZEEMAN");
     const long long nn = m->n_nodes, n3 = 3 * nn;
-    const size_t vb = sizeof(float) * (size_t)n3;
     float *S = work;                                   // states m_0 .. m_{nsteps-1}
-    float *V = work + (long long)nsteps * n3;          // 14 scratch vectors
-    float *Y[5] = {nullptr, nullptr, V + 0 * n3, V + 1 * n3, V + 2 * n3};   // y2, y3, y4
-    float *Hs[5] = {nullptr, V + 3 * n3, V + 4 * n3, V + 5 * n3, V + 6 * n3};
-    float *w = V + 7 * n3, *v = V + 8 * n3, *vjp = V + 9 * n3, *Hv = V + 10 * n3;
-    float *lacc = V + 11 * n3, *vsum = V + 12 * n3, *wn = V + 13 * n3;
+    float *V = work + (long long)nsteps * n3;          // 15 scratch vectors
+    float *lam = V + 14 * n3;                          // lambda inside the segment
+    AdjSlots *slots = reinterpret_cast<AdjSlots *>(reinterpret_cast<char *>(work) + adj_slot_offset(m, nsteps));
     const unsigned lin = terms & ~(unsigned)NM_T_ZEEMAN;
     const dim3 g3((unsigned)((n3 + 255) / 256)), gn((unsigned)((nn + 255) / 256));
-    hipStream_t st = m->stream;
     const char *who = "nm_adjoint_step";
     const bool gather = grad_hcell != nullptr;
+    const bool has_dl = dl_dm != nullptr;
+    float *vsum = V + 12 * n3;
 
-    // forward recompute of the segment's states from the checkpoint
-    NM_HIP(hipMemcpyAsync(S, m0, vb, hipMemcpyDeviceToDevice, st), who);
-    for (int j = 0; j + 1 < nsteps; ++j) {
-        float *cur = S + (long long)(j + 1) * n3;
-        NM_HIP(hipMemcpyAsync(cur, S + (long long)j * n3, vb, hipMemcpyDeviceToDevice, st), who);
-        const double tj = t0 + j * dt;
-        StageSpec sp{};
-        sp.mode = kModeRK4;
-        sp.t0 = tj;
-        sp.dt0 = dt;
-        sp.use_ctrl = false;
-        sp.mstate = cur;
-        const float *ins[4] = {cur, m->y[0], m->y[1], m->y[0]};
-        float *outs[4] = {m->y[0], m->y[1], m->y[0], nullptr};
-        for (int s = 1; s <= 4; ++s) {
-            if (terms & NM_T_DEMAG)
-                NM_HIP(demag_forward_conv_inverse(m, ins[s - 1], (terms & NM_T_ZEEMAN) ? 2 : 1), who);
-            sp.stage = s;
-            sp.in = ins[s - 1];
-            sp.y_next = outs[s - 1];
-            NM_HIP(launch_stencil(m, terms, sp), who);
-        }
-    }
-    if (gather) NM_HIP(hipMemsetAsync(vsum, 0, vb, st), who);
-    if (dl_dm && nsteps % dl_every == 0)
-        hipLaunchKernelGGL(k_axpby, g3, dim3(256), 0, st, lambda, lambda, 1.f,
-                           dl_dm + (long long)(nsteps / dl_every - 1) * n3, 1.f, n3);
-
-    // reverse sweep
-    for (int j = nsteps - 1; j >= 0; --j) {
-        const double tj = t0 + j * dt;
-        float *y1 = S + (long long)j * n3;
-        const float *yin[5] = {nullptr, y1, Y[2], Y[3], Y[4]};
-        for (int s = 1; s <= 4; ++s)
-            NM_HIP(field_stage(m, terms, kModeAdjFwd, s, yin[s], Hs[s], s < 4 ? Y[s + 1] : nullptr, y1, tj, dt),
-                   who);
-        NM_HIP(hipMemcpyAsync(lacc, lambda, vb, hipMemcpyDeviceToDevice, st), who);
-        // w4 = dt/6 lam
-        hipLaunchKernelGGL(k_axpby, g3, dim3(256), 0, st, w, lambda, (float)(dt / 6.0), (const float *)nullptr,
-                           0.f, n3);
-        const float cl[5] = {0.f, 0.f, (float)(dt / 6.0), (float)(dt / 3.0), (float)(dt / 3.0)};
-        const float cg[5] = {0.f, 0.f, (float)(dt / 2.0), (float)(dt / 2.0), (float)dt};
-        for (int s = 4; s >= 1; --s) {
-            hipLaunchKernelGGL(k_adj_vjp, gn, dim3(256), 0, st, yin[s], Hs[s], w, m->inv_mass, m->alpha_n,
-                               m->gp_n, v, vjp, gather ? vsum : nullptr, nn);
-            if (lin) {
-                if (lin & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, v, 1), who);
-                StageSpec sp{};
-                sp.mode = kModeField;
-                sp.in = v;
-                sp.out = Hv;
-                sp.t0 = tj;
-                NM_HIP(launch_stencil(m, lin, sp), who);
+    // the segment body: recorded once per (length, terms, dt, loss sampling,
+    // workspace) as a HIP graph and replayed for every segment; its inputs
+    // (checkpoint, start time, loss samples) come through the slots
+    auto enqueue = [&]() -> hipError_t {
+        hipStream_t st = m->stream;
+        float *Y[5] = {nullptr, nullptr, V + 0 * n3, V + 1 * n3, V + 2 * n3};   // y2, y3, y4
+        float *Hs[5] = {nullptr, V + 3 * n3, V + 4 * n3, V + 5 * n3, V + 6 * n3};
+        float *w = V + 7 * n3, *v = V + 8 * n3, *vjp = V + 9 * n3, *Hv = V + 10 * n3;
+        float *lacc = V + 11 * n3, *wn = V + 13 * n3;
+        hipError_t e = hipSuccess;
+#define NM_ADJ(call)                    \
+    do {                                \
+        if (e == hipSuccess) e = (call); \
+    } while (0)
+        // forward recompute of the segment's states from the checkpoint
+        hipLaunchKernelGGL(k_copy_m0, g3, dim3(256), 0, st, S, slots, n3);
+        for (int j = 0; j + 1 < nsteps; ++j) {
+            float *cur = S + (long long)(j + 1) * n3;
+            hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, cur, S + (long long)j * n3, n3);
+            hipLaunchKernelGGL(k_adj_time, dim3(1), dim3(64), 0, st, m->ctrl, slots, j, dt);
+            StageSpec sp{};
+            sp.mode = kModeRK4;
+            sp.use_ctrl = true;
+            sp.mstate = cur;
+            const float *ins[4] = {cur, m->y[0], m->y[1], m->y[0]};
+            float *outs[4] = {m->y[0], m->y[1], m->y[0], nullptr};
+            for (int s = 1; s <= 4; ++s) {
+                if (terms & NM_T_DEMAG)
+                    NM_ADJ(demag_forward_conv_inverse(m, ins[s - 1], (terms & NM_T_ZEEMAN) ? 2 : 1));
+                sp.stage = s;
+                sp.in = ins[s - 1];
+                sp.y_next = outs[s - 1];
+                NM_ADJ(launch_stencil(m, terms, sp));
             }
-            // s > 1: w_{s-1} = cl lam + cg J_s^T w_s; s = 1: lam <- lam_acc + J_1^T w_1
-            hipLaunchKernelGGL(k_adj_combine, g3, dim3(256), 0, st, vjp, Hv, m->inv_mass, lambda, lacc, wn,
-                               cl[s], cg[s], s == 1 ? lambda : nullptr, lin ? 1 : 0, nn);
-            if (s > 1) std::swap(w, wn);
         }
-        if (dl_dm && j > 0 && j % dl_every == 0)
-            hipLaunchKernelGGL(k_axpby, g3, dim3(256), 0, st, lambda, lambda, 1.f,
-                               dl_dm + (long long)(j / dl_every - 1) * n3, 1.f, n3);
+        if (gather) hipLaunchKernelGGL(k_vzero, g3, dim3(256), 0, st, vsum, n3);
+        if (has_dl && nsteps % dl_every == 0)
+            hipLaunchKernelGGL(k_add_dl, g3, dim3(256), 0, st, lam, slots,
+                               (long long)(nsteps / dl_every - 1) * n3, n3);
+        // reverse sweep
+        for (int j = nsteps - 1; j >= 0; --j) {
+            float *y1 = S + (long long)j * n3;
+            const float *yin[5] = {nullptr, y1, Y[2], Y[3], Y[4]};
+            hipLaunchKernelGGL(k_adj_time, dim3(1), dim3(64), 0, st, m->ctrl, slots, j, dt);
+            for (int s = 1; s <= 4; ++s)
+                NM_ADJ(field_stage(m, terms, kModeAdjFwd, s, yin[s], Hs[s], s < 4 ? Y[s + 1] : nullptr, y1, 0.0,
+                                   dt));
+            hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, lacc, lam, n3);
+            // w4 = dt/6 lam
+            hipLaunchKernelGGL(k_axpby, g3, dim3(256), 0, st, w, lam, (float)(dt / 6.0), (const float *)nullptr,
+                               0.f, n3);
+            const float cl[5] = {0.f, 0.f, (float)(dt / 6.0), (float)(dt / 3.0), (float)(dt / 3.0)};
+            const float cg[5] = {0.f, 0.f, (float)(dt / 2.0), (float)(dt / 2.0), (float)dt};
+            for (int s = 4; s >= 1; --s) {
+                hipLaunchKernelGGL(k_adj_vjp, gn, dim3(256), 0, st, yin[s], Hs[s], w, m->inv_mass, m->alpha_n,
+                                   m->gp_n, v, vjp, gather ? vsum : nullptr, nn);
+                if (lin) {
+                    if (lin & NM_T_DEMAG) NM_ADJ(demag_forward_conv_inverse(m, v, 1));
+                    StageSpec sp{};
+                    sp.mode = kModeField;
+                    sp.in = v;
+                    sp.out = Hv;
+                    NM_ADJ(launch_stencil(m, lin, sp));
+                }
+                // s > 1: w_{s-1} = cl lam + cg J_s^T w_s; s = 1: lam <- lam_acc + J_1^T w_1
+                hipLaunchKernelGGL(k_adj_combine, g3, dim3(256), 0, st, vjp, Hv, m->inv_mass, lam, lacc, wn,
+                                   cl[s], cg[s], s == 1 ? lam : nullptr, lin ? 1 : 0, nn);
+                if (s > 1) std::swap(w, wn);
+            }
+            if (has_dl && j > 0 && j % dl_every == 0)
+                hipLaunchKernelGGL(k_add_dl, g3, dim3(256), 0, st, lam, slots, (long long)(j / dl_every - 1) * n3,
+                                   n3);
+        }
+#undef NM_ADJ
+        return e == hipSuccess ? hipGetLastError() : e;
+    };
+
+    hipStream_t st = m->stream;
+    hipLaunchKernelGGL(k_adj_slots, dim3(1), dim3(64), 0, st, slots, t0, m0, dl_dm);
+    hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, lam, lambda, n3);
+    if (m->prof) {
+        NM_HIP(enqueue(), who);   // per-kernel events cannot live in a graph
+    } else {
+        const bool same = m->adj_gexec && m->adj_nsteps == nsteps && m->adj_terms == terms && m->adj_dt == dt &&
+                          m->adj_every == (has_dl ? dl_every : 0) && m->adj_gather == gather &&
+                          m->adj_work == work;
+        if (!same) {
+            if (m->adj_gexec) {
+                (void)hipStreamSynchronize(st);
+                (void)hipGraphExecDestroy(m->adj_gexec);
+                m->adj_gexec = nullptr;
+            }
+            m->stream = m->cap_stream;
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
+            hipError_t e2 = e == hipSuccess ? enqueue() : e;
+            if (e == hipSuccess) e = hipStreamEndCapture(m->cap_stream, &graph);
+            m->stream = st;
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&m->adj_gexec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            NM_HIP(e, who);
+            m->adj_nsteps = nsteps;
+            m->adj_terms = terms;
+            m->adj_dt = dt;
+            m->adj_every = has_dl ? dl_every : 0;
+            m->adj_gather = gather;
+            m->adj_work = work;
+        }
+        NM_HIP(hipGraphLaunch(m->adj_gexec, st), who);
     }
+    hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, lambda, lam, n3);
     if (gather)
         hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
                            m->wc, grad_hcell, m->N1, m->N2, m->N3);

@@ -141,7 +141,11 @@ static size_t footprint(const Sizes &s) {
 }
 
 static void drop_graph(nm_mesh *m) {
-    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    if (m->gexec) {
+        // a replay may still be queued (RK4 calls return without waiting)
+        (void)hipStreamSynchronize(m->stream);
+        (void)hipGraphExecDestroy(m->gexec);
+    }
     m->gexec = nullptr;
     m->g_method = 0;
     m->g_terms = 0;
@@ -149,10 +153,19 @@ static void drop_graph(nm_mesh *m) {
     m->g_batch = 0;
 }
 
+static void drop_adj_graph(nm_mesh *m) {
+    if (m->adj_gexec) {
+        (void)hipStreamSynchronize(m->stream);
+        (void)hipGraphExecDestroy(m->adj_gexec);
+    }
+    m->adj_gexec = nullptr;
+}
+
 static void free_mesh(nm_mesh *m) {
     if (!m) return;
     prof_free(m);
     drop_graph(m);
+    drop_adj_graph(m);
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
@@ -333,7 +346,7 @@ extern "C" nm_status nm_mesh_info(const nm_mesh *m, int64_t *n_nodes, int64_t *n
 
 extern "C" nm_status nm_mesh_set_field(nm_mesh *m, const float *h_cell) {
     NM_REQUIRE(m, NM_EINVAL, "nm_mesh_set_field: NULL mesh");
-    drop_graph(m);  // the field map is baked into captured kernel arguments
+    // recorded graphs stay valid: they read the repacked cell data from memory
     if (!h_cell) {
         m->has_hcell = false;
         NM_HIP(launch_cell_pack(m), "nm_mesh_set_field");
@@ -454,9 +467,18 @@ hipError_t rk4_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *
 
 namespace nm {
 
-// Validate, upload the controller state (asynchronously, from the pinned
-// mirror) and, for DP45, launch the first stage.  *batch gets the number of
-// steps / attempts one replay of the stepping graph covers.
+// Controller initialisation from a kernel argument: the values travel with
+// the launch, so a call may return while it is still queued (an asynchronous
+// copy from host memory would race with the next call filling that memory).
+__global__ void k_ctrl_set(Ctrl *C, Ctrl v) {
+    const unsigned *src = reinterpret_cast<const unsigned *>(&v);
+    unsigned *dst = reinterpret_cast<unsigned *>(C);
+    for (unsigned i = threadIdx.x; i < sizeof(Ctrl) / 4; i += blockDim.x) dst[i] = src[i];
+}
+
+// Validate, initialise the device controller and, for DP45, launch the first
+// stage.  *batch gets the number of steps / attempts one replay of the
+// stepping graph covers.
 nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integrator *in,
                      double t_end, long max_steps, int *batch) {
     NM_REQUIRE(m && mag && clk && in, NM_EINVAL, "nm_llg_step: NULL argument");
@@ -471,7 +493,8 @@ nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integ
     nm_status st = check_terms(m, in->terms, "nm_llg_step");
     if (st != NM_OK) return st;
     NM_REQUIRE(m->n_active > 0, NM_EINVAL, "nm_llg_step: the mesh has no magnetic node");
-    Ctrl *C = m->ctrl_host;
+    Ctrl c0;
+    Ctrl *C = &c0;
     std::memset(C, 0, sizeof(Ctrl));
     C->t = clk->t;
     C->dt_prop = clk->dt;
@@ -487,7 +510,9 @@ nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integ
     C->log = in->log;
     C->log_cap = in->log ? in->log_capacity : 0;
     C->done = t_end == clk->t ? 1 : 0;
-    NM_HIP(hipMemcpyAsync(m->ctrl, C, sizeof(Ctrl), hipMemcpyHostToDevice, m->stream), "nm_llg_step");
+    static_assert(sizeof(Ctrl) % 4 == 0, "word copy");
+    hipLaunchKernelGGL(k_ctrl_set, dim3(1), dim3(64), 0, m->stream, m->ctrl, c0);
+    NM_HIP(hipGetLastError(), "nm_llg_step");
     // RK4 knows its step count: never capture more steps than the call needs
     int b = 16;
     if (in->method == NM_RK4) {
@@ -585,8 +610,21 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         if (nsteps < 1) nsteps = 1;
         if (nsteps > max_steps) nsteps = max_steps;
         for (long k = 0; k < nsteps; k += batch) NM_HIP(step_batch(m, mag, NM_RK4, terms, batch), "nm_llg_step");
-        NM_HIP(ctrl_readback(m), "nm_llg_step");
-        NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
+        // Fixed steps: the call returns without waiting for the GPU; the clock
+        // advances on the host exactly as k_rk4_advance moves it on the device
+        double t = clk->t, dt = std::fmin(clk->dt, t_end - clk->t);
+        long acc = 0;
+        for (;;) {
+            const bool last = dt >= (t_end - t) * (1.0 - 1e-9);
+            t = last ? t_end : t + dt;
+            ++acc;
+            if (last || acc >= max_steps) break;
+            dt = std::fmin(clk->dt, t_end - t);
+        }
+        clk->t = t;
+        clk->accepted += acc;
+        clk->rhs_evals += 4 * acc;
+        return NM_OK;
     } else {
         long long seen = -1;
         for (;;) {

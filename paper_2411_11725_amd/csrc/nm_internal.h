@@ -112,6 +112,13 @@ struct nm_mesh {
     // `stream`; captured on the private `cap_stream`
     hipStream_t cap_stream;
     hipGraphExec_t gexec;
+    // recorded adjoint segment and its key
+    hipGraphExec_t adj_gexec;
+    int adj_nsteps, adj_every;
+    unsigned adj_terms;
+    bool adj_gather;
+    double adj_dt;
+    float *adj_work;
     int g_method;
     unsigned g_terms;
     float *g_mag;
