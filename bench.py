@@ -267,6 +267,12 @@ def main():
         print(json.dumps({"serving": serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
                                                    args.serve_active, args.serve_streams, args.serve_attempts)}))
         return
+    # the serving stream runs first, in a fresh process state
+    serving = None
+    if args.serve_count > 0:
+        torch.cuda.set_device(0)
+        serving = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
+                                args.serve_active, args.serve_streams, args.serve_attempts)
     W = WORKLOADS[args.workload]
     p = getattr(synth, W["make"])()
     tmask = {"exchange": B.NM_T_EXCHANGE, "demag": B.NM_T_DEMAG, "anisotropy": B.NM_T_ANIS,
@@ -332,9 +338,8 @@ def main():
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_bench(B, synth, args.adjoint_steps, 100)
         print("adjoint: done", file=sys.stderr, flush=True)
-    if args.serve_count > 0:
-        out["serving"] = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
-                                       args.serve_active, args.serve_streams, args.serve_attempts)
+    if serving is not None:
+        out["serving"] = serving
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, terms)
     print(json.dumps(out))
