@@ -51,6 +51,16 @@ __device__ __forceinline__ void sto(T *base, unsigned byte_off, T v) {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
 }
 
+// XCD-aware block order: the dispatcher hands consecutive workgroups to the 8
+// XCDs in turn, each with its own L2.  Renumbering so that XCD x works through
+// one contiguous range of logical blocks keeps neighbouring blocks (which
+// share halo rows) in the same L2.  A bijection of [0, nb).
+constexpr unsigned kXCDs = 8;
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    const unsigned q = nb / kXCDs, r = nb % kXCDs, x = b % kXCDs, k = b / kXCDs;
+    return x * q + (x < r ? x : r) + k;
+}
+
 // device memory: hipMalloc / hipFree, or a pool (see pool.hip)
 struct DevPool;
 constexpr size_t kPoolHostBlock = 4096;   // pinned host blocks recycled by a pool

@@ -129,7 +129,10 @@ __host__ __device__ constexpr bool shares(int d, int i) { return d == 0 || (d ==
 template <int MODE, int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_node(StencilParams P, StageArgs S) {
-    const unsigned n = blockIdx.x * 256u + threadIdx.x;
+    // consecutive node ranges on one XCD: the halo rows of a block were
+    // fetched into that XCD's L2 by its neighbours
+    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    const unsigned n = lb * 256u + threadIdx.x;
     double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
     constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE)
@@ -334,7 +337,7 @@ k_node(StencilParams P, StageArgs S) {
             if (STAGE == 7 && im > 0.f) mf = sqrtf(fn2);
         }
     }
-    if (MODE == kModeDP45 && STAGE == 7) reduce_partial(sq, mf, nf, S.partials + blockIdx.x);
+    if (MODE == kModeDP45 && STAGE == 7) reduce_partial(sq, mf, nf, S.partials + lb);
 }
 
 dim3 stencil_grid(const nm_mesh *m) { return dim3((unsigned)((m->n_nodes + 255) / 256)); }
