@@ -177,6 +177,41 @@ def test_rk4_standard_cube_trajectory():
     assert abs(e_gpu["total"] - e_or["total"]) <= 1e-4 * abs(e_or["total"])
 
 
+def test_rk4_calls_queue_without_waiting_and_keep_the_clock():
+    """RK4 calls return once queued: successive calls (a max_steps stop, then a
+    shortened last step landing on t_end, then single steps with a drive in
+    time) give the oracle's states and the exact clock."""
+    p = synth.small_random((9, 7, 3), (2e-9, 2.5e-9, 3e-9), seed=49)
+    p["drive_mask"] = np.ones((3, 7, 9), dtype=np.float32)
+    p["drive_amp"] = (0.0, 2e4, 0.0)
+    p["drive_freq"] = 2e10
+    mesh = B.mesh_from_problem(p)
+    om, omat, om0 = to_oracle(p)
+    dt, t_end = 3e-15, 3e-15 * 7.4
+    try:
+        m = _dev(p["m0"])
+        clk = B.nm_clock(0.0, dt, 0, 0, 0, 0.0)
+        B.nm_llg_step(mesh, m, clk, B.NM_RK4, B.NM_T_ALL, t_end=t_end, max_steps=3)
+        assert clk.accepted == 3 and abs(clk.t - 3 * dt) < 1e-28
+        B.nm_llg_step(mesh, m, clk, B.NM_RK4, B.NM_T_ALL, t_end=t_end)
+        assert clk.accepted == 8 and clk.t == t_end and clk.rhs_evals == 32
+        for _ in range(3):
+            B.nm_llg_step(mesh, m, clk, B.NM_RK4, B.NM_T_ALL, t_end=clk.t + dt, max_steps=1)
+        g = m.cpu().numpy().astype(np.float64)
+    finally:
+        B.nm_mesh_destroy(mesh)
+    want, t = om0, 0.0
+    for k in range(8):
+        h = min(dt, t_end - t)
+        want = oracle.rk4_step(om, omat, want, t, h)
+        t = t_end if k == 7 else t + h
+    for _ in range(3):
+        want = oracle.rk4_step(om, omat, want, t, dt)
+        t += dt
+    assert abs(clk.t - t) < 1e-27 and clk.accepted == 11
+    assert np.abs(g - want).max() <= 1e-5
+
+
 def _film_dp45(max_steps, t_end=0.05e-9):
     p = synth.make_problem((32, 16, 1), (3.9e-9, 3.9e-9, 3e-9), 8e5, 1.3e-11, 0.02,
                            m0=(np.cos(0.17), np.sin(0.17), 0.0),
