@@ -140,6 +140,16 @@ nm_status nm_demag_tensor_init(nm_mesh *mesh);
  * no mesh needed; enqueued on stream. */
 nm_status nm_newell_octant(const int n[3], const double h[3], double *out, void *stream);
 
+/* Block widths of the register-FFT y passes and z convolution of this mesh:
+ * 0 the widest column tile, 1 half of it, 2 a quarter.  nm_demag_tensor_init
+ * chooses them by timing every width on the mesh (a few launches each on the
+ * mesh stream; the choice is cached per padded shape and device).  Every
+ * width computes each column identically, so results do not depend on it.
+ * With set == 0 this only reads the choice into *y_width, *z_width; with
+ * set != 0 it imposes them first (-1 keeps one; values outside -1..2 are
+ * NM_EINVAL; a width a length cannot use falls back to 0). */
+nm_status nm_mesh_tuning(nm_mesh *mesh, int set, int *y_width, int *z_width);
+
 /* Effective field (Eq. heff with Eq. mass_lumping) of the selected terms at
  * time t: m and h are device nodal vector fields (3 * n_nodes floats). */
 nm_status nm_heff(nm_mesh *mesh, const float *m, float *h, unsigned terms, double t);

@@ -19,7 +19,7 @@ NM_RK4, NM_DP45 = 1, 2
 # entry points declared in include/nm.h
 EXPORTS = [
     "nm_mesh_create", "nm_mesh_destroy", "nm_mesh_info", "nm_mesh_footprint_bytes",
-    "nm_mesh_set_field", "nm_demag_tensor_init", "nm_newell_octant", "nm_heff",
+    "nm_mesh_set_field", "nm_mesh_tuning", "nm_demag_tensor_init", "nm_newell_octant", "nm_heff",
     "nm_demag_cell_field", "nm_llg_rhs", "nm_energy", "nm_llg_step", "nm_adjoint_step",
     "nm_adjoint_workspace_bytes", "nm_server_create", "nm_server_destroy", "nm_serve_submit",
     "nm_serve_poll", "nm_server_clock", "nm_profile_enable",
@@ -91,6 +91,7 @@ def lib():
             "nm_mesh_info": ([P, POINTER(c_int64), POINTER(c_int64), POINTER(c_int)], c_int),
             "nm_mesh_footprint_bytes": ([POINTER(nm_mesh_desc), c_int], ctypes.c_size_t),
             "nm_mesh_set_field": ([P, P], c_int),
+            "nm_mesh_tuning": ([P, c_int, POINTER(c_int), POINTER(c_int)], c_int),
             "nm_demag_tensor_init": ([P], c_int),
             "nm_newell_octant": ([POINTER(c_int), POINTER(c_double), P, P], c_int),
             "nm_heff": ([P, P, P, c_uint, c_double], c_int),
@@ -155,6 +156,14 @@ def nm_mesh_info(mesh):
     nn, nc, pad = c_int64(), c_int64(), (c_int * 3)()
     _check(lib().nm_mesh_info(mesh, ctypes.byref(nn), ctypes.byref(nc), pad))
     return nn.value, nc.value, tuple(pad)
+
+
+def nm_mesh_tuning(mesh, y=None, z=None):
+    """(y_width, z_width) of the register-FFT passes; with y or z given,
+    impose it first (0 widest, 1 half, 2 quarter)."""
+    yy, zz = c_int(-1 if y is None else y), c_int(-1 if z is None else z)
+    _check(lib().nm_mesh_tuning(mesh, 0 if (y is None and z is None) else 1, ctypes.byref(yy), ctypes.byref(zz)))
+    return yy.value, zz.value
 
 
 def nm_mesh_footprint_bytes(n, h, gamma=2.211e5, integrator=NM_DP45):

@@ -364,7 +364,23 @@ extern "C" nm_status nm_demag_tensor_init(nm_mesh *m) {
     NM_REQUIRE(m, NM_EINVAL, "nm_demag_tensor_init: NULL mesh");
     if (m->tensor_ready) return NM_OK;
     NM_HIP(build_kspace_tensor(m), "nm_demag_tensor_init");
+    NM_HIP(tune_passes(m), "nm_demag_tensor_init");
     m->tensor_ready = true;
+    return NM_OK;
+}
+
+extern "C" nm_status nm_mesh_tuning(nm_mesh *m, int set, int *y, int *z) {
+    NM_REQUIRE(m && y && z, NM_EINVAL, "nm_mesh_tuning: NULL argument");
+    if (set) {
+        NM_REQUIRE(*y >= -1 && *y <= 2 && *z >= -1 && *z <= 2, NM_EINVAL,
+                   "nm_mesh_tuning: widths are 0, 1, 2 (or -1 to keep)");
+        if (*y >= 0) m->tune_y = *y;
+        if (*z >= 0) m->tune_z = *z;
+        drop_graph(m);
+        drop_adj_graph(m);
+    }
+    *y = m->tune_y;
+    *z = m->tune_z;
     return NM_OK;
 }
 

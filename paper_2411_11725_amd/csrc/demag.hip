@@ -23,6 +23,10 @@
 // registers and trade values once through LDS (fft2 in fft_reg.h), the z
 // convolution applying the tensor in registers between its two transforms
 // (P3 >= 512 falls back to the LDS sweep, as does the film convolution).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "fft_engine.h"
 #include "fft_reg.h"
 
@@ -202,12 +206,13 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
 // NPB columns per block, T threads per column (fft2 split of L).  Forward:
 // the N2 <= L / 2 data rows in, all L rows out.  Inverse: all L rows in, the
 // N2 data rows out.
-template <int L, int DIR>
+template <int L, int DIR, int SH>
 __global__ void __launch_bounds__(256)
 k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int N2, int K1, int KP,
           const Ctrl *__restrict__ ctrl) {
     constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
-    constexpr int NPB = 256 / TT, E = L / TT;
+    constexpr int NPB = (256 / TT) >> SH, E = L / TT, NT = NPB * TT;   // 2^-SH of the widest block
+    static_assert(NPB >= 1, "block width");
     __shared__ float2 sh[TT > 1 ? L * NPB : 1];
     __shared__ float2 tl[L];
     if (ctrl && ctrl->done) return;
@@ -232,7 +237,7 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
                 }
                 v[0][a * L2 + n2] = x;
             }
-        load_twiddles_full<L, 256>(tl, tw, tid);
+        load_twiddles_full<L, NT>(tl, tw, tid);
         fft2<L1, L2, -1, 1, NPB, E>(v, sh, tl, j, b);
         if (!valid) return;
         // rows (j + T q) + L2 k1
@@ -249,7 +254,7 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
 #pragma unroll
             for (int k1 = 0; k1 < L1; ++k1)
                 v[0][q * L1 + k1] = keep(lbase[(long long)(j + TT * q + L2 * k1) * KP], valid);
-        load_twiddles_full<L, 256>(tl, tw, tid);
+        load_twiddles_full<L, NT>(tl, tw, tid);
         fft2<L2, L1, 1, 1, NPB, E>(v, sh, tl, j, b);
         if (!valid) return;
         // rows (j + T a) + L1 n2 out; only n2 < L2 / 2 can be data rows
@@ -398,12 +403,13 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
 // happens in registers between the forward and the inverse transform.  Only
 // z < L / 2 can hold data (P3 >= 2 N3), so half of the inputs are known zeros
 // and half of the outputs are never stored.
-template <int L>
+template <int L, int SH>
 __global__ void __launch_bounds__(256)
 k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
           int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
     constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
-    constexpr int NPB = 256 / TT, E = L / TT, A = L1 / TT, Q = L2 / TT;
+    constexpr int NPB = (256 / TT) >> SH, E = L / TT, A = L1 / TT, Q = L2 / TT, NT = NPB * TT;
+    static_assert(NPB >= 1, "block width");
     constexpr int NCX = E <= 8 ? 3 : 1;   // components per LDS exchange
     __shared__ float2 sh[TT > 1 ? NCX * L * NPB : 1];
     __shared__ float2 tl[L];
@@ -454,7 +460,7 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
 #pragma unroll
         for (int i = 0; i < E; ++i) Nt[i] = tensor_at(i);
     }
-    load_twiddles_full<L, 256>(tl, tw, tid);
+    load_twiddles_full<L, NT>(tl, tw, tid);
     if constexpr (NCX == 3) {
         fft2<L1, L2, -1, 3, NPB, E>(v, sh, tl, j, b);
     } else {
@@ -575,22 +581,44 @@ static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl, int src
     NM_LAUNCH(m, NM_PROF_XINV, (k_xinv<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->spec, m->hd,
               tw, m->N1, m->N2, m->N3, m->P2, m->KP, m->wc, m->wstat, src_mode, ctrl);
 }
+// block-width choice of the register-FFT passes (0: widest, 1: half, 2: quarter)
+__host__ __device__ constexpr int col_shift_default(int L) { return 0; }
+
+template <int L, int DIR, int SH>
+static void launch_y_sh(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    constexpr int TT = fft2_threads(L), NPB = (256 / TT) >> SH;
+    const int ncols = m->N3 * m->KP;
+    NM_LAUNCH(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV, (k_ypass_r<L, DIR, SH>),
+              dim3((ncols + NPB - 1) / NPB, 3), dim3(NPB * TT), 0, m->spec, tw, m->N3, m->N2, m->K1, m->KP, ctrl);
+}
 template <int L, int DIR>
 static void launch_y(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
-    const int ncols = m->N3 * m->KP;
-    constexpr int NPB = 256 / fft2_threads(L);
-    NM_LAUNCH(m, DIR < 0 ? NM_PROF_YFWD : NM_PROF_YINV, (k_ypass_r<L, DIR>), dim3((ncols + NPB - 1) / NPB, 3),
-              dim3(256), 0, m->spec, tw, m->N3, m->N2, m->K1, m->KP, ctrl);
+    switch (m->tune_y) {
+        case 1: if constexpr ((256 / fft2_threads(L)) >= 2) { launch_y_sh<L, DIR, 1>(m, tw, ctrl); return; } break;
+        case 2: if constexpr ((256 / fft2_threads(L)) >= 4) { launch_y_sh<L, DIR, 2>(m, tw, ctrl); return; } break;
+        default: break;
+    }
+    launch_y_sh<L, DIR, col_shift_default(L)>(m, tw, ctrl);
+}
+template <int L, int SH>
+static void launch_zconv_sh(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    constexpr int TT = fft2_threads(L), NPB = (256 / TT) >> SH;
+    const int ncols = m->P2 * m->KP;
+    NM_LAUNCH(m, NM_PROF_CONV, (k_zconv_r<L, SH>), dim3((ncols + NPB - 1) / NPB), dim3(NPB * TT), 0, m->spec,
+              m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
 }
 template <int L>
 static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
-    const int ncols = m->P2 * m->KP;
     if constexpr (L <= 256) {
-        constexpr int NPB = 256 / fft2_threads(L);
-        NM_LAUNCH(m, NM_PROF_CONV, (k_zconv_r<L>), dim3((ncols + NPB - 1) / NPB), dim3(256), 0, m->spec,
-                  m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
+        switch (m->tune_z) {
+            case 1: if constexpr ((256 / fft2_threads(L)) >= 2) { launch_zconv_sh<L, 1>(m, tw, ctrl); return; } break;
+            case 2: if constexpr ((256 / fft2_threads(L)) >= 4) { launch_zconv_sh<L, 2>(m, tw, ctrl); return; } break;
+            default: break;
+        }
+        launch_zconv_sh<L, col_shift_default(L)>(m, tw, ctrl);
     } else {
         constexpr int TB = tb_triple(L);
+        const int ncols = m->P2 * m->KP;
         NM_LAUNCH(m, NM_PROF_CONV, (k_zconv<L, TB>), dim3((ncols + TB - 1) / TB), dim3(256), 0, m->spec,
                   m->tensor, tw, m->N3, m->P2, m->K1, m->KP, m->P2h, m->P3h, ctrl);
     }
@@ -654,6 +682,99 @@ static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl,
     }
     NM_DISPATCH_ROW(L1, launch_x_inv, m, tw, ctrl, src_mode);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ tile tuner
+// Block widths of the register-FFT passes, chosen per padded shape by timing
+// every width on the mesh itself (a warm-up and 5 launches each; the fastest
+// total wins) and cached per (P1, P2, P3, N2, N3, device).  Small meshes run
+// only a few dozen blocks per pass, where narrower blocks finish sooner;
+// large ones keep the widest.  Every width computes each column identically,
+// so the choice never changes results.
+namespace {
+struct TuneKey {
+    int p1, p2, p3, n2, n3, dev;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(p1, p2, p3, n2, n3, dev) < std::tie(o.p1, o.p2, o.p3, o.n2, o.n3, o.dev);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+template <int L>
+void launch_y_pair(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
+    launch_y<L, -1>(m, tw, ctrl);
+    launch_y<L, 1>(m, tw, ctrl);
+}
+
+int widths(int L) {   // how many of the shifts 0, 1, 2 exist for length L
+    const int npb = 256 / fft2_threads_host(L);
+    return npb >= 4 ? 3 : npb >= 2 ? 2 : 1;
+}
+}  // namespace
+
+hipError_t tune_passes(nm_mesh *m) {
+    m->tune_y = m->tune_z = 0;
+    if (m->N3 == 1) return hipSuccess;   // films use the fused y convolution
+    const TuneKey key{m->P1, m->P2, m->P3, m->N2, m->N3, m->device};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            m->tune_y = it->second.first;
+            m->tune_z = it->second.second;
+            return hipSuccess;
+        }
+    }
+    const float2 *tw = twiddles(m->device);
+    if (!tw) return hipErrorOutOfMemory;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto time_it = [&](auto run, float *ms) -> hipError_t {
+        hipError_t r = run();   // warm-up
+        if (r == hipSuccess) r = hipEventRecord(e0, m->stream);
+        for (int k = 0; k < 5 && r == hipSuccess; ++k) r = run();
+        if (r == hipSuccess) r = hipEventRecord(e1, m->stream);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
+        return r;
+    };
+    int best_y = 0, best_z = 0;
+    float ty = 1e30f, tz = 1e30f;
+    for (int v = 0; v < widths(m->P2) && e == hipSuccess; ++v) {
+        m->tune_y = v;
+        float ms = 0.f;
+        e = time_it([&]() -> hipError_t {
+            NM_DISPATCH_COL(m->P2, launch_y_pair, m, tw, nullptr);
+            return hipGetLastError();
+        }, &ms);
+        if (e == hipSuccess && ms < ty) {
+            ty = ms;
+            best_y = v;
+        }
+    }
+    if (m->P3 <= 256)
+        for (int v = 0; v < widths(m->P3) && e == hipSuccess; ++v) {
+            m->tune_z = v;
+            float ms = 0.f;
+            e = time_it([&]() -> hipError_t {
+                NM_DISPATCH_COL(m->P3, launch_zconv, m, tw, nullptr);
+                return hipGetLastError();
+            }, &ms);
+            if (e == hipSuccess && ms < tz) {
+                tz = ms;
+                best_z = v;
+            }
+        }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    m->tune_y = best_y;
+    m->tune_z = best_z;
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {best_y, best_z};
+    return hipSuccess;
 }
 
 hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode) {

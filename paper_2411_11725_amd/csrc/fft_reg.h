@@ -81,6 +81,7 @@ __host__ __device__ constexpr int fft2_l1(int L) {
 __host__ __device__ constexpr int fft2_threads(int L) {
     return fft2_l1(L) < L / fft2_l1(L) ? fft2_l1(L) : L / fft2_l1(L);
 }
+inline int fft2_threads_host(int L) { return fft2_threads(L); }
 
 // LDS copy tl[j] = exp(-2 pi i j / L), j < L (full period)
 template <int L, int NT>

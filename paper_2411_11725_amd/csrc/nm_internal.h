@@ -122,6 +122,8 @@ struct nm_mesh {
     // `stream`; captured on the private `cap_stream`
     hipStream_t cap_stream;
     hipGraphExec_t gexec;
+    // tile choices of the register-FFT passes (see the tuner)
+    int tune_y, tune_z;
     // recorded adjoint segment and its key
     hipGraphExec_t adj_gexec;
     int adj_nsteps, adj_every;
@@ -162,6 +164,7 @@ const float2 *twiddles(int device);   // per-device table (built at mesh creatio
 // src_mode 0: hd = H_d (cell field); 1: hd = mu0 Ms V/8 H_d; 2: hd = mu0 Ms V/8
 // (H_d + h_uniform + h_cell), the weighted source the node kernel gathers
 hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode);
+hipError_t tune_passes(nm_mesh *m);   // block widths of the register-FFT passes
 hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl,
                                            int src_mode);
 

@@ -84,3 +84,5 @@ def test_adjoint_and_server_reject_bad_arguments_on_the_host():
     assert L.nm_serve_poll(None, ctypes.c_uint64(1), ctypes.byref(res), None, 0) == binding.NM_EINVAL
     assert L.nm_server_destroy(None) == binding.NM_OK
     assert L.nm_profile_enable(None, 1) == binding.NM_EINVAL
+    y, z = ctypes.c_int(0), ctypes.c_int(0)
+    assert L.nm_mesh_tuning(None, 0, ctypes.byref(y), ctypes.byref(z)) == binding.NM_EINVAL

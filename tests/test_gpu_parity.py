@@ -177,6 +177,32 @@ def test_rk4_standard_cube_trajectory():
     assert abs(e_gpu["total"] - e_or["total"]) <= 1e-4 * abs(e_or["total"])
 
 
+@pytest.mark.parametrize("n", [(40, 24, 6), (130, 20, 3)])
+def test_every_tile_width_gives_the_same_field(n):
+    """The tuner's block widths of the y passes and the z convolution compute
+    each column identically: the field is bitwise the same for every width."""
+    p = synth.small_random(n, (2e-9, 2e-9, 3e-9), seed=50)
+    mesh = B.mesh_from_problem(p)
+    try:
+        chosen = B.nm_mesh_tuning(mesh)
+        assert all(0 <= w <= 2 for w in chosen)
+        m = _dev(p["m0"])
+        outs = []
+        for w in range(3):
+            assert B.nm_mesh_tuning(mesh, y=w, z=w) == (w, w)
+            h = torch.empty_like(m)
+            B.nm_heff(mesh, m, h, ALL_TERMS, 0.0)
+            torch.cuda.synchronize()
+            outs.append(h.cpu().numpy())
+        with pytest.raises(B.NMError):
+            B.nm_mesh_tuning(mesh, y=3)
+    finally:
+        B.nm_mesh_destroy(mesh)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    om, omat, om0 = to_oracle(p)
+    assert rel_l2(outs[0], oracle.heff(om, omat, om0, ALL_TERMS)) <= 1e-5
+
+
 def test_rk4_calls_queue_without_waiting_and_keep_the_clock():
     """RK4 calls return once queued: successive calls (a max_steps stop, then a
     shortened last step landing on t_end, then single steps with a drive in
