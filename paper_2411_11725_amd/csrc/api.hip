@@ -140,10 +140,12 @@ static size_t footprint(const Sizes &s) {
     return b;
 }
 
-static void drop_graph(nm_mesh *m) {
+// Destroy the recorded graphs.  wait: a replay may still be queued on the
+// mesh stream (RK4 calls return without waiting), so let it finish first;
+// callers that know the stream is idle pass false.
+static void drop_graph(nm_mesh *m, bool wait = true) {
     if (m->gexec) {
-        // a replay may still be queued (RK4 calls return without waiting)
-        (void)hipStreamSynchronize(m->stream);
+        if (wait) (void)hipStreamSynchronize(m->stream);
         (void)hipGraphExecDestroy(m->gexec);
     }
     m->gexec = nullptr;
@@ -153,19 +155,21 @@ static void drop_graph(nm_mesh *m) {
     m->g_batch = 0;
 }
 
-static void drop_adj_graph(nm_mesh *m) {
+static void drop_adj_graph(nm_mesh *m, bool wait = true) {
     if (m->adj_gexec) {
-        (void)hipStreamSynchronize(m->stream);
+        if (wait) (void)hipStreamSynchronize(m->stream);
         (void)hipGraphExecDestroy(m->adj_gexec);
     }
     m->adj_gexec = nullptr;
 }
 
+// the mesh's stream work must be complete (nm_mesh_destroy waits for it,
+// mesh_release callers guarantee it)
 static void free_mesh(nm_mesh *m) {
     if (!m) return;
     prof_free(m);
-    drop_graph(m);
-    drop_adj_graph(m);
+    drop_graph(m, false);
+    drop_adj_graph(m, false);
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,

@@ -581,9 +581,8 @@ static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl, int src
     NM_LAUNCH(m, NM_PROF_XINV, (k_xinv<L>), dim3((rows + RB - 1) / RB), dim3(256), 0, m->spec, m->hd,
               tw, m->N1, m->N2, m->N3, m->P2, m->KP, m->wc, m->wstat, src_mode, ctrl);
 }
-// block-width choice of the register-FFT passes (0: widest, 1: half, 2: quarter)
-__host__ __device__ constexpr int col_shift_default(int L) { return 0; }
-
+// block width of the register-FFT passes: the widest column tile shifted
+// right by SH (0 widest, 1 half, 2 quarter), chosen per mesh by tune_passes
 template <int L, int DIR, int SH>
 static void launch_y_sh(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     constexpr int TT = fft2_threads(L), NPB = (256 / TT) >> SH;
@@ -598,7 +597,7 @@ static void launch_y(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
         case 2: if constexpr ((256 / fft2_threads(L)) >= 4) { launch_y_sh<L, DIR, 2>(m, tw, ctrl); return; } break;
         default: break;
     }
-    launch_y_sh<L, DIR, col_shift_default(L)>(m, tw, ctrl);
+    launch_y_sh<L, DIR, 0>(m, tw, ctrl);
 }
 template <int L, int SH>
 static void launch_zconv_sh(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
@@ -615,7 +614,7 @@ static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
             case 2: if constexpr ((256 / fft2_threads(L)) >= 4) { launch_zconv_sh<L, 2>(m, tw, ctrl); return; } break;
             default: break;
         }
-        launch_zconv_sh<L, col_shift_default(L)>(m, tw, ctrl);
+        launch_zconv_sh<L, 0>(m, tw, ctrl);
     } else {
         constexpr int TB = tb_triple(L);
         const int ncols = m->P2 * m->KP;
