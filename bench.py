@@ -36,11 +36,15 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     # the block relaxation: 128 x 128 x 32 cells of 2 nm, alpha = 1, random Ku
     # and easy axes, DP45 rtol 1e-5
-    "block": dict(desc="3D block 128x128x32 cells (2 nm), alpha=1 relaxation, per-cell Ku, DP45 rtol 1e-5",
+    "block": dict(tag="block_128x128x32", desc="3D block 128x128x32 cells (2 nm), alpha=1 relaxation, per-cell Ku, DP45 rtol 1e-5",
                   make="block", terms=("exchange", "demag", "anisotropy"), dt0=1e-14),
-    "film": dict(desc="thin film 256x64x1 cells (3.9x3.9x3 nm), field step (-25,4,0) mT, DP45 rtol 1e-5",
+    # the same recipe at 256 x 256 x 64: the demag working set (~320 MB) no
+    # longer fits the 256 MB Infinity Cache
+    "block_large": dict(tag="block_256x256x64", desc="3D block 256x256x64 cells (2 nm), alpha=1 relaxation, per-cell Ku, DP45 rtol 1e-5",
+                        make="block_large", terms=("exchange", "demag", "anisotropy"), dt0=1e-14),
+    "film": dict(tag="film_256x64x1", desc="thin film 256x64x1 cells (3.9x3.9x3 nm), field step (-25,4,0) mT, DP45 rtol 1e-5",
                  make="film", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
-    "cube": dict(desc="16x16x4 cells (2 nm), random start, DP45 rtol 1e-5",
+    "cube": dict(tag="cube_16x16x4", desc="16x16x4 cells (2 nm), random start, DP45 rtol 1e-5",
                  make="standard_cube", terms=("exchange", "demag"), dt0=1e-14),
 }
 
@@ -69,10 +73,11 @@ def byte_model(n, pad, nn, has_anis, has_hcell, stage_reads):
     return out
 
 
-def counter_traffic(kernel):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if the
-    kernel source has not changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "counters_%s.md" % kernel)
+def counter_traffic(kernel, tag):
+    """HBM bytes per launch of one kernel on one workload from a committed
+    rocprofv3 counter summary, if the kernel source has not changed since the
+    counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters_%s_%s.md" % (kernel, tag))
     src = os.path.join(ROOT, "paper_2411_11725_amd", "csrc", "demag.hip" if kernel != "stencil" else "stencil.hip")
     if not os.path.exists(path):
         return None
@@ -274,7 +279,7 @@ def main():
         serving = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
                                 args.serve_active, args.serve_streams, args.serve_attempts)
     W = WORKLOADS[args.workload]
-    p = getattr(synth, W["make"])()
+    p = synth.block(n=(256, 256, 64)) if W["make"] == "block_large" else getattr(synth, W["make"])()
     tmask = {"exchange": B.NM_T_EXCHANGE, "demag": B.NM_T_DEMAG, "anisotropy": B.NM_T_ANIS,
              "zeeman": B.NM_T_ZEEMAN}
     terms = sum(tmask[t] for t in W["terms"])
@@ -319,7 +324,7 @@ def main():
                          "gbs": bm[slot] / avg_s / 1e9, "frac": bm[slot] / avg_s / 1e9 / HBM_PEAK_GBS}
     dom = max(kernels, key=lambda k: prof[k][0])
     ach = kernels[dom]["gbs"]
-    traffic = counter_traffic(dom)
+    traffic = counter_traffic(dom, W["tag"])
     B.nm_mesh_destroy(mesh)
 
     out = {

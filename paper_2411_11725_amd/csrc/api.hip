@@ -131,10 +131,10 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
 static size_t footprint(const Sizes &s) {
     size_t b = 0;
     b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive
-    b += sizeof(float) * s.nc * (4 + 3 + 1);                  // cellP, wstat, wdrive
+    b += sizeof(float) * s.nc * (4 + 4);                      // cellP, wstat
     b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
     b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
-    b += sizeof(float) * 3 * s.nc;                              // demag cell field
+    b += sizeof(float) * 4 * s.nc;                              // demag cell field / source
     b += sizeof(float) * 3 * s.nn * 10;                         // y[2], acc, k[7]
     b += sizeof(Ctrl) + sizeof(ErrPartial) * s.partials + sizeof(double) * (4 * s.eblocks + 4);
     return b;
@@ -173,7 +173,7 @@ static void free_mesh(nm_mesh *m) {
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
-                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat, m->wdrive};
+                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat};
     for (void *p : ptrs) dev_free(p, m->pool);
     for (int j = 0; j < 7; ++j) dev_free(m->k[j], m->pool);
     host_free(m->ctrl_host, m->pool);
@@ -265,8 +265,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess) e = dalloc(m, &m->wc, nc);
     if (e == hipSuccess) e = dalloc(m, &m->h_cell, 3 * nc);
     if (e == hipSuccess) e = dalloc(m, &m->cellP, nc);
-    if (e == hipSuccess) e = dalloc(m, &m->wstat, 3 * nc);
-    if (e == hipSuccess && m->has_drive) e = dalloc(m, &m->wdrive, nc);
+    if (e == hipSuccess) e = dalloc(m, &m->wstat, nc);
     if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->Ku, nc);
     if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->easy, 3 * nc);
     if (e == hipSuccess && m->has_drive) e = dalloc(m, &m->drive_mask, nc);
@@ -275,7 +274,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess) e = dalloc(m, &m->gp_n, nn);
     if (e == hipSuccess) e = dalloc(m, &m->spec, s.spec);
     if (e == hipSuccess) e = dalloc(m, &m->tensor, s.tensor);
-    if (e == hipSuccess) e = dalloc(m, &m->hd, 3 * nc);
+    if (e == hipSuccess) e = dalloc(m, &m->hd, 4 * nc);
     if (e == hipSuccess) e = dalloc(m, &m->y[0], 3 * nn);
     if (e == hipSuccess) e = dalloc(m, &m->y[1], 3 * nn);
     if (e == hipSuccess) e = dalloc(m, &m->acc, 3 * nn);

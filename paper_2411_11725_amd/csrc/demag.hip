@@ -124,7 +124,7 @@ template <int L>
 __global__ void __launch_bounds__(256)
 k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__restrict__ tw,
        int N1, int N2, int N3, int P2, int KP, const float *__restrict__ wc,
-       const float *__restrict__ wstat, int src_mode, const Ctrl *__restrict__ ctrl) {
+       const float4 *__restrict__ wstat, int src_mode, const Ctrl *__restrict__ ctrl) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
@@ -153,25 +153,26 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
             xc[i][c] = keep(cconj(rowp[L - k]), rok);
         }
     }
-    // output item (row ro, element no -> cells 2 no, 2 no + 1): only the first
-    // L / 2 elements of a row are cells (N1 <= P1 / 2), one per thread; its
-    // weights and static fields are fetched now, at clamped cells
-    static_assert(RB * L / 2 == 256, "one output element per thread");
-    const int ro = tid / (L / 2), no = tid - (tid / (L / 2)) * (L / 2);
-    const bool ook = row0 + ro < rows;
+    // output items (row, cell x): only the first L / 2 complex elements of a
+    // row are cells (N1 <= P1 / 2, element n holds cells 2n and 2n + 1), so
+    // a block has RB L cells, two per thread, consecutive cells on
+    // consecutive lanes; their weights and static fields are fetched now, at
+    // clamped cells
+    static_assert(RB * L == 512, "two output cells per thread");
     long long oi[2];
-    float wv[2], av[2][3];
-    {
-        const int rc = min(row0 + ro, rows - 1);
-        const long long cb = ((long long)(rc / N2) * N2 + rc % N2) * N1;
-        oi[0] = cb + min(2 * no, N1 - 1);
-        oi[1] = cb + min(2 * no + 1, N1 - 1);
+    int ol[2];
+    bool ook[2];
+    float wv[2];
+    float4 av[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            wv[h] = src_mode > 0 ? wc[oi[h]] : 1.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) av[h][c] = src_mode == 2 ? wstat[c * nc + oi[h]] : 0.f;
-        }
+    for (int h = 0; h < 2; ++h) {
+        const int it = tid + 256 * h;
+        const int rb = it / L, x = it - (it / L) * L;
+        ook[h] = row0 + rb < rows && x < N1;
+        oi[h] = (long long)min(row0 + rb, rows - 1) * N1 + min(x, N1 - 1);
+        ol[h] = rb * L + (x >> 1);
+        wv[h] = src_mode > 0 ? wc[oi[h]] : 1.f;
+        av[h] = src_mode == 2 ? wstat[oi[h]] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     load_twiddles<2 * L, 256>(tl, tw, tid);
     __syncthreads();
@@ -192,13 +193,24 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
     }
     __syncthreads();
     lds_fft<L, 1, NP, 256, false, 2 * L>(s, tl, tid);
-    if (!ook) return;
-    const int x0 = 2 * no;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float2 v = s[(c * RB + ro) * L + no];
-        if (x0 < N1) hd[c * nc + oi[0]] = wv[0] * v.x + av[0][c];
-        if (x0 + 1 < N1) hd[c * nc + oi[1]] = wv[1] * v.y + av[1][c];
+    for (int h = 0; h < 2; ++h) {
+        if (!ook[h]) continue;
+        const bool odd = (tid + 256 * h) & 1;   // L is even: the cell's parity
+        float v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 e = s[c * RB * L + ol[h]];
+            v[c] = odd ? e.y : e.x;
+        }
+        if (src_mode == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hd[c * nc + oi[h]] = v[c];
+        } else {
+            // the node kernel's source, one float4 per cell
+            reinterpret_cast<float4 *>(hd)[oi[h]] =
+                make_float4(wv[h] * v[0] + av[h].x, wv[h] * v[1] + av[h].y, wv[h] * v[2] + av[h].z, av[h].w);
+        }
     }
 }
 

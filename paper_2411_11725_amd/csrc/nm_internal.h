@@ -91,8 +91,7 @@ struct nm_mesh {
     float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;
     float *wc;               // mu0 Ms_c V / 8: weight of a cell-constant field
     float4 *cellP;           // packed per cell: {2A with the sign of Ku, sqrt|Ku| e}
-    float *wstat;            // 3 x nc: mu0 Ms V/8 (h_uniform + h_cell)
-    float *wdrive;           // mu0 Ms V/8 * drive mask (when a drive is set)
+    float4 *wstat;           // per cell: mu0 Ms V/8 {h_uniform + h_cell, drive mask}
     float h_uniform[3], drive_amp[3];
     double drive_freq, drive_phase;
     bool has_anis, has_hcell, has_drive;
@@ -104,7 +103,8 @@ struct nm_mesh {
     // demagnetisation
     float2 *spec;            // [3][N3][P2][KP] complex workspace
     float *tensor;           // [6][P3h][P2h][KP] real k-space tensor / (P1 P2 P3)
-    float *hd;               // [3][n_cells] demag cell field
+    float *hd;               // demag cell field: [3][n_cells] H_d, or the node
+                             // kernel's source, float4 [n_cells] (see demag_forward_conv_inverse)
     bool tensor_ready;
 
     // integrator buffers
@@ -161,8 +161,9 @@ const float2 *twiddles(int device);   // per-device table (built at mesh creatio
 
 // demag FFT pipeline: m (nodal, stage input) -> mesh->hd (cell field); the
 // ctrl variant skips its kernels once the device controller reports done
-// src_mode 0: hd = H_d (cell field); 1: hd = mu0 Ms V/8 H_d; 2: hd = mu0 Ms V/8
-// (H_d + h_uniform + h_cell), the weighted source the node kernel gathers
+// src_mode 0: hd = H_d, [3][n_cells]; 1 and 2: hd = the source the node kernel
+// gathers, one float4 per cell: {mu0 Ms V/8 H_d, 0} (1) or
+// {mu0 Ms V/8 (H_d + h_uniform + h_cell), mu0 Ms V/8 drive mask} (2)
 hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode);
 hipError_t tune_passes(nm_mesh *m);   // block widths of the register-FFT passes
 hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl,
@@ -194,7 +195,7 @@ dim3 stencil_grid(const nm_mesh *m);   // blocks of the fused node kernel
 hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]);
 hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
-hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat, wdrive from the raw copies
+hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat from the raw copies
 void mesh_release(nm_mesh *m);             // free a mesh whose stream work has completed
 hipError_t launch_rk4_advance(nm_mesh *m);
 

@@ -24,8 +24,11 @@ struct StencilParams {
     float Kp[8], Mp[8];
     // node kernel: packed cell data and the pre-weighted cell-field source
     const float4 *cellP;           // {2A with the sign bit of Ku, sqrt|Ku| e}
-    const float *src;              // 3 x nc: mu0 Ms V/8 (H_d [+ static H_ext]) or NULL
-    const float *wdrive;           // mu0 Ms V/8 * drive mask, or NULL
+    // {mu0 Ms V/8 (H_d [+ static H_ext]), mu0 Ms V/8 drive mask} per cell, or NULL
+    const float4 *src;
+    int drive;                     // add the drive (the w component times sin and its amplitude)
+    int W;                         // LDS window length per z offset: 256 + 2 NX + 2
+    float rNX, rNY;                // 1 / NX, 1 / NY
     // energy kernel: raw cell data
     const float *wc, *A2, *Ku, *easy, *hcell, *dmask, *hd;
     float hu[3], damp[3];
@@ -83,28 +86,29 @@ __device__ __forceinline__ void llg_rhs(const float m[3], const float H[3], floa
     f[2] = -gp * c2 - ag * d2;
 }
 
-// block reduction of the DP45 error partials (256 threads = 4 waves)
+// block reduction of the DP45 error partials (256 threads = 4 waves): within
+// each wave by lane exchanges, then the 4 wave results through LDS
 __device__ __forceinline__ void reduce_partial(double sq, float mf, int nf, ErrPartial *out) {
-    __shared__ double s_sq[256];
-    __shared__ float s_mf[256];
-    __shared__ int s_nf[256];
-    const int t = threadIdx.x;
-    s_sq[t] = sq;
-    s_mf[t] = mf;
-    s_nf[t] = nf;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) {
-            s_sq[t] += s_sq[t + w];
-            s_mf[t] = fmaxf(s_mf[t], s_mf[t + w]);
-            s_nf[t] |= s_nf[t + w];
-        }
-        __syncthreads();
+    __shared__ double s_sq[4];
+    __shared__ float s_mf[4];
+    __shared__ int s_nf[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sq += __shfl_xor(sq, o, 64);
+        mf = fmaxf(mf, __shfl_xor(mf, o, 64));
+        nf |= __shfl_xor(nf, o, 64);
     }
+    const int t = threadIdx.x, w = t >> 6;
+    if ((t & 63) == 0) {
+        s_sq[w] = sq;
+        s_mf[w] = mf;
+        s_nf[w] = nf;
+    }
+    __syncthreads();
     if (t == 0) {
-        out->sumsq = s_sq[0];
-        out->maxf = s_mf[0];
-        out->nonfinite = s_nf[0];
+        out->sumsq = (s_sq[0] + s_sq[1]) + (s_sq[2] + s_sq[3]);
+        out->maxf = fmaxf(fmaxf(s_mf[0], s_mf[1]), fmaxf(s_mf[2], s_mf[3]));
+        out->nonfinite = s_nf[0] | s_nf[1] | s_nf[2] | s_nf[3];
     }
 }
 
@@ -112,27 +116,55 @@ __device__ __forceinline__ void reduce_partial(double sq, float mf, int nf, ErrP
 // corner the node is at local index i (0/1) along that axis?
 __host__ __device__ constexpr bool shares(int d, int i) { return d == 0 || (d == 1 && i == 0) || (d == -1 && i == 1); }
 
-// One thread per node (consecutive nodes along x).  All loads (27 neighbour
-// values per component, one packed float4 and the cell-field source per
-// cell, the epilogue operands) are issued before any arithmetic, at clamped
-// addresses with zero weights for whatever lies outside the mesh, so a thread
-// waits for one memory round trip.  The exchange sum is taken per neighbour:
-// neighbour d of node n is weighted by K^e at the axis-difference pattern of d
-// times the sum of 2A over the cells containing both (4 cells for a face
-// neighbour, 2 for an edge, 1 for a corner), which is the cell-by-cell sum
-// regrouped.  The stage is a template parameter so every tableau coefficient
-// is a compile-time constant.  The kernel is bound by VALU issue; a target of
-// two waves per SIMD (up to 256 VGPRs) keeps the neighbourhood, cell data and
-// epilogue operands in registers with all loads issued at once, where a
-// three-wave target spills and splits the loads (about 25 vs 32 us per launch
-// on a 128 x 128 x 32 block).
-template <int MODE, int STAGE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// q = floor(a / d) for 0 <= a < 2^20 from a float reciprocal rd ~ 1/d: the
+// product is exact or one step low (never high: a / d is at least 1/a away
+// from the next integer above it), so one correction suffices
+__device__ __forceinline__ int small_div(int a, int d, float rd) {
+    int q = (int)((float)a * rd);
+    if (a - q * d >= d) ++q;
+    return q;
+}
+
+// One thread per node (consecutive nodes along x, 256 per block).
+//
+// Neighbourhood.  With NIT > 0 the block first copies the m values it needs
+// into LDS: for each z offset dz in {-1, 0, 1}, the nodes whose linear index
+// lies within NX + 1 of (a node of the block + dz NX NY), a window of
+// W = 256 + 2 NX + 2 nodes, stored as float4 {m_x, m_y, m_z, 0}; NIT items of
+// the 3W per thread, read at clamped indices.  The neighbour at offsets
+// (dx, dy, dz) of the block's thread t then sits at (dz + 1) W + t + NX + 1 +
+// dy NX + dx.  Every value is fetched from the caches once per block instead
+// of by each of its 27 readers.  With NIT = 0 (rows too long for the window)
+// every thread reads its 27 neighbours itself, at clamped indices.  A
+// neighbour outside the mesh only enters through cells outside it, whose
+// weight is 0, so whatever finite value its slot holds is harmless.
+//
+// Exchange is summed per neighbour d: m_d - m_n weighted by K^e at the
+// axis-difference pattern of d times the sum of 2A over the cells holding
+// both nodes (4 for a face neighbour, 2 for an edge, 1 for a corner), the
+// cell-by-cell sum regrouped.  The Q1 mass matrix of a cuboid is a tensor
+// product, M^e_ab = M^e(all axes differ) prod_k (2 if a_k = b_k else 1), so
+// the anisotropy sum over the nodes b of cell q, sum_b M^e_ab (m_b . u_q), is
+// u_q . S_q with S_q built by weighted pair sums along x, then y, then z;
+// neighbouring cells share the partial sums.
+//
+// Loads are issued before any arithmetic, at clamped addresses with zero
+// weights (a branch around a load makes each load its own round trip), the
+// window loads first so that the LDS copy waits for them alone.  The stage
+// is a template parameter, so every tableau coefficient is a compile-time
+// constant.
+#ifndef NM_NODE_WAVES
+#define NM_NODE_WAVES 3
+#endif
+template <int MODE, int STAGE, int NIT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
 k_node(StencilParams P, StageArgs S) {
     // consecutive node ranges on one XCD: the halo rows of a block were
     // fetched into that XCD's L2 by its neighbours
     const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    const unsigned n = lb * 256u + threadIdx.x;
+    const int tid = (int)threadIdx.x;
+    const int n0 = (int)lb * 256;
+    const int n = n0 + tid;
     double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
     constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE)
@@ -145,188 +177,271 @@ k_node(StencilParams P, StageArgs S) {
         dt = S.dt0;
         t = S.t0 + cst * dt;
     }
-    const long long nn = P.nn;
-    const bool valid = n < (unsigned)nn;
-    const unsigned on = n * 4u;   // byte offset of node n in one component
+    const int nn = (int)P.nn;
+    const int NX = P.NX, NY = P.NY, NZ = P.NZ, W = P.W;
+    const float *in0 = S.in, *in1 = S.in + nn, *in2 = S.in + 2 * nn;
+
+    // ---- LDS window of the stage input (issued first)
+    __shared__ float4 sw[NIT > 0 ? NIT * 256 : 1];
+    float wv[NIT > 0 ? NIT : 1][3];
+    if constexpr (NIT > 0) {
+        const int D = NX * NY - W;                 // window p starts at n0 - NX - 1 + (p - 1) NX NY
+        const int g0 = n0 - NX - 1 - NX * NY;      // = that start minus p W
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int j = tid + 256 * it;
+            const int g = min(max(g0 + j + (j >= W ? D : 0) + (j >= 2 * W ? D : 0), 0), nn - 1);
+            wv[it][0] = ldo(in0, 4u * (unsigned)g);
+            wv[it][1] = ldo(in1, 4u * (unsigned)g);
+            wv[it][2] = ldo(in2, 4u * (unsigned)g);
+        }
+    }
+
+    // every thread computes (threads past the last node on the last one) so
+    // that the whole block reaches the barrier; only real nodes store
+    const bool valid = n < nn;
+    const unsigned on = (unsigned)min(n, nn - 1) * 4u;   // byte offset of the node in one component
+    const unsigned oc[3] = {on, on + 4u * (unsigned)nn, on + 8u * (unsigned)nn};
     constexpr int NK = MODE == kModeDP45 ? (STAGE > 1 ? STAGE - 1 : 1) : 1;
     float ms[3] = {0.f, 0.f, 0.f}, ac[3] = {0.f, 0.f, 0.f}, kk[NK][3];
-    double sq = 0.0;
-    float mf = 0.f;
-    int nf = 0;
-    if (valid) {
-        // ---- epilogue operands
-        if (MODE == kModeRK4 || MODE == kModeDP45 || (MODE == kModeAdjFwd && STAGE < 4)) {
+    // ---- epilogue operands
+    if (MODE == kModeRK4 || MODE == kModeDP45 || (MODE == kModeAdjFwd && STAGE < 4)) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ms[c] = ldo(S.mstate + c * nn, on);
+        for (int c = 0; c < 3; ++c) ms[c] = ldo(S.mstate, oc[c]);
+    }
+    if (MODE == kModeRK4 && STAGE > 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ac[c] = ldo(S.acc, oc[c]);
+    }
+    if (MODE == kModeDP45) {
+#pragma unroll
+        for (int j = 0; j < NK; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                kk[j][c] = (j < STAGE - 1 && dp_w(STAGE, j + 1) != 0.0) ? ldo(S.k[j], oc[c]) : 0.f;
+    }
+    // ---- per-node coefficients
+    const float im = ldo(P.inv_mass, on);
+    float gp = 0.f, al = 0.f;
+    if (MODE != kModeField) {
+        gp = ldo(P.gp_n, on);
+        al = ldo(P.alpha_n, on);
+    }
+    // ---- node coordinates from the block's first node (threads past the
+    // end are moved onto the last plane)
+    int x, y, z;
+    {
+        const int x0 = n0 % NX, r0 = n0 / NX;
+        const int y0 = r0 % NY, z0 = r0 / NY;
+        const int q1 = small_div(x0 + tid, NX, P.rNX);
+        x = x0 + tid - q1 * NX;
+        const int q2 = small_div(y0 + q1, NY, P.rNY);
+        y = y0 + q1 - q2 * NY;
+        z = min(z0 + q2, NZ - 1);
+    }
+    // ---- the 8 cells around the node, q = i1 + 2 i2 + 4 i3 for the cell
+    // (x - i1, y - i2, z - i3), at clamped indices with weight cw = 0
+    // outside the mesh
+    float cw[8];
+    unsigned co[8];
+    float4 cp[8], cs[8];
+    {
+        const int N1 = P.N1, N2 = P.N2, N3 = P.N3;
+        const unsigned ox[2] = {(unsigned)min(x, N1 - 1), (unsigned)max(x - 1, 0)};
+        const unsigned oy[2] = {(unsigned)min(y, N2 - 1) * (unsigned)N1, (unsigned)max(y - 1, 0) * (unsigned)N1};
+        const unsigned oz[2] = {(unsigned)min(z, N3 - 1) * (unsigned)(N1 * N2),
+                                (unsigned)min(max(z - 1, 0), N3 - 1) * (unsigned)(N1 * N2)};
+        const float fx[2] = {x < N1 ? 1.f : 0.f, x > 0 ? 1.f : 0.f};
+        const float fy[2] = {y < N2 ? 1.f : 0.f, y > 0 ? 1.f : 0.f};
+        const float fz[2] = {z < N3 ? 1.f : 0.f, z > 0 ? 1.f : 0.f};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i1 = q & 1, i2 = (q >> 1) & 1, i3 = q >> 2;
+            co[q] = 16u * (oz[i3] + oy[i2] + ox[i1]);
+            cw[q] = fx[i1] * fy[i2] * fz[i3];
+            cp[q] = ldo(P.cellP, co[q]);
         }
-        if (MODE == kModeRK4 && STAGE > 1) {
+    }
+    if (P.src) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ac[c] = ldo(S.acc + c * nn, on);
+        for (int q = 0; q < 8; ++q) cs[q] = ldo(P.src, co[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) cs[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // ---- neighbourhood
+    float v[NIT > 0 ? 1 : 27][3];
+    int lrow[9];
+    if constexpr (NIT > 0) {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int j = tid + 256 * it;
+            if (j < 3 * W) sw[j] = make_float4(wv[it][0], wv[it][1], wv[it][2], 0.f);
         }
-        if (MODE == kModeDP45) {
+        // row starts (dx = -1) of the 9 (dz, dy) neighbour rows in the window
 #pragma unroll
-            for (int j = 0; j < NK; ++j)
+        for (int k = 0; k < 9; ++k) lrow[k] = tid + NX + (k / 3) * W + (k % 3 - 1) * NX;
+        __syncthreads();
+    } else {
+        int cx[3], cy[3], cz[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    kk[j][c] = (j < STAGE - 1 && dp_w(STAGE, j + 1) != 0.0) ? ldo(S.k[j] + c * nn, on) : 0.f;
+        for (int d = 0; d < 3; ++d) {
+            cx[d] = min(max(x + d - 1, 0), NX - 1);
+            cy[d] = min(max(y + d - 1, 0), NY - 1) * NX;
+            cz[d] = min(max(z + d - 1, 0), NZ - 1) * NX * NY;
         }
-        // ---- per-node coefficients
-        const float im = ldo(P.inv_mass, on);
-        float gp = 0.f, al = 0.f;
-        if (MODE != kModeField) {
-            gp = ldo(P.gp_n, on);
-            al = ldo(P.alpha_n, on);
-        }
-        // ---- neighbourhood of m at clamped indices (a neighbour outside the
-        // mesh only enters through cells outside it, whose weight is zero)
-        const int NX = P.NX, NY = P.NY;
-        const int x = (int)(n % (unsigned)NX);
-        const unsigned r = n / (unsigned)NX;
-        const int y = (int)(r % (unsigned)NY);
-        const int z = (int)(r / (unsigned)NY);
-        unsigned xo[3], ro[9];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) xo[d] = 4u * (unsigned)min(max(x + d - 1, 0), NX - 1);
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-                ro[dz * 3 + dy] = 4u * ((unsigned)min(max(z + dz - 1, 0), P.NZ - 1) * (unsigned)NY +
-                                        (unsigned)min(max(y + dy - 1, 0), NY - 1)) * (unsigned)NX;
-        const float *in0 = S.in, *in1 = S.in + nn, *in2 = S.in + 2 * nn;
-        float v[27][3];
 #pragma unroll
         for (int k = 0; k < 27; ++k) {
-            const unsigned o = ro[k / 3] + xo[k % 3];
+            const unsigned o = 4u * (unsigned)(cz[k / 9] + cy[(k / 3) % 3] + cx[k % 3]);
             v[k][0] = ldo(in0, o);
             v[k][1] = ldo(in1, o);
             v[k][2] = ldo(in2, o);
         }
-        // ---- the 8 cells around the node, q = i1 + 2 i2 + 4 i3 for the cell
-        // (x - i1, y - i2, z - i3), at clamped indices with weight cw = 0
-        // outside the mesh
-        unsigned co[8];
-        float cw[8];
-        float4 cp[8];
+    }
+    // neighbour (dx, dy, dz) = (k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1)
+    auto nb = [&](int k) -> float4 {
+        if constexpr (NIT > 0)
+            return sw[lrow[k / 3] + k % 3];
+        else
+            return make_float4(v[k][0], v[k][1], v[k][2], 0.f);
+    };
+
+    float r0 = 0.f, r1 = 0.f, r2 = 0.f, wd = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int cx = x - (q & 1), cy = y - ((q >> 1) & 1), cz = z - (q >> 2);
-            const bool inside = cx >= 0 && cx < P.N1 && cy >= 0 && cy < P.N2 && cz >= 0 && cz < P.N3;
-            co[q] = 4u * (((unsigned)min(max(cz, 0), P.N3 - 1) * (unsigned)P.N2 +
-                           (unsigned)min(max(cy, 0), P.N2 - 1)) * (unsigned)P.N1 +
-                          (unsigned)min(max(cx, 0), P.N1 - 1));
-            cw[q] = inside ? 1.f : 0.f;
-            cp[q] = ldo(P.cellP, 4u * co[q]);
-        }
-        float r0 = 0.f, r1 = 0.f, r2 = 0.f;
-        if (P.src) {
-            const float *s0 = P.src, *s1 = P.src + P.nc, *s2 = P.src + 2 * P.nc;
+    for (int q = 0; q < 8; ++q) {
+        r0 += cw[q] * cs[q].x;
+        r1 += cw[q] * cs[q].y;
+        r2 += cw[q] * cs[q].z;
+        wd += cw[q] * cs[q].w;
+    }
+    if (P.drive) {
+        wd *= (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
+        r0 += wd * P.damp[0];
+        r1 += wd * P.damp[1];
+        r2 += wd * P.damp[2];
+    }
+    const float4 mn = nb(13);
+    const bool ex = P.terms & NM_T_EXCHANGE;
+    const bool an = (P.terms & NM_T_ANIS) != 0;
+    // cp = {2A carrying the sign of Ku, u = sqrt|Ku| e}
+    float a2[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                r0 += cw[q] * ldo(s0, co[q]);
-                r1 += cw[q] * ldo(s1, co[q]);
-                r2 += cw[q] * ldo(s2, co[q]);
-            }
-        }
-        if (P.wdrive) {
-            const float sdrive = (float)sin(2.0 * 3.14159265358979323846 * P.dfreq * t + P.dphase);
-            float wd = 0.f;
+    for (int q = 0; q < 8; ++q) a2[q] = cw[q] * fabsf(cp[q].x);
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+    // anisotropy partial sums: S[q] = sum_b 2^(3 - #differing axes) m_b over cell q
+    float3 Sq[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) wd += cw[q] * ldo(P.wdrive, co[q]);
-            wd *= sdrive;
-            r0 += wd * P.damp[0];
-            r1 += wd * P.damp[1];
-            r2 += wd * P.damp[2];
-        }
-        const float mn[3] = {v[13][0], v[13][1], v[13][2]};
-        const bool ex = P.terms & NM_T_EXCHANGE;
-        const bool an = (P.terms & NM_T_ANIS) != 0;
-        float g0 = 0.f, g1 = 0.f, g2 = 0.f;
-        // cp = {2A carrying the sign of Ku, u = sqrt|Ku| e}
-        float a2[8];
+    for (int q = 0; q < 8; ++q) Sq[q] = make_float3(0.f, 0.f, 0.f);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a2[q] = cw[q] * fabsf(cp[q].x);
+    for (int dz = -1; dz <= 1; ++dz) {
+        float4 vb[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) vb[k] = nb((dz + 1) * 9 + k);
         if (ex) {
 #pragma unroll
-            for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-                for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0 && dz == 0) continue;
+                    float as = 0.f;
 #pragma unroll
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        if (dx == 0 && dy == 0 && dz == 0) continue;
-                        float as = 0.f;
-#pragma unroll
-                        for (int q = 0; q < 8; ++q)
-                            if (shares(dx, q & 1) && shares(dy, (q >> 1) & 1) && shares(dz, q >> 2)) as += a2[q];
-                        const int mask = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2);
-                        const int k = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-                        const float w = as * P.Kp[mask];
-                        g0 += w * (v[k][0] - mn[0]);
-                        g1 += w * (v[k][1] - mn[1]);
-                        g2 += w * (v[k][2] - mn[2]);
-                    }
+                    for (int q = 0; q < 8; ++q)
+                        if (shares(dx, q & 1) && shares(dy, (q >> 1) & 1) && shares(dz, q >> 2)) as += a2[q];
+                    const int mask = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2);
+                    const float w = as * P.Kp[mask];
+                    const float4 b = vb[(dy + 1) * 3 + dx + 1];
+                    g0 += w * (b.x - mn.x);
+                    g1 += w * (b.y - mn.y);
+                    g2 += w * (b.z - mn.z);
+                }
         }
         if (an) {
+            // x pairs of the three rows: cell side i1 = 0 pairs x with x + 1, i1 = 1 with x - 1
+            float3 tx[2][3];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int i1 = q & 1, i2 = (q >> 1) & 1, i3 = q >> 2;
-                float sp = 0.f;
+            for (int r = 0; r < 3; ++r)
 #pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    const int b1 = b & 1, b2 = (b >> 1) & 1, b3 = b >> 2;
-                    const int mask = (i1 ^ b1) | ((i2 ^ b2) << 1) | ((i3 ^ b3) << 2);
-                    const int k = (b3 - i3 + 1) * 9 + (b2 - i2 + 1) * 3 + (b1 - i1 + 1);
-                    sp += P.Mp[mask] * (v[k][0] * cp[q].y + v[k][1] * cp[q].z + v[k][2] * cp[q].w);
+                for (int i1 = 0; i1 < 2; ++i1) {
+                    const float4 c = vb[r * 3 + 1], o = vb[r * 3 + (i1 ? 0 : 2)];
+                    tx[i1][r] = make_float3(2.f * c.x + o.x, 2.f * c.y + o.y, 2.f * c.z + o.z);
                 }
-                // -2 Ku e (sum M m . e) = -2 sign(Ku) u (sum M m . u)
-                const float f2 = signbit(cp[q].x) ? -2.f * cw[q] * sp : 2.f * cw[q] * sp;
-                g0 -= f2 * cp[q].y;
-                g1 -= f2 * cp[q].z;
-                g2 -= f2 * cp[q].w;
-            }
+#pragma unroll
+            for (int i1 = 0; i1 < 2; ++i1)
+#pragma unroll
+                for (int i2 = 0; i2 < 2; ++i2) {
+                    const float3 c = tx[i1][1], o = tx[i1][i2 ? 0 : 2];
+                    const float3 ty = make_float3(2.f * c.x + o.x, 2.f * c.y + o.y, 2.f * c.z + o.z);
+                    const int q0 = i1 + 2 * i2, q1 = q0 + 4;   // cells below (i3 = 0) / above (i3 = 1)
+                    if (dz == -1) {
+                        Sq[q1] = ty;
+                    } else if (dz == 0) {
+                        Sq[q1] = make_float3(Sq[q1].x + 2.f * ty.x, Sq[q1].y + 2.f * ty.y, Sq[q1].z + 2.f * ty.z);
+                        Sq[q0] = make_float3(2.f * ty.x, 2.f * ty.y, 2.f * ty.z);
+                    } else {
+                        Sq[q0] = make_float3(Sq[q0].x + ty.x, Sq[q0].y + ty.y, Sq[q0].z + ty.z);
+                    }
+                }
         }
-        const float H[3] = {(r0 - g0) * im, (r1 - g1) * im, (r2 - g2) * im};
-        float f[3] = {0.f, 0.f, 0.f};
-        if (MODE != kModeField) llg_rhs(mn, H, gp, al, f);
+    }
+    if (an) {
+        const float m7 = P.Mp[7];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            // -2 Ku e (sum M m . e) = -2 sign(Ku) u (sum M m . u)
+            const float dot = cp[q].y * Sq[q].x + cp[q].z * Sq[q].y + cp[q].w * Sq[q].z;
+            const float f2 = (signbit(cp[q].x) ? -2.f : 2.f) * m7 * cw[q] * dot;
+            g0 -= f2 * cp[q].y;
+            g1 -= f2 * cp[q].z;
+            g2 -= f2 * cp[q].w;
+        }
+    }
+    const float mv[3] = {mn.x, mn.y, mn.z};
+    const float H[3] = {(r0 - g0) * im, (r1 - g1) * im, (r2 - g2) * im};
+    float f[3] = {0.f, 0.f, 0.f};
+    if (MODE != kModeField) llg_rhs(mv, H, gp, al, f);
+    double sq = 0.0;
+    float mf = 0.f;
+    int nf = 0;
+    if (valid) {
         if (MODE == kModeField) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sto(S.out + c * nn, on, H[c]);
+            for (int c = 0; c < 3; ++c) sto(S.out, oc[c], H[c]);
         } else if (MODE == kModeAdjFwd) {
             // H(y_s) for the reverse sweep, y_{s+1} = m + c_{s+1} dt f_s
             const float cy = (float)(dt * (STAGE == 3 ? 1.0 : 0.5));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sto(S.out + c * nn, on, H[c]);
-                if (STAGE < 4) sto(S.y_next + c * nn, on, ms[c] + cy * f[c]);
+                sto(S.out, oc[c], H[c]);
+                if (STAGE < 4) sto(S.y_next, oc[c], ms[c] + cy * f[c]);
             }
         } else if (MODE == kModeRhs) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sto(S.out + c * nn, on, f[c]);
+            for (int c = 0; c < 3; ++c) sto(S.out, oc[c], f[c]);
         } else if (MODE == kModeRK4) {
             const float cy = (float)(dt * (STAGE == 3 ? 1.0 : 0.5));
             const float c6 = (float)(dt / 6.0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (STAGE == 4) {
-                    sto(S.mstate + c * nn, on, ms[c] + c6 * (ac[c] + f[c]));
+                    sto(S.mstate, oc[c], ms[c] + c6 * (ac[c] + f[c]));
                 } else {
-                    sto(S.acc + c * nn, on, STAGE == 1 ? f[c] : ac[c] + 2.f * f[c]);
-                    sto(S.y_next + c * nn, on, ms[c] + cy * f[c]);
+                    sto(S.acc, oc[c], STAGE == 1 ? f[c] : ac[c] + 2.f * f[c]);
+                    sto(S.y_next, oc[c], ms[c] + cy * f[c]);
                 }
             }
         } else {  // DP45: store k_s, then y_{s+1} or (s = 7) the scaled error
             float fn2 = 0.f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                sto(S.k[STAGE - 1] + c * nn, on, f[c]);
+                sto(S.k[STAGE - 1], oc[c], f[c]);
                 float acc = (float)(dt * dp_w(STAGE, STAGE)) * f[c];
 #pragma unroll
                 for (int j = 0; j < STAGE - 1; ++j)
                     if (dp_w(STAGE, j + 1) != 0.0) acc += (float)(dt * dp_w(STAGE, j + 1)) * kk[j][c];
                 if (STAGE < 7) {
-                    sto(S.y_next + c * nn, on, ms[c] + acc);
+                    sto(S.y_next, oc[c], ms[c] + acc);
                 } else {
-                    const float yn = mn[c];
+                    const float yn = mv[c];
                     const double sct = C->atol + C->rtol * fmax(fabs((double)ms[c]), fabs((double)yn));
                     const double rr = (double)acc / sct;
                     if (im > 0.f) sq += rr * rr;
@@ -552,8 +667,12 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     P.cellP = m->cellP;
     // source of the node kernel: the demag pass writes mu0 Ms V/8 (H_d [+ static
     // H_ext]) into hd; without demag the static Zeeman part is read directly
-    P.src = (terms & NM_T_DEMAG) ? m->hd : ((terms & NM_T_ZEEMAN) ? m->wstat : nullptr);
-    P.wdrive = ((terms & NM_T_ZEEMAN) && m->has_drive) ? m->wdrive : nullptr;
+    P.src = (terms & NM_T_DEMAG) ? reinterpret_cast<const float4 *>(m->hd)
+                                 : ((terms & NM_T_ZEEMAN) ? m->wstat : nullptr);
+    P.drive = ((terms & NM_T_ZEEMAN) && m->has_drive) ? 1 : 0;
+    P.W = 256 + 2 * m->NX + 2;
+    P.rNX = 1.f / (float)m->NX;
+    P.rNY = 1.f / (float)m->NY;
     P.wc = m->wc;
     P.A2 = m->A2;
     P.Ku = m->has_anis ? m->Ku : nullptr;
@@ -574,9 +693,22 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     return P;
 }
 
+// window items per thread: the smallest of 5, 7, 10, 13 covering 3 W; rows
+// longer than that (NX > 425) read their neighbours directly
+static int window_items(int NX) {
+    const int need = (3 * (256 + 2 * NX + 2) + 255) / 256;
+    return need <= 5 ? 5 : need <= 7 ? 7 : need <= 10 ? 10 : need <= 13 ? 13 : 0;
+}
+
 template <int MODE, int STAGE>
 static void launch_node(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
-    NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE>), grid, dim3(256), 0, P, S);
+    switch (window_items(m->NX)) {
+        case 5: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 5>), grid, dim3(256), 0, P, S); break;
+        case 7: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 7>), grid, dim3(256), 0, P, S); break;
+        case 10: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 10>), grid, dim3(256), 0, P, S); break;
+        case 13: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 13>), grid, dim3(256), 0, P, S); break;
+        default: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 0>), grid, dim3(256), 0, P, S); break;
+    }
 }
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
@@ -666,8 +798,7 @@ __global__ void k_cell_pack(const float *__restrict__ A2, const float *__restric
                             const float *__restrict__ easy, const float *__restrict__ wc,
                             const float *__restrict__ hcell, const float *__restrict__ dmask,
                             float hu0, float hu1, float hu2, float4 *__restrict__ cellP,
-                            float *__restrict__ wstat,
-                            float *__restrict__ wdrive, long long nc) {
+                            float4 *__restrict__ wstat, long long nc) {
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
     if (c >= nc) return;
     float u0 = 0.f, u1 = 0.f, u2 = 0.f, k = 0.f;
@@ -688,10 +819,7 @@ __global__ void k_cell_pack(const float *__restrict__ A2, const float *__restric
         h1 += hcell[nc + c];
         h2 += hcell[2 * nc + c];
     }
-    wstat[c] = w * h0;
-    wstat[nc + c] = w * h1;
-    wstat[2 * nc + c] = w * h2;
-    if (dmask) wdrive[c] = w * dmask[c];
+    wstat[c] = make_float4(w * h0, w * h1, w * h2, dmask ? w * dmask[c] : 0.f);
 }
 
 hipError_t launch_cell_pack(nm_mesh *m) {
@@ -699,7 +827,7 @@ hipError_t launch_cell_pack(nm_mesh *m) {
     hipLaunchKernelGGL(k_cell_pack, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, m->stream, m->A2,
                        m->has_anis ? m->Ku : nullptr, m->easy, m->wc, m->has_hcell ? m->h_cell : nullptr,
                        m->has_drive ? m->drive_mask : nullptr, m->h_uniform[0], m->h_uniform[1],
-                       m->h_uniform[2], m->cellP, m->wstat, m->wdrive, nc);
+                       m->h_uniform[2], m->cellP, m->wstat, nc);
     return hipGetLastError();
 }
 
