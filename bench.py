@@ -49,8 +49,17 @@ WORKLOADS = {
 }
 
 
-def byte_model(n, pad, nn, has_anis, has_hcell, stage_reads):
-    """Algorithmic bytes per launch of each kernel slot (inputs + outputs once)."""
+# DP45 node-kernel launches per accepted step run stages 2..7 (the first
+# stage of a step is the last of the one before): stage s writes k_s and,
+# below 7, y_{s+1}, and reads the earlier k_j with non-zero weights
+# (1, 2, 3, 4, 4, 5 of them)
+DP45_WRITES = 11.0 / 6.0
+DP45_READS = 19.0 / 6.0
+
+
+def byte_model(n, pad, nn, zeeman, stage_writes=DP45_WRITES, stage_reads=DP45_READS):
+    """Algorithmic bytes per launch of each kernel slot (inputs + outputs once).
+    zeeman: the static applied field is part of the cell-field source."""
     n1, n2, n3 = n
     p1, p2, p3 = pad
     k1 = p1 // 2 + 1
@@ -66,10 +75,14 @@ def byte_model(n, pad, nn, has_anis, has_hcell, stage_reads):
     else:
         tensor = 4 * (p2 // 2 + 1) * k1 * 4
         out["conv"] = 2 * 3 * n2 * k1 * c8 + tensor
-    out["xinv"] = 3 * n3 * n2 * k1 * c8 + 12 * nc
-    cell = 12 * nc + 8 * nc + (16 * nc if has_anis else 0) + (12 * nc if has_hcell else 0)
-    # stage input, state, node coefficients, k_s and y_{s+1} written, earlier k_j read
-    out["stencil"] = cell + 12 * nn * (1 + 1 + 1 + 2) + 12 * nn * stage_reads
+    # spectrum rows in, cell weight in, one float4 source per cell out (plus
+    # the static Zeeman float4 in when the field has one)
+    out["xinv"] = 3 * n3 * n2 * k1 * c8 + 4 * nc + 16 * nc + (16 * nc if zeeman else 0)
+    # per cell: packed {2A, u} and the float4 source; per node: stage input,
+    # state, coefficients (1/M, gamma', alpha), the stage outputs written,
+    # earlier k_j read
+    cell = 16 * nc + 16 * nc
+    out["stencil"] = cell + 12 * nn * (1 + 1 + 1 + stage_writes + stage_reads)
     return out
 
 
@@ -313,8 +326,7 @@ def main():
     prof = B.nm_profile_read(mesh)
     B.nm_profile_enable(mesh, False)
 
-    # DP45 stages read on average ~2.7 earlier k_j in the epilogue
-    bm = byte_model(p["n"], pad, nn, p["Ku"] is not None, p["h_cell"] is not None, 2.7)
+    bm = byte_model(p["n"], pad, nn, "zeeman" in W["terms"])
     kernels = {}
     for slot, (ms, cnt) in prof.items():
         if cnt == 0 or slot not in bm:

@@ -45,9 +45,10 @@ __device__ __forceinline__ float2 keep(float2 v, bool ok) {
 }
 
 // ---------------------------------------------------------------- x forward
-// block (by, z): the RB cell rows y0 <= y < y0 + RB of plane z.  The 8 corners
-// of each cell are gathered straight from HBM; adjacent rows of the block share
-// node rows, which the L1 / L2 serve.
+// block (by, z): the RB cell rows y0 <= y < y0 + RB of plane z.  A cell's
+// value is Ms / 8 times the sum of its 8 corners: the block first sums the
+// node pairs (z, z + 1) of its RB + 1 node rows into LDS (each node value is
+// read once per block), then each cell adds four of those pair sums.
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
@@ -55,42 +56,54 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
        const Ctrl *__restrict__ ctrl) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
+    constexpr int NR = RB + 1, RL = L + 1;      // node rows; node slots per row (N1 + 1 <= L + 1)
+    constexpr int NZI = 3 * NR * RL;            // pair sums: component, node row, node x
+    constexpr int NA = (NZI + 255) / 256;
     __shared__ float2 s[NP * L];
+    __shared__ float zs[NZI];
     __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
     if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int y0 = blockIdx.x * RB, z = blockIdx.y;
     const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
-    const long long nn = (long long)NX * NY * (N3 + 1);
+    const unsigned nn = (unsigned)NX * NY * (N3 + 1);
+    const unsigned plane = (unsigned)NX * NY;
+    // node pair sums m(x, y, z) + m(x, y, z + 1), at clamped nodes (slots
+    // past the row end and rows past the plane are never used unzeroed)
+    float za[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        const int it = min(tid + 256 * a, NZI - 1);
+        const int c = it / (NR * RL), rem = it - c * (NR * RL);
+        const int jr = rem / RL, xn = rem - jr * RL;
+        const unsigned o = 4u * (c * nn + ((unsigned)z * NY + (unsigned)min(y0 + jr, NY - 1)) * NX +
+                                 (unsigned)min(xn, NX - 1));
+        za[a] = ldo(mag, o) + ldo(mag, o + 4u * plane);
+    }
     // Only the first L / 2 complex elements of a row hold cells (N1 <= P1 / 2);
     // the upper half is zero padding.  One thread per (row, element) of the
-    // data half: RB L / 2 = 256.  Rows past the plane's end and cells past N1
-    // are read at clamped addresses and zeroed by a factor (a branch around a
-    // load would make each load its own memory round trip).
+    // data half: RB L / 2 = 256.
     static_assert(RB * L / 2 == 256, "one data element per thread");
+    const int rb = tid / (L / 2), n = tid - (tid / (L / 2)) * (L / 2);
+    const bool rok = rb < nrows;
+    const int y = y0 + min(rb, nrows - 1);
+    float ms[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) ms[hh] = 0.125f * Ms[((long long)z * N2 + y) * N1 + min(2 * n + hh, N1 - 1)];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+        if (tid + 256 * a < NZI) zs[tid + 256 * a] = za[a];
+    __syncthreads();
     {
-        const int rb = tid / (L / 2), n = tid - (tid / (L / 2)) * (L / 2);
-        const bool rok = rb < nrows;
-        const int y = y0 + min(rb, nrows - 1);
         float2 v[3];
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            const bool ok = rok && 2 * n + hh < N1;
-            const int x = min(2 * n + hh, N1 - 1);
-            const float ms = 0.125f * Ms[((long long)z * N2 + y) * N1 + x];
-            const long long b00 = ((long long)z * NY + y) * NX + x;
-            const long long b01 = b00 + NX;
-            const long long b10 = b00 + (long long)NX * NY;
-            const long long b11 = b10 + NX;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float *mc = mag + c * nn;
-                const float sum = ((mc[b00] + mc[b00 + 1]) + (mc[b01] + mc[b01 + 1]))
-                                + ((mc[b10] + mc[b10 + 1]) + (mc[b11] + mc[b11 + 1]));
-                const float val = (ok ? 1.f : 0.f) * (ms * sum);
-                if (hh == 0) v[c].x = val; else v[c].y = val;
-            }
+        for (int c = 0; c < 3; ++c) {
+            const float *r0 = zs + (c * NR + rb) * RL + 2 * n, *r1 = r0 + RL;
+            // cells 2n (nodes 2n, 2n + 1) and 2n + 1 (nodes 2n + 1, 2n + 2)
+            const float p0 = r0[0] + r1[0], p1 = r0[1] + r1[1], p2 = r0[2] + r1[2];
+            v[c].x = (rok && 2 * n < N1 ? 1.f : 0.f) * (ms[0] * (p0 + p1));
+            v[c].y = (rok && 2 * n + 1 < N1 ? 1.f : 0.f) * (ms[1] * (p1 + p2));
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -114,7 +127,8 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
             const float2 e = cscale(cadd(zk, zc), 0.5f);
             const float2 d = cscale(csub(zk, zc), 0.5f);
             const float2 o = make_float2(d.y, -d.x);  // -i d
-            spec[(((long long)c * N3 + z) * P2 + y) * KP + k] = cadd(e, cmul(w, o));
+            sto(spec + (long long)c * N3 * P2 * KP, 8u * (((unsigned)z * (unsigned)P2 + (unsigned)y) * (unsigned)KP + (unsigned)k),
+                cadd(e, cmul(w, o)));
         }
     }
 }
@@ -146,11 +160,13 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
         const bool rok = row < rows;   // rows past the end: clamped read, zeroed
         const int rc = min(row, rows - 1);
         const int y = rc % N2, z = rc / N2;
+        // 32-bit byte offset of the row within one component
+        const unsigned ro = 8u * (((unsigned)z * (unsigned)P2 + (unsigned)y) * (unsigned)KP);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float2 *rowp = spec + (((long long)c * N3 + z) * P2 + y) * KP;
-            xk[i][c] = keep(rowp[k], rok);
-            xc[i][c] = keep(cconj(rowp[L - k]), rok);
+            const float2 *cb = spec + (long long)c * N3 * P2 * KP;
+            xk[i][c] = keep(ldo(cb, ro + 8u * (unsigned)k), rok);
+            xc[i][c] = keep(cconj(ldo(cb, ro + 8u * (unsigned)(L - k))), rok);
         }
     }
     // output items (row, cell x): only the first L / 2 complex elements of a
@@ -232,8 +248,11 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
     const int col = blockIdx.x * NPB + b;
     const int zc = col / KP, kx = col - zc * KP;
     const bool valid = col < N3 * KP && kx < K1;
-    float2 *cbase = spec + (long long)blockIdx.y * N3 * L * KP + (long long)zc * L * KP + kx;
-    const float2 *lbase = valid ? cbase : spec + (long long)blockIdx.y * N3 * L * KP;
+    // 32-bit byte offsets within one component (N3 P2 KP complex < 4 GiB);
+    // pad / past-the-end lanes read column 0
+    float2 *cb = spec + (long long)blockIdx.y * N3 * L * KP;
+    const unsigned oc = valid ? 8u * ((unsigned)zc * (unsigned)(L * KP) + (unsigned)kx) : 0u;
+    const unsigned rs = 8u * (unsigned)KP;   // row stride
     float2 v[1][E];
     if constexpr (DIR < 0) {
         // rows (j + T a) + L1 n2; only n2 < L2 / 2 can hold data
@@ -245,19 +264,19 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
                 float2 x = make_float2(0.f, 0.f);
                 if (n2 < L2 / 2) {
                     const int y = j + TT * a + L1 * n2;
-                    x = keep(lbase[(long long)min(y, N2 - 1) * KP], valid && y < N2);
+                    x = keep(ldo(cb, oc + (unsigned)min(y, N2 - 1) * rs), valid && y < N2);
                 }
                 v[0][a * L2 + n2] = x;
             }
         load_twiddles_full<L, NT>(tl, tw, tid);
-        fft2<L1, L2, -1, 1, NPB, E>(v, sh, tl, j, b);
+        fft2<L1, L2, -1, 1, NPB, E, true, false>(v, sh, tl, j, b);
         if (!valid) return;
         // rows (j + T q) + L2 k1
         constexpr int Q = L2 / TT;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int k1 = 0; k1 < L1; ++k1) cbase[(long long)(j + TT * q + L2 * k1) * KP] = v[0][q * L1 + k1];
+            for (int k1 = 0; k1 < L1; ++k1) sto(cb, oc + (unsigned)(j + TT * q + L2 * k1) * rs, v[0][q * L1 + k1]);
     } else {
         // rows (j + T q) + L2 k1 in (the forward output layout)
         constexpr int Q = L2 / TT;
@@ -265,9 +284,9 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int k1 = 0; k1 < L1; ++k1)
-                v[0][q * L1 + k1] = keep(lbase[(long long)(j + TT * q + L2 * k1) * KP], valid);
+                v[0][q * L1 + k1] = keep(ldo(cb, oc + (unsigned)(j + TT * q + L2 * k1) * rs), valid);
         load_twiddles_full<L, NT>(tl, tw, tid);
-        fft2<L2, L1, 1, 1, NPB, E>(v, sh, tl, j, b);
+        fft2<L2, L1, 1, 1, NPB, E, false, true>(v, sh, tl, j, b);
         if (!valid) return;
         // rows (j + T a) + L1 n2 out; only n2 < L2 / 2 can be data rows
         constexpr int A = L1 / TT;
@@ -276,7 +295,7 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
 #pragma unroll
             for (int n2 = 0; n2 < L2 / 2; ++n2) {
                 const int y = j + TT * a + L1 * n2;
-                if (y < N2) cbase[(long long)y * KP] = v[0][a * L2 + n2];
+                if (y < N2) sto(cb, oc + (unsigned)y * rs, v[0][a * L2 + n2]);
             }
     }
 }
@@ -420,7 +439,7 @@ __global__ void __launch_bounds__(256)
 k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
           int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
     constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
-    constexpr int NPB = (256 / TT) >> SH, E = L / TT, A = L1 / TT, Q = L2 / TT, NT = NPB * TT;
+    constexpr int NPB = (256 / TT) >> SH, E = L / TT, A = L1 / TT, NT = NPB * TT;
     static_assert(NPB >= 1, "block width");
     constexpr int NCX = E <= 8 ? 3 : 1;   // components per LDS exchange
     __shared__ float2 sh[TT > 1 ? NCX * L * NPB : 1];
@@ -474,11 +493,11 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     }
     load_twiddles_full<L, NT>(tl, tw, tid);
     if constexpr (NCX == 3) {
-        fft2<L1, L2, -1, 3, NPB, E>(v, sh, tl, j, b);
+        fft2<L1, L2, -1, 3, NPB, E, true, false>(v, sh, tl, j, b);
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            fft2<L1, L2, -1, 1, NPB, E>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
+            fft2<L1, L2, -1, 1, NPB, E, true, false>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
     }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -486,11 +505,11 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
         else apply(i, tensor_at(i));
     }
     if constexpr (NCX == 3) {
-        fft2<L2, L1, 1, 3, NPB, E>(v, sh, tl, j, b);
+        fft2<L2, L1, 1, 3, NPB, E, false, true>(v, sh, tl, j, b);
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            fft2<L2, L1, 1, 1, NPB, E>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
+            fft2<L2, L1, 1, 1, NPB, E, false, true>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
     }
     if (!valid) return;
 #pragma unroll

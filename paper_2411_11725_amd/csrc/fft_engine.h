@@ -49,37 +49,63 @@ __device__ __forceinline__ void load_twiddles(float2 *tl, const float2 *__restri
     for (int j = tid; j <= TWL / 2; j += NT) tl[j] = tw[j * (kTwN / TWL)];
 }
 
-template <int R, int DIR>
+template <int R, int DIR, bool ZH = false, bool OH = false>
 __device__ __forceinline__ void dft_small(float2 *v) {
+    // ZH: inputs v[R/2 ..] are zero (and are not read); OH: only the outputs
+    // v[0 .. R/2) are wanted (the others are left as they are)
     if constexpr (R == 2) {
-        float2 a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
+        if constexpr (ZH) {
+            v[1] = v[0];
+        } else {
+            float2 a = v[0], b = v[1];
+            v[0] = cadd(a, b);
+            if constexpr (!OH) v[1] = csub(a, b);
+        }
     } else if constexpr (R == 4) {
-        float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-        float2 s13 = cadd(v[1], v[3]), d13 = mul_dir_i<DIR>(csub(v[1], v[3]));
-        v[0] = cadd(s02, s13);
-        v[2] = csub(s02, s13);
-        v[1] = cadd(d02, d13);
-        v[3] = csub(d02, d13);
+        if constexpr (ZH) {
+            const float2 a = v[0], b = v[1], d = mul_dir_i<DIR>(v[1]);
+            v[0] = cadd(a, b);
+            v[1] = cadd(a, d);
+            if constexpr (!OH) {
+                v[2] = csub(a, b);
+                v[3] = csub(a, d);
+            }
+        } else {
+            float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+            float2 s13 = cadd(v[1], v[3]), d13 = mul_dir_i<DIR>(csub(v[1], v[3]));
+            v[0] = cadd(s02, s13);
+            v[1] = cadd(d02, d13);
+            if constexpr (!OH) {
+                v[2] = csub(s02, s13);
+                v[3] = csub(d02, d13);
+            }
+        }
     } else {  // R == 8: two radix-4 halves joined by w8^k
-        float2 e[4] = {v[0], v[2], v[4], v[6]};
-        float2 o[4] = {v[1], v[3], v[5], v[7]};
-        dft_small<4, DIR>(e);
-        dft_small<4, DIR>(o);
+        float2 e[4] = {v[0], v[2], make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        float2 o[4] = {v[1], v[3], make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        if constexpr (!ZH) {
+            e[2] = v[4];
+            e[3] = v[6];
+            o[2] = v[5];
+            o[3] = v[7];
+        }
+        dft_small<4, DIR, ZH>(e);
+        dft_small<4, DIR, ZH>(o);
         const float r = 0.70710678118654752440f;
         // w8^1 = (1 + DIR i)/sqrt2, w8^2 = DIR i, w8^3 = (-1 + DIR i)/sqrt2
         float2 o1 = cscale(cadd(o[1], mul_dir_i<DIR>(o[1])), r);
         float2 o2 = mul_dir_i<DIR>(o[2]);
         float2 o3 = cscale(csub(mul_dir_i<DIR>(o[3]), o[3]), r);
         v[0] = cadd(e[0], o[0]);
-        v[4] = csub(e[0], o[0]);
         v[1] = cadd(e[1], o1);
-        v[5] = csub(e[1], o1);
         v[2] = cadd(e[2], o2);
-        v[6] = csub(e[2], o2);
         v[3] = cadd(e[3], o3);
-        v[7] = csub(e[3], o3);
+        if constexpr (!OH) {
+            v[4] = csub(e[0], o[0]);
+            v[5] = csub(e[1], o1);
+            v[6] = csub(e[2], o2);
+            v[7] = csub(e[3], o3);
+        }
     }
 }
 

@@ -44,32 +44,38 @@ __device__ __forceinline__ float2 rot(float2 v, int m) {
     return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
 }
 
-// X_k = sum_n x_n exp(DIR 2 pi i n k / R), in place, natural order
-template <int R, int DIR>
+// X_k = sum_n x_n exp(DIR 2 pi i n k / R), in place, natural order.
+// ZH: the inputs x_n, n >= R/2, are zero (not read); OH: only X_k, k < R/2,
+// are wanted (the upper outputs are left unspecified).  Zero padding makes
+// half of every forward input and inverse output of the demag transforms
+// such, and skipping them saves a butterfly stage's work.
+template <int R, int DIR, bool ZH = false, bool OH = false>
 __device__ __forceinline__ void dft_reg(float2 *v) {
     if constexpr (R <= 8) {
-        if constexpr (R > 1) dft_small<R, DIR>(v);
+        if constexpr (R > 1) dft_small<R, DIR, ZH, OH>(v);
     } else {
         static_assert(R == 16 || R == 32, "R <= 32");
         constexpr int A = 4, B = R / 4;
         float2 t[R];
 #pragma unroll
         for (int n1 = 0; n1 < A; ++n1) {
+            // x_{n1 + A n2} with n2 >= B / 2 lies in the upper half
             float2 u[B];
 #pragma unroll
-            for (int n2 = 0; n2 < B; ++n2) u[n2] = v[n1 + A * n2];
-            dft_reg<B, DIR>(u);
+            for (int n2 = 0; n2 < B; ++n2) u[n2] = (ZH && n2 >= B / 2) ? make_float2(0.f, 0.f) : v[n1 + A * n2];
+            dft_reg<B, DIR, ZH>(u);
 #pragma unroll
             for (int k2 = 0; k2 < B; ++k2) t[n1 * B + k2] = rot<R, DIR>(u[k2], n1 * k2);
         }
 #pragma unroll
         for (int k2 = 0; k2 < B; ++k2) {
+            // X_{k2 + B k1} with k1 >= A / 2 lies in the upper half
             float2 u[A];
 #pragma unroll
             for (int n1 = 0; n1 < A; ++n1) u[n1] = t[n1 * B + k2];
-            dft_small<A, DIR>(u);
+            dft_small<A, DIR, false, OH>(u);
 #pragma unroll
-            for (int k1 = 0; k1 < A; ++k1) v[k2 + B * k1] = u[k1];
+            for (int k1 = 0; k1 < (OH ? A / 2 : A); ++k1) v[k2 + B * k1] = u[k1];
         }
     }
 }
@@ -101,20 +107,23 @@ __device__ __forceinline__ void load_twiddles_full(float2 *tl, const float2 *__r
 // sh[(c L + e) NPB + b]: consecutive lanes, consecutive pencils); tl is a
 // forward twiddle table of period L.  Begins with a block barrier (sh and tl
 // must be free / ready), so every thread of the block must call it.
-template <int L1, int L2, int DIR, int NC, int NPB, int E>
+//
+// ZIN: the inputs with n2 >= L2 / 2 (the upper half of x) are zero; ZOUT:
+// only the outputs with k1 < L1 / 2 (the lower half of X) are wanted.
+template <int L1, int L2, int DIR, int NC, int NPB, int E, bool ZIN = false, bool ZOUT = false>
 __device__ __forceinline__ void fft2(float2 (&v)[NC][E], float2 *sh, const float2 *tl, int j, int b) {
     constexpr int L = L1 * L2;
     constexpr int T = L1 < L2 ? L1 : L2;
     static_assert(E == L / T, "values per thread");
     if constexpr (T == 1) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) dft_reg<L, DIR>(v[c]);
+        for (int c = 0; c < NC; ++c) dft_reg<L, DIR, ZIN, ZOUT>(v[c]);
     } else {
         constexpr int A = L1 / T, Q = L2 / T;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int a = 0; a < A; ++a) dft_reg<L2, DIR>(&v[c][a * L2]);
+            for (int a = 0; a < A; ++a) dft_reg<L2, DIR, ZIN>(&v[c][a * L2]);
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < A; ++a) {
@@ -138,7 +147,7 @@ __device__ __forceinline__ void fft2(float2 (&v)[NC][E], float2 *sh, const float
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int q = 0; q < Q; ++q) dft_reg<L1, DIR>(&v[c][q * L1]);
+            for (int q = 0; q < Q; ++q) dft_reg<L1, DIR, false, ZOUT>(&v[c][q * L1]);
     }
 }
 
