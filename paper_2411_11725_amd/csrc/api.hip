@@ -144,9 +144,13 @@ static size_t footprint(const Sizes &s) {
 // mesh stream (RK4 calls return without waiting), so let it finish first;
 // callers that know the stream is idle pass false.
 static void drop_graph(nm_mesh *m, bool wait = true) {
-    if (m->gexec) {
-        if (wait) (void)hipStreamSynchronize(m->stream);
-        (void)hipGraphExecDestroy(m->gexec);
+    bool any = m->gexec != nullptr;
+    for (hipGraphExec_t g : m->gtail) any = any || g != nullptr;
+    if (any && wait) (void)hipStreamSynchronize(m->stream);
+    if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+    for (hipGraphExec_t &g : m->gtail) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
     }
     m->gexec = nullptr;
     m->g_method = 0;
@@ -548,7 +552,23 @@ nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integ
 
 // One batch of steps / attempts: launched directly while profiling, else
 // captured once into a graph (keyed on method, terms, state pointer and
-// batch) and replayed on the mesh stream.
+// batch) and replayed on the mesh stream.  Power-of-two batches below the
+// keyed one (the end of an integration) are captured beside it.
+static int tail_slot(int batch) {
+    for (int k = 0; k < 6; ++k)
+        if (batch == (1 << k)) return k;
+    return -1;
+}
+
+int next_batch(const nm_mesh *m, int batch) {
+    const Ctrl *C = m->ctrl_host;
+    double est = (double)(C->max_accepted - C->accepted);
+    if (C->dt_prop > 0.0) est = std::fmin(est, std::ceil((C->t_end - C->t) / C->dt_prop * (1.0 + 1e-9)));
+    int b = 1;
+    while (b < batch && (double)b < est) b *= 2;
+    return std::min(b, batch);
+}
+
 hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int batch) {
     auto enqueue_batch = [&]() -> hipError_t {
         hipError_t e = hipSuccess;
@@ -568,8 +588,7 @@ hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int ba
         return e;
     };
     if (m->prof) return enqueue_batch();
-    if (!(m->gexec && m->g_method == method && m->g_terms == terms && m->g_mag == mag && m->g_batch == batch)) {
-        drop_graph(m);
+    auto capture = [&](hipGraphExec_t *out) -> hipError_t {
         hipStream_t user = m->stream;
         m->stream = m->cap_stream;
         hipGraph_t graph = nullptr;
@@ -578,8 +597,22 @@ hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int ba
         if (e == hipSuccess) e = hipStreamEndCapture(m->cap_stream, &graph);
         m->stream = user;
         if (e == hipSuccess) e = e2;
-        if (e == hipSuccess) e = hipGraphInstantiate(&m->gexec, graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
+        return e;
+    };
+    const bool key = m->gexec && m->g_method == method && m->g_terms == terms && m->g_mag == mag;
+    const int ts = tail_slot(batch);
+    if (key && batch < m->g_batch && ts >= 0) {
+        if (!m->gtail[ts]) {
+            hipError_t e = capture(&m->gtail[ts]);
+            if (e != hipSuccess) return e;
+        }
+        return hipGraphLaunch(m->gtail[ts], m->stream);
+    }
+    if (!(key && m->g_batch == batch)) {
+        drop_graph(m);
+        hipError_t e = capture(&m->gexec);
         if (e != hipSuccess) return e;
         m->g_method = method;
         m->g_terms = terms;
@@ -628,7 +661,17 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         long nsteps = (long)std::ceil(span * (1.0 - 1e-12));
         if (nsteps < 1) nsteps = 1;
         if (nsteps > max_steps) nsteps = max_steps;
-        for (long k = 0; k < nsteps; k += batch) NM_HIP(step_batch(m, mag, NM_RK4, terms, batch), "nm_llg_step");
+        for (long k = 0; k < nsteps;) {
+            // the last replay takes the smallest power of two covering the rest
+            int b = batch;
+            if (nsteps - k < batch) {
+                b = 1;
+                while (b < nsteps - k) b *= 2;
+                b = std::min(b, batch);
+            }
+            NM_HIP(step_batch(m, mag, NM_RK4, terms, b), "nm_llg_step");
+            k += b;
+        }
         // Fixed steps: the call returns without waiting for the GPU; the clock
         // advances on the host exactly as k_rk4_advance moves it on the device
         double t = clk->t, dt = std::fmin(clk->dt, t_end - clk->t);
@@ -646,8 +689,9 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         return NM_OK;
     } else {
         long long seen = -1;
+        int b = batch;
         for (;;) {
-            NM_HIP(step_batch(m, mag, NM_DP45, terms, batch), "nm_llg_step");
+            NM_HIP(step_batch(m, mag, NM_DP45, terms, b), "nm_llg_step");
             NM_HIP(ctrl_readback(m), "nm_llg_step");
             NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
             if (m->ctrl_host->done) break;
@@ -655,6 +699,7 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
             // the controller must make progress; anything else is a bug
             NM_REQUIRE(m->ctrl_host->attempts > seen, NM_EHIP, "nm_llg_step: controller made no progress");
             seen = m->ctrl_host->attempts;
+            b = next_batch(m, batch);
         }
     }
     return step_finish(m, in->method, clk);

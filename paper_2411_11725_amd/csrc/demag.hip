@@ -62,7 +62,6 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     __shared__ float2 s[NP * L];
     __shared__ float zs[NZI];
     __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
-    if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int y0 = blockIdx.x * RB, z = blockIdx.y;
     const int nrows = min(RB, N2 - y0);
@@ -91,6 +90,9 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     float ms[2];
 #pragma unroll
     for (int hh = 0; hh < 2; ++hh) ms[hh] = 0.125f * Ms[((long long)z * N2 + y) * N1 + min(2 * n + hh, N1 - 1)];
+    // a finished controller turns the kernel into a no-op; the flag is read
+    // after the data loads are issued, so its round trip overlaps theirs
+    if (ctrl && ctrl->done) return;
 #pragma unroll
     for (int a = 0; a < NA; ++a)
         if (tid + 256 * a < NZI) zs[tid + 256 * a] = za[a];
@@ -143,7 +145,6 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
     __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
-    if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const int rows = N2 * N3;
     const int row0 = blockIdx.x * RB;
@@ -190,6 +191,9 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
         wv[h] = src_mode > 0 ? wc[oi[h]] : 1.f;
         av[h] = src_mode == 2 ? wstat[oi[h]] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    // a finished controller turns the kernel into a no-op; the flag is read
+    // after the data loads are issued, so its round trip overlaps theirs
+    if (ctrl && ctrl->done) return;
     load_twiddles<2 * L, 256>(tl, tw, tid);
     __syncthreads();
     // Z_k = E_k + i O_k with E_k = X_k + conj X_{L-k},
@@ -243,7 +247,6 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
     static_assert(NPB >= 1, "block width");
     __shared__ float2 sh[TT > 1 ? L * NPB : 1];
     __shared__ float2 tl[L];
-    if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
     const int col = blockIdx.x * NPB + b;
     const int zc = col / KP, kx = col - zc * KP;
@@ -268,6 +271,7 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
                 }
                 v[0][a * L2 + n2] = x;
             }
+        if (ctrl && ctrl->done) return;   // read after the loads are issued
         load_twiddles_full<L, NT>(tl, tw, tid);
         fft2<L1, L2, -1, 1, NPB, E, true, false>(v, sh, tl, j, b);
         if (!valid) return;
@@ -285,6 +289,7 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
 #pragma unroll
             for (int k1 = 0; k1 < L1; ++k1)
                 v[0][q * L1 + k1] = keep(ldo(cb, oc + (unsigned)(j + TT * q + L2 * k1) * rs), valid);
+        if (ctrl && ctrl->done) return;   // read after the loads are issued
         load_twiddles_full<L, NT>(tl, tw, tid);
         fft2<L2, L1, 1, 1, NPB, E, false, true>(v, sh, tl, j, b);
         if (!valid) return;
@@ -350,7 +355,6 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     constexpr int NP = 3 * TB;
     __shared__ float2 s[(L + 1) * NP];   // + one spare row for masked lanes
     __shared__ float2 tl[L / 2 + 1];
-    if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const long long plane = (long long)P2 * KP;
     const int ncols = P2 * KP;
@@ -392,6 +396,9 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
         const int kyr = fy ? P2 - ky : ky;
         Nt[i] = tensor_load(T, tstride, ((long long)(ok ? kzr : 0) * P2h + kyr) * KP + kx, fy ? -1.f : 1.f, true);
     }
+    // a finished controller turns the kernel into a no-op; the flag is read
+    // after the data loads are issued, so its round trip overlaps theirs
+    if (ctrl && ctrl->done) return;
     load_twiddles<L, 256>(tl, tw, tid);
 #pragma unroll
     for (int i = 0; i < NI; ++i) s[tid + i * 256] = v[i];   // = s[e * NP + p]
@@ -444,7 +451,6 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     constexpr int NCX = E <= 8 ? 3 : 1;   // components per LDS exchange
     __shared__ float2 sh[TT > 1 ? NCX * L * NPB : 1];
     __shared__ float2 tl[L];
-    if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
     const int col = blockIdx.x * NPB + b;
     const bool valid = col < P2 * KP && col % KP < K1;
@@ -491,6 +497,9 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
 #pragma unroll
         for (int i = 0; i < E; ++i) Nt[i] = tensor_at(i);
     }
+    // a finished controller turns the kernel into a no-op; the flag is read
+    // after the data loads are issued, so its round trip overlaps theirs
+    if (ctrl && ctrl->done) return;
     load_twiddles_full<L, NT>(tl, tw, tid);
     if constexpr (NCX == 3) {
         fft2<L1, L2, -1, 3, NPB, E, true, false>(v, sh, tl, j, b);
@@ -532,7 +541,6 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     constexpr int NP = 3 * TB;
     __shared__ float2 s[(L + 1) * NP];   // + one spare row for masked lanes
     __shared__ float2 tl[L / 2 + 1];
-    if (ctrl && ctrl->done) return;
     const int tid = threadIdx.x;
     const long long cstride = (long long)L * KP;
     const int col0 = blockIdx.x * TB;
@@ -558,6 +566,9 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
         const bool ok = col0 + b < K1 && kyr <= L / 2;
         Nt[i] = tensor_load(T, tstride, (long long)(ok ? kyr : 0) * KP + min(col0 + b, K1 - 1), 1.f, false);
     }
+    // a finished controller turns the kernel into a no-op; the flag is read
+    // after the data loads are issued, so its round trip overlaps theirs
+    if (ctrl && ctrl->done) return;
     load_twiddles<L, 256>(tl, tw, tid);
 #pragma unroll
     for (int i = 0; i < NI; ++i) s[tid + i * 256] = v[i];

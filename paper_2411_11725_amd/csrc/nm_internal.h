@@ -119,9 +119,11 @@ struct nm_mesh {
     nm::ProfState *prof;     // non-null while profiling is enabled
 
     // captured stepping graph (one batch of attempts / steps), launched on
-    // `stream`; captured on the private `cap_stream`
+    // `stream`; captured on the private `cap_stream`.  gtail[k] holds the
+    // same graph with 2^k attempts (< g_batch) for the end of an integration
     hipStream_t cap_stream;
     hipGraphExec_t gexec;
+    hipGraphExec_t gtail[6];
     // tile choices of the register-FFT passes (see the tuner)
     int tune_y, tune_z;
     // recorded adjoint segment and its key
@@ -196,6 +198,10 @@ hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t,
 hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
 hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat from the raw copies
+// attempts for the next replay of a DP45 integration: the smallest power of
+// two (at most batch) covering what the host mirror of the controller says
+// is left by step count and by time at the proposed step
+int next_batch(const nm_mesh *m, int batch);
 void mesh_release(nm_mesh *m);             // free a mesh whose stream work has completed
 hipError_t launch_rk4_advance(nm_mesh *m);
 

@@ -47,6 +47,7 @@ struct Solve {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     int batch = 16;
+    int next = 16;           // attempts in the next replay (fewer near the end)
     bool inflight = false;
     nm_clock clk{};
     nm_solve_result res{};
@@ -151,6 +152,7 @@ bool admit(nm_server *S, Solve *s) {
     s->clk = nm_clock{0.0, r.dt0, 0, 0, 0, 0.0};
     if (step_begin(s->mesh, s->m_dev, &s->clk, &in, r.t_end, 1L << 40, &s->batch) != NM_OK) return false;
     s->batch = S->desc.attempts_per_launch;
+    s->next = s->batch;
     s->res.t_admit = now_s();
     return true;
 }
@@ -219,7 +221,7 @@ void run(nm_server *S) {
         bool progressed = false;
         for (Solve *s : S->active) {
             if (s->inflight) continue;
-            hipError_t e = step_batch(s->mesh, s->m_dev, NM_DP45, s->req.terms, s->batch);
+            hipError_t e = step_batch(s->mesh, s->m_dev, NM_DP45, s->req.terms, s->next);
             if (e == hipSuccess) e = ctrl_readback(s->mesh);
             if (e == hipSuccess) e = hipEventRecord(s->ev, s->stream);
             if (e != hipSuccess) {
@@ -248,6 +250,7 @@ void run(nm_server *S) {
                     complete(S, s);
                     continue;
                 }
+                s->next = next_batch(s->mesh, s->batch);
             }
             still.push_back(s);
         }

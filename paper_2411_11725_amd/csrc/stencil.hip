@@ -28,6 +28,7 @@ struct StencilParams {
     const float4 *src;
     int drive;                     // add the drive (the w component times sin and its amplitude)
     int W;                         // LDS window length per z offset: 256 + 2 NX + 2
+    int faces;                     // K^e couples face neighbours (cells are not cubes)
     float rNX, rNY;                // 1 / NX, 1 / NY
     // energy kernel: raw cell data
     const float *wc, *A2, *Ku, *easy, *hcell, *dmask, *hd;
@@ -165,18 +166,7 @@ k_node(StencilParams P, StageArgs S) {
     const int tid = (int)threadIdx.x;
     const int n0 = (int)lb * 256;
     const int n = n0 + tid;
-    double t = S.t0, dt = 0.0;
     const Ctrl *C = S.ctrl;
-    constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE)
-                         : (MODE == kModeRK4 || MODE == kModeAdjFwd) ? rk4_c(STAGE) : 0.0;
-    if (C) {
-        if (C->done) return;
-        dt = C->dt;
-        t = C->t + cst * dt;
-    } else {
-        dt = S.dt0;
-        t = S.t0 + cst * dt;
-    }
     const int nn = (int)P.nn;
     const int NX = P.NX, NY = P.NY, NZ = P.NZ, W = P.W;
     const float *in0 = S.in, *in1 = S.in + nn, *in2 = S.in + 2 * nn;
@@ -269,6 +259,22 @@ k_node(StencilParams P, StageArgs S) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) cs[q] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    // ---- the step clock: a finished controller turns the kernel into a
+    // no-op; it is read after the loads above are issued, so its round trip
+    // overlaps theirs
+    double t, dt;
+    {
+        constexpr double cst = MODE == kModeDP45 ? dp_c(STAGE)
+                             : (MODE == kModeRK4 || MODE == kModeAdjFwd) ? rk4_c(STAGE) : 0.0;
+        if (C) {
+            if (C->done) return;
+            dt = C->dt;
+            t = C->t + cst * dt;
+        } else {
+            dt = S.dt0;
+            t = S.t0 + cst * dt;
+        }
+    }
     // ---- neighbourhood
     float v[NIT > 0 ? 1 : 27][3];
     int lrow[9];
@@ -337,23 +343,33 @@ k_node(StencilParams P, StageArgs S) {
         float4 vb[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) vb[k] = nb((dz + 1) * 9 + k);
+        // exchange: edge and corner neighbours, then (K^e of a cube gives
+        // them weight 0) the face neighbours unless the cells are cubes
+        auto exch = [&](int dx, int dy) {
+            float as = 0.f;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (shares(dx, q & 1) && shares(dy, (q >> 1) & 1) && shares(dz, q >> 2)) as += a2[q];
+            const int mask = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2);
+            const float w = as * P.Kp[mask];
+            const float4 b = vb[(dy + 1) * 3 + dx + 1];
+            g0 += w * (b.x - mn.x);
+            g1 += w * (b.y - mn.y);
+            g2 += w * (b.z - mn.z);
+        };
         if (ex) {
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
-                for (int dx = -1; dx <= 1; ++dx) {
-                    if (dx == 0 && dy == 0 && dz == 0) continue;
-                    float as = 0.f;
+                for (int dx = -1; dx <= 1; ++dx)
+                    if ((dx != 0) + (dy != 0) + (dz != 0) >= 2) exch(dx, dy);
+            if (P.faces) {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (shares(dx, q & 1) && shares(dy, (q >> 1) & 1) && shares(dz, q >> 2)) as += a2[q];
-                    const int mask = (dx != 0) | ((dy != 0) << 1) | ((dz != 0) << 2);
-                    const float w = as * P.Kp[mask];
-                    const float4 b = vb[(dy + 1) * 3 + dx + 1];
-                    g0 += w * (b.x - mn.x);
-                    g1 += w * (b.y - mn.y);
-                    g2 += w * (b.z - mn.z);
-                }
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        if ((dx != 0) + (dy != 0) + (dz != 0) == 1) exch(dx, dy);
+            }
         }
         if (an) {
             // x pairs of the three rows: cell side i1 = 0 pairs x with x + 1, i1 = 1 with x - 1
@@ -671,6 +687,7 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
                                  : ((terms & NM_T_ZEEMAN) ? m->wstat : nullptr);
     P.drive = ((terms & NM_T_ZEEMAN) && m->has_drive) ? 1 : 0;
     P.W = 256 + 2 * m->NX + 2;
+    P.faces = (m->Kp[1] != 0.f || m->Kp[2] != 0.f || m->Kp[4] != 0.f) ? 1 : 0;
     P.rNX = 1.f / (float)m->NX;
     P.rNY = 1.f / (float)m->NY;
     P.wc = m->wc;
