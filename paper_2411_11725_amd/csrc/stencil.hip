@@ -564,36 +564,60 @@ __global__ void k_energy_final(const double *__restrict__ part, int nb, double *
 }
 
 // ---------------------------------------------------------- step control
-__global__ void k_dp45_control(Ctrl *C, const ErrPartial *__restrict__ part, int np) {
-    __shared__ double s_sq[256];
-    __shared__ float s_mf[256];
-    __shared__ int s_nf[256];
-    if (C->done) {
-        if (threadIdx.x == 0) C->accept = 0;
-        return;
-    }
+// One block of 1024 threads: each thread sums a fixed strided subset of the
+// block partials (8 loads in flight per round), then lane exchanges and LDS
+// combine the 16 waves; the order is fixed, so the result is reproducible.
+__global__ void __launch_bounds__(1024) k_dp45_control(Ctrl *C, const ErrPartial *__restrict__ part, int np) {
+    __shared__ double s_sq[16];
+    __shared__ float s_mf[16];
+    __shared__ int s_nf[16];
+    const int t = threadIdx.x;
     double sq = 0.0;
     float mf = 0.f;
     int nf = 0;
-    for (int i = threadIdx.x; i < np; i += 256) {
-        sq += part[i].sumsq;
-        mf = fmaxf(mf, part[i].maxf);
-        nf |= part[i].nonfinite;
-    }
-    const int t = threadIdx.x;
-    s_sq[t] = sq;
-    s_mf[t] = mf;
-    s_nf[t] = nf;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w) {
-            s_sq[t] += s_sq[t + w];
-            s_mf[t] = fmaxf(s_mf[t], s_mf[t + w]);
-            s_nf[t] |= s_nf[t + w];
+    for (int i0 = 0; i0 < np; i0 += 8 * 1024) {
+        ErrPartial q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024 + t;
+            q[u] = part[min(i, np - 1)];
+            if (i >= np) q[u] = ErrPartial{0.0, 0.f, 0};
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sq += q[u].sumsq;
+            mf = fmaxf(mf, q[u].maxf);
+            nf |= q[u].nonfinite;
+        }
     }
+    if (C->done) {
+        if (t == 0) C->accept = 0;
+        return;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        sq += __shfl_xor(sq, o, 64);
+        mf = fmaxf(mf, __shfl_xor(mf, o, 64));
+        nf |= __shfl_xor(nf, o, 64);
+    }
+    if ((t & 63) == 0) {
+        s_sq[t >> 6] = sq;
+        s_mf[t >> 6] = mf;
+        s_nf[t >> 6] = nf;
+    }
+    __syncthreads();
     if (t != 0) return;
+    double tsq = 0.0;
+    float tmf = 0.f;
+    int tnf = 0;
+    for (int w = 0; w < 16; ++w) {
+        tsq += s_sq[w];
+        tmf = fmaxf(tmf, s_mf[w]);
+        tnf |= s_nf[w];
+    }
+    s_sq[0] = tsq;
+    s_mf[0] = tmf;
+    s_nf[0] = tnf;
     const double err = sqrt(s_sq[0] * C->norm_scale);
     C->accept = 0;
     C->err = err;
@@ -644,12 +668,17 @@ __global__ void k_dp45_finish(const Ctrl *__restrict__ C, float *__restrict__ ms
     const bool acc = C->accept;
     const bool done = C->done;
     if (!acc && done) return;
-    float mv = mstate[i], kv = k1[i];
+    // accepted: the 5th-order solution and k7 become the state and k1
+    // (first same as last); rejected: both stay
+    float mv, kv;
     if (acc) {
         mv = y7[i];
         kv = k7[i];
         mstate[i] = mv;
         k1[i] = kv;
+    } else {
+        mv = mstate[i];
+        kv = k1[i];
     }
     if (!done) y2[i] = mv + (float)(C->dt * a21) * kv;
 }
@@ -798,7 +827,7 @@ hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t,
 
 hipError_t launch_dp45_control(nm_mesh *m) {
     const int np = (int)stencil_grid(m).x;
-    NM_LAUNCH(m, NM_PROF_CONTROL, k_dp45_control, dim3(1), dim3(256), 0, m->ctrl, m->partials, np);
+    NM_LAUNCH(m, NM_PROF_CONTROL, k_dp45_control, dim3(1), dim3(1024), 0, m->ctrl, m->partials, np);
     return hipGetLastError();
 }
 
