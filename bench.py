@@ -42,6 +42,11 @@ WORKLOADS = {
     # longer fits the 256 MB Infinity Cache
     "block_large": dict(tag="block_256x256x64", desc="3D block 256x256x64 cells (2 nm), alpha=1 relaxation, per-cell Ku, DP45 rtol 1e-5",
                         make="block_large", terms=("exchange", "demag", "anisotropy"), dt0=1e-14),
+    # the same film under the thin-film basis (one node layer, Sec. 3.3)
+    "film_basis": dict(tag="film_256x64x1_filmbasis",
+                       desc="thin film 256x64x1 cells (3.9x3.9x3 nm), thin-film basis (one node layer), "
+                            "field step (-25,4,0) mT, DP45 rtol 1e-5",
+                       make="film_basis", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
     "film": dict(tag="film_256x64x1", desc="thin film 256x64x1 cells (3.9x3.9x3 nm), field step (-25,4,0) mT, DP45 rtol 1e-5",
                  make="film", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
     "cube": dict(tag="cube_16x16x4", desc="16x16x4 cells (2 nm), random start, DP45 rtol 1e-5",
@@ -55,6 +60,14 @@ WORKLOADS = {
 # (1, 2, 3, 4, 4, 5 of them)
 DP45_WRITES = 11.0 / 6.0
 DP45_READS = 19.0 / 6.0
+
+
+def make_workload(synth, W):
+    if W["make"] == "block_large":
+        return synth.block(n=(256, 256, 64))
+    if W["make"] == "film_basis":
+        return synth.as_film(synth.film())
+    return getattr(synth, W["make"])()
 
 
 def byte_model(n, pad, nn, zeeman, stage_writes=DP45_WRITES, stage_reads=DP45_READS):
@@ -111,7 +124,7 @@ def cpu_baseline(p, terms_mask, evals=4):
     import oracle
     from oracle.field import demag_cell_field
 
-    mesh = oracle.Mesh(p["n"], p["h"])
+    mesh = oracle.Mesh(p["n"], p["h"], basis=p.get("basis", "3d"))
     f = lambda a: None if a is None else np.asarray(a, dtype=np.float64)
     mat = oracle.Material(Ms=f(p["Ms"]), A=f(p["A"]), alpha=f(p["alpha"]), gamma=p["gamma"],
                           Ku=f(p["Ku"]), easy=f(p["easy"]), h_cell=f(p["h_cell"]),
@@ -292,7 +305,7 @@ def main():
         serving = serving_bench(B, synth, args.serve_count, args.serve_tend, args.serve_nmax,
                                 args.serve_active, args.serve_streams, args.serve_attempts)
     W = WORKLOADS[args.workload]
-    p = synth.block(n=(256, 256, 64)) if W["make"] == "block_large" else getattr(synth, W["make"])()
+    p = make_workload(synth, W)
     tmask = {"exchange": B.NM_T_EXCHANGE, "demag": B.NM_T_DEMAG, "anisotropy": B.NM_T_ANIS,
              "zeeman": B.NM_T_ZEEMAN}
     terms = sum(tmask[t] for t in W["terms"])

@@ -63,13 +63,25 @@ enum { NM_RK4 = 1, NM_DP45 = 2 };
 
 typedef struct nm_mesh nm_mesh;
 
-/* Grid and constants.  n[k] >= 2 for k = 0, 1 and n[2] >= 1; every padded
- * FFT length (next power of two >= 2 n[k] - 1) must not exceed 1024. */
+/* Nodal bases (Sec. 3.1 and Sec. 3.3, low-dimensional geometries). */
+enum {
+    NM_BASIS_3D = 0,   /* trilinear functions: (N1+1)(N2+1)(N3+1) nodes */
+    NM_BASIS_FILM = 1  /* bilinear in-plane functions constant along z, the weak
+                        * form still integrated over the full cells: one cell
+                        * layer (N3 = 1) and (N1+1)(N2+1) nodes, every nodal
+                        * array laid out as [3][1][N2+1][N1+1] */
+};
+
+/* Grid and constants.  n[k] >= 2 for k = 0, 1 and n[2] >= 1 (= 1 for the
+ * film basis); every padded FFT length (next power of two >= 2 n[k] - 1)
+ * must not exceed 1024.  A zero-initialised descriptor selects the 3D
+ * basis. */
 typedef struct {
     int n[3];          /* cells N1, N2, N3 */
     double h[3];       /* cell edges (m), > 0 */
     double gamma;      /* reduced gyromagnetic ratio, m/(A s), > 0 */
     void *stream;      /* hipStream_t for all work on this mesh */
+    int basis;         /* NM_BASIS_3D or NM_BASIS_FILM */
 } nm_mesh_desc;
 
 /* Cell-wise material parameters (Eqs. ms_discrete, cell_basis) and applied

@@ -22,7 +22,7 @@ Ingredients, written out from the definitions:
 import numpy as np
 
 from .field import ZEEMAN, heff, lumped_mass, nodal_alpha
-from .mesh import CORNERS, MU0
+from .mesh import MU0
 
 
 def llg_vjp(m, H, w, alpha_n, gp):
@@ -41,9 +41,9 @@ def llg_vjp(m, H, w, alpha_n, gp):
 def cell_gather(mesh, mat, v):
     """dL/dtheta_c = mu0 Ms_c V/8 sum_{n in c} v_n for the nodal v = M^-1 u."""
     acc = np.zeros((3,) + mesh.cell_shape)
-    for a in CORNERS:
+    for a in mesh.corners:
         acc += mesh.corner(v, a)
-    return MU0 * mat.Ms * mesh.V / 8.0 * acc
+    return MU0 * mat.Ms * mesh.V / len(mesh.corners) * acc
 
 
 def rhs_vjp(mesh, mat, y, t, w, terms, alpha_n=None):

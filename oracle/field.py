@@ -7,7 +7,8 @@ Everything here follows Sec. 3 of the paper step by step, in float64:
   (a, b) of the 8 x 8 element matrix, the cell contribution is added to the
   node c + a;
 * the field follows from mass lumping, Eq. (mass_lumping):
-  H_n = -g_n / M_n with M_n = int mu0 Ms^h phi_n = mu0 sum_{c containing n} Ms_c V/8;
+  H_n = -g_n / M_n with M_n = int mu0 Ms^h phi_n = mu0 sum_{c containing n} Ms_c V/8
+  (V/4 under the thin-film basis, whose cells have 4 local vertices);
 * demagnetisation (Sec. 3.2): nodal m is averaged to cells, convolved with
   the cuboid tensor by FFT (zero padded), and the cell field is brought back
   to the nodes through the same lumped weak form.
@@ -20,7 +21,7 @@ Energies (J):
 """
 import numpy as np
 
-from .mesh import CORNERS, MU0
+from .mesh import MU0
 from .newell import newell_octant
 
 EXCHANGE, DEMAG, ANISOTROPY, ZEEMAN = 1, 2, 4, 8
@@ -31,10 +32,11 @@ ALL_TERMS = 15
 # mass, nodal coefficients, external field
 # ---------------------------------------------------------------------------
 def lumped_mass(mesh, mat):
-    """M_n = mu0 sum_{c containing n} Ms_c V / 8  (Eq. mass_lumping)."""
+    """M_n = mu0 sum_{c containing n} Ms_c V / 8  (Eq. mass_lumping; V / 4 for
+    the 4 vertices of a film-basis cell)."""
     M = np.zeros(mesh.node_shape)
-    for a in CORNERS:
-        mesh.corner(M, a)[...] += MU0 * mat.Ms * mesh.V / 8.0
+    for a in mesh.corners:
+        mesh.corner(M, a)[...] += MU0 * mat.Ms * mesh.V / len(mesh.corners)
     return M
 
 
@@ -42,7 +44,7 @@ def nodal_alpha(mesh, mat):
     """Ms-weighted mean of the cell damping over the cells sharing a node."""
     num = np.zeros(mesh.node_shape)
     den = np.zeros(mesh.node_shape)
-    for a in CORNERS:
+    for a in mesh.corners:
         mesh.corner(num, a)[...] += mat.Ms * mat.alpha
         mesh.corner(den, a)[...] += mat.Ms
     return np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
@@ -66,9 +68,9 @@ def external_cell_field(mesh, mat, t):
 # ---------------------------------------------------------------------------
 def _exchange_gradient(mesh, mat, m, g):
     K, _ = mesh.element_matrices()
-    for p, a in enumerate(CORNERS):
+    for p, a in enumerate(mesh.corners):
         acc = np.zeros((3,) + mesh.cell_shape)
-        for q, b in enumerate(CORNERS):
+        for q, b in enumerate(mesh.corners):
             acc += K[p, q] * mesh.corner(m, b)
         mesh.corner(g, a)[...] += 2.0 * mat.A * acc
 
@@ -76,18 +78,18 @@ def _exchange_gradient(mesh, mat, m, g):
 def _anisotropy_gradient(mesh, mat, m, g):
     _, Me = mesh.element_matrices()
     e = mat.easy
-    proj = [np.einsum("jzyx,jzyx->zyx", mesh.corner(m, b), e) for b in CORNERS]
-    for p, a in enumerate(CORNERS):
+    proj = [np.einsum("jzyx,jzyx->zyx", mesh.corner(m, b), e) for b in mesh.corners]
+    for p, a in enumerate(mesh.corners):
         acc = np.zeros(mesh.cell_shape)
-        for q in range(8):
+        for q in range(len(mesh.corners)):
             acc += Me[p, q] * proj[q]
         mesh.corner(g, a)[...] += -2.0 * mat.Ku * acc * e
 
 
 def _cell_source_gradient(mesh, mat, Hc, g):
     """Gradient of -mu0 int Ms m^h . H for a cell-wise constant field H."""
-    w = -MU0 * mat.Ms * mesh.V / 8.0
-    for a in CORNERS:
+    w = -MU0 * mat.Ms * mesh.V / len(mesh.corners)
+    for a in mesh.corners:
         mesh.corner(g, a)[...] += w * Hc
 
 
@@ -95,11 +97,12 @@ def _cell_source_gradient(mesh, mat, Hc, g):
 # demagnetisation
 # ---------------------------------------------------------------------------
 def cell_average(mesh, m):
-    """mbar_c = (1/8) sum_i m_{c+i}: the exact cell mean of the trilinear m^h."""
+    """mbar_c = (1/8) sum_i m_{c+i} (1/4 under the film basis): the exact cell
+    mean of the nodal m^h."""
     acc = np.zeros(m.shape[:-3] + mesh.cell_shape)
-    for a in CORNERS:
+    for a in mesh.corners:
         acc += mesh.corner(m, a)
-    return acc / 8.0
+    return acc / len(mesh.corners)
 
 
 _SIGNS = {  # parity of each component under d_k -> -d_k, axes (x, y, z)
@@ -236,22 +239,22 @@ def energies(mesh, mat, m, terms=ALL_TERMS, t=0.0):
     out = {"exchange": 0.0, "demag": 0.0, "anisotropy": 0.0, "zeeman": 0.0}
     if terms & EXCHANGE:
         e = 0.0
-        for p, a in enumerate(CORNERS):
+        for p, a in enumerate(mesh.corners):
             ma = mesh.corner(m, a)
-            for q, b in enumerate(CORNERS):
+            for q, b in enumerate(mesh.corners):
                 e += K[p, q] * np.sum(mat.A * np.sum(ma * mesh.corner(m, b), axis=0))
         out["exchange"] = e
     if terms & ANISOTROPY and mat.Ku is not None:
-        proj = [np.sum(mesh.corner(m, a) * mat.easy, axis=0) for a in CORNERS]
+        proj = [np.sum(mesh.corner(m, a) * mat.easy, axis=0) for a in mesh.corners]
         e = 0.0
-        for p in range(8):
-            for q in range(8):
+        for p in range(len(mesh.corners)):
+            for q in range(len(mesh.corners)):
                 e -= Me[p, q] * np.sum(mat.Ku * proj[p] * proj[q])
         out["anisotropy"] = e
     if terms & ZEEMAN:
         H = external_cell_field(mesh, mat, t)
-        msum = 8.0 * cell_average(mesh, m)
-        out["zeeman"] = -MU0 * np.sum(mat.Ms * mesh.V / 8.0 * np.sum(H * msum, axis=0))
+        msum = len(mesh.corners) * cell_average(mesh, m)
+        out["zeeman"] = -MU0 * np.sum(mat.Ms * mesh.V / len(mesh.corners) * np.sum(H * msum, axis=0))
     if terms & DEMAG:
         Hc = demag_cell_field(mesh, mat, m)
         mbar = cell_average(mesh, m)

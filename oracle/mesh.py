@@ -3,6 +3,12 @@
 Follows Sec. 3.1 of the paper: cells c and nodes n = c + i with the local
 vertex index i in {0,1}^3, trilinear nodal basis functions (Eq. nodal_basis)
 and cell-wise constant material parameters (Eqs. ms_discrete, cell_basis).
+
+The thin-film basis of Sec. 3.3 (low-dimensional geometries) keeps the
+in-plane bilinear functions and makes them constant along z, with the weak
+form still integrated over the full cell: a single layer of cells then
+carries one layer of (N1 + 1) x (N2 + 1) nodes, and a cell has the 4 local
+vertices (i1, i2, 0).
 """
 from dataclasses import dataclass, field
 from itertools import product
@@ -18,14 +24,29 @@ MU0 = 4.0e-7 * np.pi
 CORNERS = [(i1, i2, i3) for i3 in (0, 1) for i2 in (0, 1) for i1 in (0, 1)]
 
 
-class Mesh:
-    """Regular cuboid grid of N1 x N2 x N3 cells of size h1 x h2 x h3 (Sec. 3.1)."""
+# the 4 local vertices of a cell under the thin-film basis (constant along z)
+FILM_CORNERS = [(i1, i2, 0) for i2 in (0, 1) for i1 in (0, 1)]
 
-    def __init__(self, n, h):
+
+class Mesh:
+    """Regular cuboid grid of N1 x N2 x N3 cells of size h1 x h2 x h3 (Sec. 3.1).
+
+    basis "3d": trilinear nodal functions, (N1+1)(N2+1)(N3+1) nodes;
+    basis "film": bilinear in-plane functions constant along z (Sec. 3.3),
+    one cell layer (N3 = 1) and (N1+1)(N2+1) nodes.
+    """
+
+    def __init__(self, n, h, basis="3d"):
         self.n = tuple(int(v) for v in n)
         self.h = tuple(float(v) for v in h)
         if min(self.n) < 1 or min(self.h) <= 0:
             raise ValueError("mesh needs n >= 1 and h > 0")
+        if basis not in ("3d", "film"):
+            raise ValueError("basis is '3d' or 'film'")
+        if basis == "film" and self.n[2] != 1:
+            raise ValueError("the film basis takes one layer of cells")
+        self.basis = basis
+        self.corners = CORNERS if basis == "3d" else FILM_CORNERS
         self.V = self.h[0] * self.h[1] * self.h[2]
 
     @property
@@ -36,7 +57,7 @@ class Mesh:
     @property
     def node_shape(self):
         n1, n2, n3 = self.n
-        return (n3 + 1, n2 + 1, n1 + 1)
+        return (n3 + 1 if self.basis == "3d" else 1, n2 + 1, n1 + 1)
 
     @property
     def n_cells(self):
@@ -44,7 +65,7 @@ class Mesh:
 
     @property
     def n_nodes(self):
-        return (self.n[0] + 1) * (self.n[1] + 1) * (self.n[2] + 1)
+        return int(np.prod(self.node_shape))
 
     def corner(self, f, i):
         """View of a nodal array at the nodes c + i of every cell c.
@@ -58,16 +79,27 @@ class Mesh:
 
     # --- element matrices -------------------------------------------------
     def element_matrices(self):
-        """Exact element stiffness K^e and mass M^e of the Q1 basis, 8 x 8.
+        """Exact element stiffness K^e and mass M^e, one row per local vertex.
 
         K^e_ab = int_cell grad(phi_a) . grad(phi_b),  M^e_ab = int_cell phi_a phi_b,
         with phi the trilinear reference functions of Eq. (nodal_basis) scaled
         to the cell.  Both factor into 1D integrals per axis; 2-point Gauss
-        quadrature per axis is exact for these integrands.
+        quadrature per axis is exact for these integrands.  Under the film
+        basis the z factor is constant: its integral is h3 and its derivative
+        vanishes.
         """
-        K = np.zeros((8, 8))
-        M = np.zeros((8, 8))
+        nc = len(self.corners)
+        K = np.zeros((nc, nc))
+        M = np.zeros((nc, nc))
         h = self.h
+        if self.basis == "film":
+            for p, a in enumerate(self.corners):
+                for q, b in enumerate(self.corners):
+                    mx, my = (h[k] * (2.0 if a[k] == b[k] else 1.0) / 6.0 for k in range(2))
+                    sx, sy = ((1.0 if a[k] == b[k] else -1.0) / h[k] for k in range(2))
+                    K[p, q] = (sx * my + mx * sy) * h[2]
+                    M[p, q] = mx * my * h[2]
+            return K, M
         # 1D integrals on [0, hk] of the two linear hat pieces
         def s1(a, b, hk):  # int phi_a' phi_b'
             return (1.0 if a == b else -1.0) / hk
@@ -105,11 +137,25 @@ class Mesh:
             return out
 
         h = self.h
+        if self.basis == "film":
+            # the 2D reference functions of Sec. 3.3, constant along x3
+            def phi(i, x):
+                return np.prod([1 - i[k] + (2 * i[k] * x[k] - x[k]) for k in range(2)])
+
+            def dphi(i, x, k):
+                if k == 2:
+                    return 0.0
+                out = 1.0
+                for l in range(2):
+                    out *= (2 * i[l] - 1) if l == k else 1 - i[l] + (2 * i[l] * x[l] - x[l])
+                return out
+            K = np.zeros((4, 4))
+            M = np.zeros((4, 4))
         for q in product(range(2), repeat=3):
             x = [g[q[0]], g[q[1]], g[q[2]]]
             wt = w[q[0]] * w[q[1]] * w[q[2]] * self.V
-            for p, a in enumerate(CORNERS):
-                for r, b in enumerate(CORNERS):
+            for p, a in enumerate(self.corners):
+                for r, b in enumerate(self.corners):
                     M[p, r] += wt * phi(a, x) * phi(b, x)
                     K[p, r] += wt * sum(dphi(a, x, k) * dphi(b, x, k) / h[k] ** 2
                                         for k in range(3))

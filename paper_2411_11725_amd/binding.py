@@ -15,6 +15,7 @@ NM_OK, NM_EINVAL, NM_ENOMEM, NM_EHIP, NM_ENOTREADY = 0, -1, -2, -3, -4
 NM_ENONFINITE, NM_ESTEPSIZE, NM_EBUDGET, NM_EUNSUPPORTED = -5, -6, -7, -8
 NM_T_EXCHANGE, NM_T_DEMAG, NM_T_ANIS, NM_T_ZEEMAN, NM_T_ALL = 1, 2, 4, 8, 15
 NM_RK4, NM_DP45 = 1, 2
+NM_BASIS_3D, NM_BASIS_FILM = 0, 1
 
 # entry points declared in include/nm.h
 EXPORTS = [
@@ -29,7 +30,8 @@ PROF_SLOTS = ["xfwd", "yfwd", "conv", "yinv", "xinv", "stencil", "control", "oth
 
 
 class nm_mesh_desc(ctypes.Structure):
-    _fields_ = [("n", c_int * 3), ("h", c_double * 3), ("gamma", c_double), ("stream", c_void_p)]
+    _fields_ = [("n", c_int * 3), ("h", c_double * 3), ("gamma", c_double), ("stream", c_void_p),
+                ("basis", c_int)]
 
 
 class nm_material(ctypes.Structure):
@@ -137,9 +139,10 @@ def _stream_handle(stream):
 # ---------------------------------------------------------------- entry points
 def nm_mesh_create(n, h, gamma, Ms, A, alpha, Ku=None, easy=None, h_cell=None,
                    h_uniform=(0.0, 0.0, 0.0), drive_mask=None, drive_amp=(0.0, 0.0, 0.0),
-                   drive_freq=0.0, drive_phase=0.0, stream=None):
+                   drive_freq=0.0, drive_phase=0.0, stream=None, basis=NM_BASIS_3D):
     """Create a mesh from float32 device tensors (copied by the library)."""
-    desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), _stream_handle(stream))
+    desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), _stream_handle(stream),
+                        int(basis))
     mat = nm_material(_ptr(Ms), _ptr(A), _ptr(alpha), _ptr(Ku), _ptr(easy), _ptr(h_cell),
                       (c_float * 3)(*h_uniform), _ptr(drive_mask), (c_float * 3)(*drive_amp),
                       float(drive_freq), float(drive_phase))
@@ -166,8 +169,8 @@ def nm_mesh_tuning(mesh, y=None, z=None):
     return yy.value, zz.value
 
 
-def nm_mesh_footprint_bytes(n, h, gamma=2.211e5, integrator=NM_DP45):
-    desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), None)
+def nm_mesh_footprint_bytes(n, h, gamma=2.211e5, integrator=NM_DP45, basis=NM_BASIS_3D):
+    desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), None, int(basis))
     return lib().nm_mesh_footprint_bytes(ctypes.byref(desc), integrator)
 
 
@@ -299,7 +302,8 @@ def mesh_from_problem(p, device="cuda", stream=None, tensor=True):
                           h_uniform=tuple(float(v) for v in p["h_uniform"]),
                           drive_mask=arrays["drive_mask"],
                           drive_amp=tuple(float(v) for v in p["drive_amp"]),
-                          drive_freq=p["drive_freq"], drive_phase=p["drive_phase"], stream=stream)
+                          drive_freq=p["drive_freq"], drive_phase=p["drive_phase"], stream=stream,
+                          basis=NM_BASIS_FILM if p.get("basis", "3d") == "film" else NM_BASIS_3D)
     if tensor:
         nm_demag_tensor_init(mesh)
     return mesh

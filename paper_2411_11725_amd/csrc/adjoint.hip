@@ -129,19 +129,21 @@ __global__ void __launch_bounds__(256) k_add_dl(float *__restrict__ y, const Adj
     if (i < n) y[i] += S->dl[off + i];
 }
 
-// grad_c += mu0 Ms_c V/8 sum_{n in c} v_n
+// grad_c += mu0 Ms_c V/8 sum_{n in c} v_n (the 4 nodes of a cell under the
+// film basis, NZ = 1: the field map enters each of them once)
 __global__ void __launch_bounds__(256)
 k_cell_gather(const float *__restrict__ v, const float *__restrict__ wc, float *__restrict__ grad,
-              int N1, int N2, int N3) {
+              int N1, int N2, int N3, int NZ) {
     const long long nc = (long long)N1 * N2 * N3;
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
     if (c >= nc) return;
     const int NX = N1 + 1, NY = N2 + 1;
-    const long long nn = (long long)NX * NY * (N3 + 1);
+    const long long nn = (long long)NX * NY * NZ;
     const int cx = (int)(c % N1), cy = (int)((c / N1) % N2), cz = (int)(c / ((long long)N1 * N2));
     for (int k = 0; k < 3; ++k) {
         float s = 0.f;
         for (int b = 0; b < 8; ++b) {
+            if (cz + (b >> 2) >= NZ) continue;
             const long long nb = ((long long)(cz + (b >> 2)) * NY + cy + ((b >> 1) & 1)) * NX + cx + (b & 1);
             s += v[k * nn + nb];
         }
@@ -344,7 +346,7 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
     hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, lambda, lam, n3);
     if (gather)
         hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
-                           m->wc, grad_hcell, m->N1, m->N2, m->N3);
+                           m->wc, grad_hcell, m->N1, m->N2, m->N3, m->NZ);
     NM_HIP(hipGetLastError(), who);
     return NM_OK;
 }

@@ -48,13 +48,16 @@ __global__ void k_cell_setup(const float *__restrict__ Ms, const float *__restri
     A2[c] = 2.f * A[c];
 }
 
-// M_n = mu0 sum_{c containing n} Ms_c V/8 (Eq. mass_lumping); Ms-weighted damping
+// M_n = mu0 sum_{c containing n} Ms_c V/8 (Eq. mass_lumping); Ms-weighted damping.
+// Under the film basis the single node layer sits at z = 0: its 4 cells give
+// half the film mass, consistent with the node kernel's gradient there (the
+// field -g/M is the film's).
 __global__ void k_node_setup(const float *__restrict__ Ms, const float *__restrict__ alpha,
                              const float *__restrict__ wc, float *__restrict__ inv_mass,
                              float *__restrict__ alpha_n, float *__restrict__ gp_n, int N1, int N2,
-                             int N3, double gamma) {
+                             int N3, int NZ, double gamma) {
     const int NX = N1 + 1, NY = N2 + 1;
-    const long long nn = (long long)NX * NY * (N3 + 1);
+    const long long nn = (long long)NX * NY * NZ;
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     if (n >= nn) return;
     const int x = (int)(n % NX), y = (int)((n / NX) % NY), z = (int)(n / ((long long)NX * NY));
@@ -111,6 +114,8 @@ struct Sizes {
 static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
     const int n1 = d->n[0], n2 = d->n[1], n3 = d->n[2];
     if (n1 < 2 || n2 < 2 || n3 < 1) return false;
+    if (d->basis != NM_BASIS_3D && d->basis != NM_BASIS_FILM) return false;
+    if (d->basis == NM_BASIS_FILM && n3 != 1) return false;
     s->P1 = pad_len(n1);
     s->P2 = pad_len(n2);
     s->P3 = pad_len(n3);
@@ -119,7 +124,7 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
     s->KP = (s->K1 + 15) / 16 * 16;
     s->P2h = s->P2 / 2 + 1;
     s->P3h = s->P3 / 2 + 1;
-    s->nn = (long long)(n1 + 1) * (n2 + 1) * (n3 + 1);
+    s->nn = (long long)(n1 + 1) * (n2 + 1) * (d->basis == NM_BASIS_FILM ? 1 : n3 + 1);
     s->nc = (long long)n1 * n2 * n3;
     s->spec = 3LL * n3 * s->P2 * s->KP;
     s->tensor = 6LL * s->P3h * s->P2h * s->KP;
@@ -204,7 +209,8 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     *out = nullptr;
     Sizes s;
     NM_REQUIRE(sizes_of(d, &s), NM_EINVAL,
-               "nm_mesh_create: need n[0], n[1] >= 2, n[2] >= 1 and padded lengths <= 1024");
+               "nm_mesh_create: need n[0], n[1] >= 2, n[2] >= 1 (= 1 for the film basis), a known basis "
+               "and padded lengths <= 1024");
     for (int k = 0; k < 3; ++k)
         NM_REQUIRE(std::isfinite(d->h[k]) && d->h[k] > 0.0, NM_EINVAL, "nm_mesh_create: h must be > 0");
     NM_REQUIRE(std::isfinite(d->gamma) && d->gamma > 0.0, NM_EINVAL, "nm_mesh_create: gamma must be > 0");
@@ -221,7 +227,9 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     m->N3 = d->n[2];
     m->NX = m->N1 + 1;
     m->NY = m->N2 + 1;
-    m->NZ = m->N3 + 1;
+    // the film basis keeps one node layer: every kernel reads the node layer
+    // above a cell (z + 1) at z, which makes m constant along z
+    m->NZ = d->basis == NM_BASIS_FILM ? 1 : m->N3 + 1;
     m->P1 = s.P1;
     m->P2 = s.P2;
     m->P3 = s.P3;
@@ -312,7 +320,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
                            Atmp, m->wc, m->A2, nc, (float)(kMu0 * m->V / 8.0));
         hipLaunchKernelGGL(k_node_setup, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->Ms,
                            m->acc, m->wc, m->inv_mass, m->alpha_n, m->gp_n, m->N1, m->N2, m->N3,
-                           m->gamma);
+                           m->NZ, m->gamma);
         e = hipGetLastError();
         if (e == hipSuccess) e = launch_cell_pack(m);
     }
@@ -560,13 +568,17 @@ static int tail_slot(int batch) {
     return -1;
 }
 
+int batch_for(double est, int batch) {
+    int b = 1;
+    while (b < batch && (double)b < est) b *= 2;
+    return std::min(b, batch);
+}
+
 int next_batch(const nm_mesh *m, int batch) {
     const Ctrl *C = m->ctrl_host;
     double est = (double)(C->max_accepted - C->accepted);
     if (C->dt_prop > 0.0) est = std::fmin(est, std::ceil((C->t_end - C->t) / C->dt_prop * (1.0 + 1e-9)));
-    int b = 1;
-    while (b < batch && (double)b < est) b *= 2;
-    return std::min(b, batch);
+    return batch_for(est, batch);
 }
 
 hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int batch) {
@@ -689,7 +701,7 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         return NM_OK;
     } else {
         long long seen = -1;
-        int b = batch;
+        int b = batch_for(std::fmin((double)max_steps, std::ceil((t_end - clk->t) / clk->dt * (1.0 + 1e-9))), batch);
         for (;;) {
             NM_HIP(step_batch(m, mag, NM_DP45, terms, b), "nm_llg_step");
             NM_HIP(ctrl_readback(m), "nm_llg_step");

@@ -52,7 +52,7 @@ __device__ __forceinline__ float2 keep(float2 v, bool ok) {
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
-       const float2 *__restrict__ tw, int N1, int N2, int N3, int P2, int KP,
+       const float2 *__restrict__ tw, int N1, int N2, int N3, int NZ, int P2, int KP,
        const Ctrl *__restrict__ ctrl) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
@@ -66,8 +66,10 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     const int y0 = blockIdx.x * RB, z = blockIdx.y;
     const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
-    const unsigned nn = (unsigned)NX * NY * (N3 + 1);
-    const unsigned plane = (unsigned)NX * NY;
+    const unsigned nn = (unsigned)NX * NY * NZ;
+    // node layer z + 1 of the cell layer z; the same layer under the film
+    // basis (one node layer), which sums it twice: the mean of 4 corners
+    const unsigned plane = NZ > 1 ? (unsigned)NX * NY : 0u;
     // node pair sums m(x, y, z) + m(x, y, z + 1), at clamped nodes (slots
     // past the row end and rows past the plane are never used unzeroed)
     float za[NA];
@@ -614,7 +616,7 @@ template <int L>
 static void launch_x_fwd(nm_mesh *m, const float *mag, const float2 *tw, const Ctrl *ctrl) {
     constexpr int RB = x_rows_per_block(L);
     NM_LAUNCH(m, NM_PROF_XFWD, (k_xfwd<L>), dim3((m->N2 + RB - 1) / RB, m->N3), dim3(256), 0, mag,
-              m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->P2, m->KP, ctrl);
+              m->Ms, m->spec, tw, m->N1, m->N2, m->N3, m->NZ, m->P2, m->KP, ctrl);
 }
 template <int L>
 static void launch_x_inv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl, int src_mode) {

@@ -202,6 +202,7 @@ hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat from the raw copies
 // two (at most batch) covering what the host mirror of the controller says
 // is left by step count and by time at the proposed step
 int next_batch(const nm_mesh *m, int batch);
+int batch_for(double est, int batch);   // smallest power of two >= est, within 1 .. batch
 void mesh_release(nm_mesh *m);             // free a mesh whose stream work has completed
 hipError_t launch_rk4_advance(nm_mesh *m);
 

@@ -14,6 +14,7 @@
 // the same kernels on its own buffers, so its result does not depend on what
 // else is in the mix.
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -152,7 +153,7 @@ bool admit(nm_server *S, Solve *s) {
     s->clk = nm_clock{0.0, r.dt0, 0, 0, 0, 0.0};
     if (step_begin(s->mesh, s->m_dev, &s->clk, &in, r.t_end, 1L << 40, &s->batch) != NM_OK) return false;
     s->batch = S->desc.attempts_per_launch;
-    s->next = s->batch;
+    s->next = batch_for(std::ceil(r.t_end / r.dt0 * (1.0 + 1e-9)), s->batch);
     s->res.t_admit = now_s();
     return true;
 }

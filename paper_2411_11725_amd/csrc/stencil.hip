@@ -175,8 +175,11 @@ k_node(StencilParams P, StageArgs S) {
     __shared__ float4 sw[NIT > 0 ? NIT * 256 : 1];
     float wv[NIT > 0 ? NIT : 1][3];
     if constexpr (NIT > 0) {
-        const int D = NX * NY - W;                 // window p starts at n0 - NX - 1 + (p - 1) NX NY
-        const int g0 = n0 - NX - 1 - NX * NY;      // = that start minus p W
+        // window p starts at n0 - NX - 1 + (p - 1) NXY; NXY = 0 with one node
+        // layer (the film basis), whose z neighbours are the layer itself
+        const int NXY = NZ > 1 ? NX * NY : 0;
+        const int D = NXY - W;
+        const int g0 = n0 - NX - 1 - NXY;          // = that start minus p W
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int j = tid + 256 * it;
@@ -485,7 +488,9 @@ __global__ void __launch_bounds__(256) k_energy_cells(StencilParams P, const flo
         const int cz = (int)(r / P.N2);
         float v[8][3];
         for (int b = 0; b < 8; ++b) {
-            const long long nb = ((long long)(cz + (b >> 2)) * P.NY + (cy + ((b >> 1) & 1))) * P.NX + cx + (b & 1);
+            // the node layer above the cell (the same layer under the film basis)
+            const long long nb = ((long long)min(cz + (b >> 2), P.NZ - 1) * P.NY + (cy + ((b >> 1) & 1))) * P.NX +
+                                 cx + (b & 1);
             for (int k = 0; k < 3; ++k) v[b][k] = m[k * P.nn + nb];
         }
         if (P.terms & NM_T_EXCHANGE) {

@@ -123,6 +123,17 @@ def magnonic(n=(256, 128, 1), seed=105):
                         drive_amp=(0.0, 1e-3 / MU0_SI, 0.0), drive_freq=10e9)
 
 
+def as_film(p):
+    """The same single-layer problem under the thin-film basis: one node layer
+    (the lower one of m0), the cell arrays unchanged."""
+    if p["n"][2] != 1:
+        raise ValueError("the film basis takes one layer of cells")
+    q = dict(p)
+    q["basis"] = "film"
+    q["m0"] = np.ascontiguousarray(p["m0"][:, :1])
+    return q
+
+
 def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
                  hetero=True, ku_range=(0.0, 5e5)):
     """Small heterogeneous problem used by the parity tests: every term on,

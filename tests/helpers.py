@@ -6,7 +6,7 @@ import oracle
 
 def to_oracle(p):
     """Mesh and float64 Material from a problem dict of float32 arrays."""
-    mesh = oracle.Mesh(p["n"], p["h"])
+    mesh = oracle.Mesh(p["n"], p["h"], basis=p.get("basis", "3d"))
     f = lambda a: None if a is None else np.asarray(a, dtype=np.float64)
     mat = oracle.Material(
         Ms=f(p["Ms"]), A=f(p["A"]), alpha=f(p["alpha"]), gamma=p["gamma"],

@@ -271,6 +271,32 @@ def _film_dp45(max_steps, t_end=0.05e-9):
     return p, g, steps, clk
 
 
+def test_dp45_split_calls_follow_the_same_steps():
+    """The same adaptive run as one call and as calls of 3, 1, 5, 2, ... steps
+    (every last replay of a call is a smaller graph): the same accepted steps
+    and the same state, up to the rounding of the first stage recomputed at
+    each call."""
+    p, g1, steps1, clk1 = _film_dp45(max_steps=1 << 40, t_end=0.01e-9)
+    mesh = B.mesh_from_problem(p)
+    try:
+        m = _dev(p["m0"])
+        clk = B.nm_clock(0.0, 1e-14, 0, 0, 0, 0.0)
+        sizes = [3, 1, 5, 2, 7, 4, 6]
+        k = 0
+        while clk.t < 0.01e-9:
+            before = clk.accepted
+            B.nm_llg_step(mesh, m, clk, B.NM_DP45, B.NM_T_ALL, t_end=0.01e-9, rtol=1e-5, atol=1e-5,
+                          max_steps=sizes[k % len(sizes)])
+            assert clk.accepted - before <= sizes[k % len(sizes)]
+            k += 1
+        g2 = m.cpu().numpy().astype(np.float64)
+    finally:
+        B.nm_mesh_destroy(mesh)
+    assert k >= 3 and clk.t == 0.01e-9
+    assert clk.accepted == clk1.accepted
+    assert np.abs(g2 - g1).max() <= 1e-5
+
+
 def test_dp45_replay_first_steps_pointwise():
     """Replay parity, node by node, while the steps are inside the stability
     region of the exchange modes (the first accepted steps)."""
