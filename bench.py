@@ -47,6 +47,16 @@ WORKLOADS = {
                        desc="thin film 256x64x1 cells (3.9x3.9x3 nm), thin-film basis (one node layer), "
                             "field step (-25,4,0) mT, DP45 rtol 1e-5",
                        make="film_basis", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
+    # a 512 x 512 x 1 film (the largest single-layer grid of 1024-point
+    # transforms) under both bases
+    "film_large": dict(tag="film_512x512x1",
+                       desc="thin film 512x512x1 cells (3.9x3.9x3 nm), 3D basis, field step (-25,4,0) mT, "
+                            "DP45 rtol 1e-5",
+                       make="film_large", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
+    "film_large_basis": dict(tag="film_512x512x1_filmbasis",
+                             desc="thin film 512x512x1 cells (3.9x3.9x3 nm), thin-film basis (one node layer), "
+                                  "field step (-25,4,0) mT, DP45 rtol 1e-5",
+                             make="film_large_basis", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
     "film": dict(tag="film_256x64x1", desc="thin film 256x64x1 cells (3.9x3.9x3 nm), field step (-25,4,0) mT, DP45 rtol 1e-5",
                  make="film", terms=("exchange", "demag", "zeeman"), dt0=1e-13),
     "cube": dict(tag="cube_16x16x4", desc="16x16x4 cells (2 nm), random start, DP45 rtol 1e-5",
@@ -67,6 +77,10 @@ def make_workload(synth, W):
         return synth.block(n=(256, 256, 64))
     if W["make"] == "film_basis":
         return synth.as_film(synth.film())
+    if W["make"] == "film_large":
+        return synth.film(n=(512, 512, 1))
+    if W["make"] == "film_large_basis":
+        return synth.as_film(synth.film(n=(512, 512, 1)))
     return getattr(synth, W["make"])()
 
 
@@ -217,7 +231,7 @@ def adjoint_bench(B, synth, nsteps, ckpt):
     gives the gradient with respect to the per-cell field map."""
     import torch
 
-    from paper_2411_11725_amd.adjoint import LLGTrajectory
+    from paper_2411_11725_amd.adjoint import LLGTrajectory, LLGTrajectoryContinuous
 
     p = synth.magnonic()
     mesh = B.mesh_from_problem(p, device="cuda:0")
@@ -242,6 +256,21 @@ def adjoint_bench(B, synth, nsteps, ckpt):
         torch.cuda.synchronize()
         t_bwd = time.perf_counter() - t0
         gnorm = float(theta.grad.norm())
+        g_disc = theta.grad.clone()
+        # the same gradient by the continuous adjoint (final state only)
+        theta.grad = None
+        w = LLGTrajectoryContinuous.apply(theta, m0, mesh, 5e-14, ckpt, 1, B.NM_T_ALL)
+        (-(w[:, 2][:, region] ** 2).mean()).backward()
+        theta.grad = None
+        torch.cuda.synchronize()
+        traj = LLGTrajectoryContinuous.apply(theta, m0, mesh, 5e-14, nsteps, 1, B.NM_T_ALL)
+        loss = -(traj[:, 2][:, region] ** 2).mean()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t_cont = time.perf_counter() - t0
+        gap = float((theta.grad - g_disc).norm() / g_disc.norm())
     finally:
         B.nm_mesh_destroy(mesh)
     cells = n1 * n2 * n3
@@ -249,7 +278,9 @@ def adjoint_bench(B, synth, nsteps, ckpt):
                         "gradient w.r.t. the per-cell field map" % (n1, n2, n3, nsteps, ckpt),
             "forward_steps_per_s": nsteps / t_fwd, "backward_steps_per_s": nsteps / t_bwd,
             "backward_over_forward": t_bwd / t_fwd,
-            "forward_cell_updates_per_s": 4 * cells * nsteps / t_fwd, "grad_norm": gnorm}
+            "forward_cell_updates_per_s": 4 * cells * nsteps / t_fwd, "grad_norm": gnorm,
+            "continuous_backward_steps_per_s": nsteps / t_cont,
+            "continuous_vs_discrete_gradient_rel_diff": gap}
 
 
 def main():

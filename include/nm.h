@@ -213,6 +213,26 @@ nm_status nm_adjoint_step(nm_mesh *mesh, const float *m0, double t0, double dt, 
 /* Workspace bytes nm_adjoint_step needs for a segment of nsteps steps. */
 size_t nm_adjoint_workspace_bytes(const nm_mesh *mesh, int nsteps);
 
+/* The continuous adjoint of Sec. 4 (Eq. adjoint_system): the joint system
+ *   dm/dt = f(t, m),  da/dt = -(df/dm)^T a,  du/dt = -(df/dtheta)^T a
+ * integrated backwards with nsteps classical RK4 steps of -dt from t_end,
+ * with theta the per-cell applied field map.  No forward state is stored:
+ * m is rebuilt by integrating the LLG equation backwards, which costs
+ * accuracy (O(dt^4) against the discrete adjoint of nm_adjoint_step) and,
+ * for damped dynamics, limits how far back the reconstruction stays close.
+ *   m           device, 3 * n_nodes: m(t_end) in, m(t_end - nsteps dt) out
+ *   a           device, 3 * n_nodes: dL/dm(t_end) in, a at the earlier time
+ *               out (dL/dm there)
+ *   grad_hcell  device, 3 * n_cells or NULL: u, the gradient with respect to
+ *               the field map, added to what it holds; needs NM_T_ZEEMAN
+ * The mesh's stepping buffers serve as scratch (an integration in progress
+ * restarts its first stage at the next nm_llg_step).  Asynchronous on the
+ * mesh stream; NM_EINVAL for NULL arguments, nsteps < 1, dt <= 0, unknown
+ * term bits, NM_T_DEMAG before nm_demag_tensor_init, or a gradient without
+ * NM_T_ZEEMAN. */
+nm_status nm_adjoint_continuous(nm_mesh *mesh, float *m, double t_end, double dt, int nsteps,
+                                unsigned terms, float *a, float *grad_hcell);
+
 /* ------------------------------------------------------------------------
  * Solve server: continuous batching of independent LLG solves of uneven
  * size.  Requests wait in a FIFO queue; a scheduler thread admits them while

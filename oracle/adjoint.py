@@ -126,3 +126,40 @@ def region_mz2_loss(mesh, region, nsteps):
         return g
 
     return loss, dloss
+
+
+def continuous_adjoint(mesh, mat, m_end, t_end, dt, nsteps, a_end, terms, alpha_n=None):
+    """The adjoint system of Sec. 4 (Eq. adjoint_system), integrated backwards.
+
+    From t_end down to t_end - nsteps dt with classical RK4 steps of -dt on the
+    joint state (m, a, u):
+        dm/dt = f(t, m),   da/dt = -(df/dm)^T a,   du/dt = -(df/dtheta)^T a,
+    with m(t_end) = m_end, a(t_end) = a_end = dL/dm(t_end) and u(t_end) = 0.
+    The trajectory m is rebuilt by integrating the LLG equation backwards, so
+    no forward state is stored.  Returns (m, a, u) at the earlier time: u is
+    the gradient of L with respect to the field map theta, a the one with
+    respect to the initial state."""
+    from .llg import llg_rhs
+    if alpha_n is None:
+        alpha_n = nodal_alpha(mesh, mat)
+
+    def F(t, m, a):
+        f = llg_rhs(mesh, mat, m, t, terms, alpha_n)
+        ja, jth = rhs_vjp(mesh, mat, m, t, a, terms, alpha_n)
+        return f, -ja, -jth
+
+    h = -float(dt)
+    m = np.array(m_end, dtype=np.float64)
+    a = np.array(a_end, dtype=np.float64)
+    u = np.zeros((3,) + mesh.cell_shape)
+    t = float(t_end)
+    for _ in range(nsteps):
+        f1, g1, q1 = F(t, m, a)
+        f2, g2, q2 = F(t + 0.5 * h, m + 0.5 * h * f1, a + 0.5 * h * g1)
+        f3, g3, q3 = F(t + 0.5 * h, m + 0.5 * h * f2, a + 0.5 * h * g2)
+        f4, g4, q4 = F(t + h, m + h * f3, a + h * g3)
+        m = m + h / 6.0 * (f1 + 2.0 * f2 + 2.0 * f3 + f4)
+        a = a + h / 6.0 * (g1 + 2.0 * g2 + 2.0 * g3 + g4)
+        u = u + h / 6.0 * (q1 + 2.0 * q2 + 2.0 * q3 + q4)
+        t = t + h
+    return m, a, u

@@ -8,7 +8,16 @@ returns the states after every `sample_every`-th step, shape
 samples can be back-propagated: the backward pass walks the checkpoints
 (every `ckpt_every` steps) from last to first and calls nm_adjoint_step,
 which recomputes the segment and runs the exact discrete adjoint on the GPU.
-Gradients flow to theta and m0.  This module only marshals arguments.
+Gradients flow to theta and m0.
+
+LLGTrajectoryContinuous.apply(theta, m0, mesh, dt, nsteps, sample_every,
+terms) returns the same samples but keeps only the final state: its backward
+pass integrates the continuous adjoint system of Sec. 4 backwards with
+nm_adjoint_continuous, rebuilding the trajectory as it goes and adding each
+sample's loss gradient to the co-state at its time (the multi-time objective
+the paper describes).  Memory stays that of the forward pass; the gradient
+differs from the discrete one by O(dt^4).  This module only marshals
+arguments.
 """
 import torch
 
@@ -77,3 +86,37 @@ class LLGTrajectory(torch.autograd.Function):
                               dl_dm=dl, dl_every=sample_every, grad_hcell=gth,
                               work=_workspace(mesh, nseg, lam.device))
         return gth, lam, None, None, None, None, None, None, None
+
+
+class LLGTrajectoryContinuous(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, m0, mesh, dt, nsteps, sample_every, terms, t0=0.0):
+        if nsteps < 1 or sample_every < 1 or nsteps % sample_every:
+            raise ValueError("nsteps must be a positive multiple of sample_every >= 1")
+        theta = theta.detach().contiguous()
+        B.nm_mesh_set_field(mesh, theta)
+        m = m0.detach().clone().contiguous()
+        samples = []
+        clk = B.nm_clock(t0, dt, 0, 0, 0, 0.0)
+        for k in range(sample_every, nsteps + 1, sample_every):
+            B.nm_llg_step(mesh, m, clk, B.NM_RK4, terms, t_end=t0 + k * dt, max_steps=sample_every)
+            samples.append(m.clone())
+        ctx.mesh = mesh
+        ctx.args = (dt, nsteps, sample_every, terms, t0)
+        ctx.save_for_backward(m)
+        ctx.theta_shape = theta.shape
+        return torch.stack(samples)
+
+    @staticmethod
+    def backward(ctx, grad_samples):
+        dt, nsteps, sample_every, terms, t0 = ctx.args
+        (m_end,) = ctx.saved_tensors
+        g = grad_samples.contiguous()
+        m = m_end.clone()
+        a = torch.zeros_like(m)
+        gth = torch.zeros(ctx.theta_shape, dtype=torch.float32, device=m.device)
+        for si in range(nsteps // sample_every - 1, -1, -1):
+            a += g[si]
+            B.nm_adjoint_continuous(ctx.mesh, m, t0 + (si + 1) * sample_every * dt, dt, sample_every, terms, a,
+                                    grad_hcell=gth)
+        return gth, a, None, None, None, None, None, None

@@ -22,7 +22,7 @@ EXPORTS = [
     "nm_mesh_create", "nm_mesh_destroy", "nm_mesh_info", "nm_mesh_footprint_bytes",
     "nm_mesh_set_field", "nm_mesh_tuning", "nm_demag_tensor_init", "nm_newell_octant", "nm_heff",
     "nm_demag_cell_field", "nm_llg_rhs", "nm_energy", "nm_llg_step", "nm_adjoint_step",
-    "nm_adjoint_workspace_bytes", "nm_server_create", "nm_server_destroy", "nm_serve_submit",
+    "nm_adjoint_workspace_bytes", "nm_adjoint_continuous", "nm_server_create", "nm_server_destroy", "nm_serve_submit",
     "nm_serve_poll", "nm_server_clock", "nm_profile_enable",
     "nm_profile_read", "nm_last_error",
 ]
@@ -103,6 +103,7 @@ def lib():
             "nm_llg_step": ([P, P, POINTER(nm_clock), POINTER(nm_integrator), c_double, c_long], c_int),
             "nm_adjoint_step": ([P, P, c_double, c_double, c_int, c_uint, P, c_int, P, P, P], c_int),
             "nm_adjoint_workspace_bytes": ([P, c_int], ctypes.c_size_t),
+            "nm_adjoint_continuous": ([P, P, c_double, c_double, c_int, c_uint, P, P], c_int),
             "nm_server_create": ([POINTER(nm_server_desc), POINTER(c_void_p)], c_int),
             "nm_server_destroy": ([P], c_int),
             "nm_serve_submit": ([P, POINTER(nm_solve_request), POINTER(ctypes.c_uint64)], c_int),
@@ -213,6 +214,14 @@ def nm_llg_step(mesh, m, clock, method=NM_RK4, terms=NM_T_ALL, t_end=0.0, max_st
     _check(lib().nm_llg_step(mesh, _ptr(m), ctypes.byref(clock), ctypes.byref(integ),
                              float(t_end), int(max_steps)))
     return clock
+
+
+def nm_adjoint_continuous(mesh, m, t_end, dt, nsteps, terms, a, grad_hcell=None):
+    """Backward integration of the continuous adjoint system; m and a (device
+    tensors) are updated in place, grad_hcell accumulates the field-map
+    gradient."""
+    _check(lib().nm_adjoint_continuous(mesh, _ptr(m), float(t_end), float(dt), int(nsteps), int(terms),
+                                       _ptr(a), _ptr(grad_hcell)))
 
 
 def nm_adjoint_workspace_bytes(mesh, nsteps):

@@ -82,6 +82,74 @@ k_axpby(float *__restrict__ y, const float *__restrict__ x, float a, const float
     y[i] = a * x[i] + (z ? b * z[i] : 0.f);
 }
 
+// ---- continuous adjoint (Eq. adjoint_system, integrated backwards)
+// At a stage state (y, a) with field H(y): f = f(y) (the LLG right-hand
+// side), vjp = df/dm^T a at fixed H, v = vs M^-1 df/dH^T a; vsum += wv v
+// (the field-map density, weighted by the quadrature factor).  M^-1 is of
+// order 1e25 in SI units: without the scale vs (a power of two near dt) the
+// linear field of v would overflow float32.
+__global__ void __launch_bounds__(256)
+k_cadj_node(const float *__restrict__ y, const float *__restrict__ H, const float *__restrict__ a,
+            const float *__restrict__ inv_mass, const float *__restrict__ alpha_n,
+            const float *__restrict__ gp_n, float *__restrict__ f, float *__restrict__ vjp,
+            float *__restrict__ v, float *__restrict__ vsum, float wv, float vs, long long nn) {
+    const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (n >= nn) return;
+    float m[3], h[3], c[3];
+    for (int k = 0; k < 3; ++k) {
+        m[k] = y[k * nn + n];
+        h[k] = H[k * nn + n];
+        c[k] = a[k * nn + n];
+    }
+    const float ga = gp_n[n], gb = alpha_n[n] * gp_n[n], im = inv_mass[n];
+    // f = -g' m x H - alpha g' m x (m x H)
+    const float mxh[3] = {m[1] * h[2] - m[2] * h[1], m[2] * h[0] - m[0] * h[2], m[0] * h[1] - m[1] * h[0]};
+    const float mmh[3] = {m[1] * mxh[2] - m[2] * mxh[1], m[2] * mxh[0] - m[0] * mxh[2], m[0] * mxh[1] - m[1] * mxh[0]};
+    const float wm = c[0] * m[0] + c[1] * m[1] + c[2] * m[2];
+    const float mh = m[0] * h[0] + m[1] * h[1] + m[2] * h[2];
+    const float wh = c[0] * h[0] + c[1] * h[1] + c[2] * h[2];
+    const float mm = m[0] * m[0] + m[1] * m[1] + m[2] * m[2];
+    const float hxw[3] = {h[1] * c[2] - h[2] * c[1], h[2] * c[0] - h[0] * c[2], h[0] * c[1] - h[1] * c[0]};
+    const float mxw[3] = {m[1] * c[2] - m[2] * c[1], m[2] * c[0] - m[0] * c[2], m[0] * c[1] - m[1] * c[0]};
+    for (int k = 0; k < 3; ++k) {
+        f[k * nn + n] = -ga * mxh[k] - gb * mmh[k];
+        vjp[k * nn + n] = -ga * hxw[k] - gb * (h[k] * wm + mh * c[k] - 2.f * m[k] * wh);
+        const float vv = (ga * mxw[k] - gb * (wm * m[k] - mm * c[k])) * im * vs;
+        v[k * nn + n] = vv;
+        if (vsum) vsum[k * nn + n] += wv * vv;
+    }
+}
+
+// Stage s of a backward RK4 step of size h on (m, a): g = -(vjp + M Hv / vs)
+// is da/dt (Hv is the linear field of the scaled v); the increments are accumulated with weight b, and either the next
+// stage state (m + ch f, a + ch g) is written or, after the last stage, the
+// step is applied: m += h/6 (acc_m + b f), a += h/6 (acc_a + b g).
+__global__ void __launch_bounds__(256)
+k_cadj_combine(const float *__restrict__ f, const float *__restrict__ vjp, const float *__restrict__ Hv,
+               const float *__restrict__ inv_mass, int has_lin, float inv_vs, float *__restrict__ m,
+               float *__restrict__ a,
+               float *__restrict__ acc_m, float *__restrict__ acc_a, float *__restrict__ ym,
+               float *__restrict__ ya, float b, float ch, int first, int last, float h6, long long nn) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= 3 * nn) return;
+    const long long n = i % nn;
+    const float im = inv_mass[n];
+    const float M = im > 0.f ? 1.f / im : 0.f;
+    // (M Hv) first: M ~ 1e-26 and Hv / vs alone can exceed the float range
+    const float g = -(vjp[i] + (has_lin ? (M * Hv[i]) * inv_vs : 0.f));
+    const float am = (first ? 0.f : acc_m[i]) + b * f[i];
+    const float aa = (first ? 0.f : acc_a[i]) + b * g;
+    if (last) {
+        m[i] += h6 * am;
+        a[i] += h6 * aa;
+    } else {
+        acc_m[i] = am;
+        acc_a[i] = aa;
+        ym[i] = m[i] + ch * f[i];
+        ya[i] = a[i] + ch * g;
+    }
+}
+
 // Per-segment inputs of a recorded adjoint segment, read by the kernels of the
 // graph at run time so that one graph serves every segment of the same length
 struct AdjSlots {
@@ -344,6 +412,75 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
         NM_HIP(hipGraphLaunch(m->adj_gexec, st), who);
     }
     hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, lambda, lam, n3);
+    if (gather)
+        hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
+                           m->wc, grad_hcell, m->N1, m->N2, m->N3, m->NZ);
+    NM_HIP(hipGetLastError(), who);
+    return NM_OK;
+}
+
+// The adjoint system of Sec. 4 integrated backwards: classical RK4 steps of
+// h = -dt on (m, a, u).  Per stage the field H(y) gives f and the node-local
+// part of (df/dm)^T a; the transpose of the linear field is the forward
+// linear field of v = M^-1 (df/dH)^T a (as in the discrete adjoint), and the
+// field-map density v is accumulated with the weight -h/6 b_s of u's
+// quadrature, then gathered to cells once.  The mesh's stepping buffers
+// hold the stage vectors, so no trajectory is stored.
+extern "C" nm_status nm_adjoint_continuous(nm_mesh *m, float *mag, double t_end, double dt, int nsteps,
+                                           unsigned terms, float *a, float *grad_hcell) {
+    const char *who = "nm_adjoint_continuous";
+    NM_REQUIRE(m && mag && a, NM_EINVAL, "nm_adjoint_continuous: NULL argument");
+    NM_REQUIRE(nsteps >= 1, NM_EINVAL, "nm_adjoint_continuous: nsteps must be >= 1");
+    NM_REQUIRE(std::isfinite(t_end) && std::isfinite(dt) && dt > 0.0, NM_EINVAL,
+               "nm_adjoint_continuous: need finite t_end and dt > 0");
+    NM_REQUIRE(!(terms & ~(unsigned)NM_T_ALL), NM_EINVAL, "nm_adjoint_continuous: unknown term bits");
+    NM_REQUIRE(!(terms & NM_T_DEMAG) || m->tensor_ready, NM_EINVAL,
+               "nm_adjoint_continuous: NM_T_DEMAG needs nm_demag_tensor_init first");
+    NM_REQUIRE(!grad_hcell || (terms & NM_T_ZEEMAN), NM_EINVAL,
+               "nm_adjoint_continuous: a field-map gradient needs NM_T_ZEEMAN");
+    const long long nn = m->n_nodes, n3 = 3 * nn;
+    const dim3 g3((unsigned)((n3 + 255) / 256)), gn((unsigned)((nn + 255) / 256));
+    hipStream_t st = m->stream;
+    float *ym = m->y[0], *ya = m->y[1], *H = m->acc, *f = m->k[0], *vjp = m->k[1], *v = m->k[2];
+    float *Hv = m->k[3], *accm = m->k[4], *acca = m->k[5], *vsum = m->k[6];
+    const unsigned lin = terms & ~(unsigned)NM_T_ZEEMAN;
+    const bool gather = grad_hcell != nullptr;
+    const double h = -dt;
+    const double c[4] = {0.0, 0.5, 0.5, 1.0}, b[4] = {1.0, 2.0, 2.0, 1.0};
+    // v is scaled by a power of two near dt (exact in float32), as the
+    // discrete adjoint's co-vectors carry dt
+    const double vs = std::ldexp(1.0, (int)std::floor(std::log2(dt)));
+    if (gather) hipLaunchKernelGGL(k_vzero, g3, dim3(256), 0, st, vsum, n3);
+    for (int j = 0; j < nsteps; ++j) {
+        const double t = t_end + j * h;
+        for (int s = 0; s < 4; ++s) {
+            const float *yin = s == 0 ? mag : ym;
+            const float *ain = s == 0 ? a : ya;
+            // H at the stage state and time
+            if (terms & NM_T_DEMAG)
+                NM_HIP(demag_forward_conv_inverse(m, yin, (terms & NM_T_ZEEMAN) ? 2 : 1), who);
+            StageSpec sp{};
+            sp.mode = kModeField;
+            sp.in = yin;
+            sp.out = H;
+            sp.t0 = t + c[s] * h;
+            NM_HIP(launch_stencil(m, terms, sp), who);
+            hipLaunchKernelGGL(k_cadj_node, gn, dim3(256), 0, st, yin, H, ain, m->inv_mass, m->alpha_n, m->gp_n,
+                               f, vjp, v, gather ? vsum : nullptr, (float)(-h / 6.0 * b[s] / vs), (float)vs, nn);
+            if (lin) {
+                if (lin & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, v, 1), who);
+                StageSpec sl{};
+                sl.mode = kModeField;
+                sl.in = v;
+                sl.out = Hv;
+                NM_HIP(launch_stencil(m, lin, sl), who);
+            }
+            hipLaunchKernelGGL(k_cadj_combine, g3, dim3(256), 0, st, f, vjp, Hv, m->inv_mass, lin ? 1 : 0,
+                               (float)(1.0 / vs), mag, a,
+                               accm, acca, ym, ya, (float)b[s], (float)((s < 3 ? c[s + 1] : 0.0) * h), s == 0 ? 1 : 0,
+                               s == 3 ? 1 : 0, (float)(h / 6.0), nn);
+        }
+    }
     if (gather)
         hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
                            m->wc, grad_hcell, m->N1, m->N2, m->N3, m->NZ);

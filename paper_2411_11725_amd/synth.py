@@ -91,9 +91,9 @@ def standard_cube(seed=101):
                         seed=seed)
 
 
-def film(seed=102):
+def film(seed=102, n=(256, 64, 1)):
     th = math.radians(10.0)
-    return make_problem((256, 64, 1), (3.9e-9, 3.9e-9, 3e-9), 8.0e5, 1.3e-11, 0.02,
+    return make_problem(n, (3.9e-9, 3.9e-9, 3e-9), 8.0e5, 1.3e-11, 0.02,
                         m0=(math.cos(th), math.sin(th), 0.0), seed=seed,
                         h_uniform=(-25e-3 / MU0_SI, 4e-3 / MU0_SI, 0.0))
 

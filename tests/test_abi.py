@@ -74,6 +74,7 @@ def test_adjoint_and_server_reject_bad_arguments_on_the_host():
     P = ctypes.c_void_p
     assert L.nm_adjoint_step(None, None, 0.0, 1e-14, 1, 15, None, 1, None, None, None) == binding.NM_EINVAL
     assert L.nm_adjoint_workspace_bytes(None, 4) == 0
+    assert L.nm_adjoint_continuous(None, None, 0.0, 1e-14, 1, 15, None, None) == binding.NM_EINVAL
     out = ctypes.c_void_p()
     for bad in [(0, 0, 1, 4), (0, 2, 0, 4), (0, 2, 17, 4), (0, 2, 4, 0), (0, 2, 4, 65)]:
         d = binding.nm_server_desc(*bad)

@@ -6,12 +6,12 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import oracle
-from oracle.adjoint import region_mz2_loss, rk4_gradient, rk4_step_adjoint
+from oracle.adjoint import continuous_adjoint, region_mz2_loss, rk4_gradient, rk4_step_adjoint
 from oracle.field import ALL_TERMS
 from helpers import rel_l2, to_oracle
 from paper_2411_11725_amd import binding as B
 from paper_2411_11725_amd import synth
-from paper_2411_11725_amd.adjoint import LLGTrajectory
+from paper_2411_11725_amd.adjoint import LLGTrajectory, LLGTrajectoryContinuous
 
 pytestmark = pytest.mark.gpu
 
@@ -105,3 +105,87 @@ def test_autograd_gradient_against_fp64_finite_differences():
         fd = (Lfd(oracle.Material(**{**omat.__dict__, "h_cell": hp}))
               - Lfd(oracle.Material(**{**omat.__dict__, "h_cell": hm}))) / (2 * h)
         assert abs(g[j, c3, c2, c1] - fd) <= 1e-4 * max(abs(fd), 1e-3 * gmax), (j, c2, c1, g[j, c3, c2, c1], fd)
+
+
+@pytest.mark.parametrize("film", [False, True])
+def test_continuous_adjoint_matches_oracle(film):
+    """Backward RK4 on (m, a, u) from the same final state: the rebuilt m, the
+    co-state a and the field-map gradient u against the float64 oracle."""
+    p = synth.small_random((6, 5, 3) if not film else (20, 9, 1), (2e-9, 2.5e-9, 3e-9), seed=62)
+    if film:
+        p = synth.as_film(p)
+    om, omat, m0 = to_oracle(p)
+    rng = np.random.default_rng(4)
+    aT = rng.standard_normal(m0.shape)
+    dt, ns = 2e-14, 6
+    mT = m0
+    for k in range(ns):
+        mT = oracle.rk4_step(om, omat, mT, k * dt, dt)
+    mesh = B.mesh_from_problem(p)
+    try:
+        m = _dev(mT)
+        a = _dev(aT)
+        u = torch.zeros((3,) + om.cell_shape, device="cuda")
+        B.nm_adjoint_continuous(mesh, m, ns * dt, dt, ns, B.NM_T_ALL, a, grad_hcell=u)
+        torch.cuda.synchronize()
+        gm, ga, gu = (x.cpu().numpy().astype(np.float64) for x in (m, a, u))
+    finally:
+        B.nm_mesh_destroy(mesh)
+    om_, oa, ou = continuous_adjoint(om, omat, mT.astype(np.float32).astype(np.float64), ns * dt, dt, ns,
+                                     aT.astype(np.float32).astype(np.float64), ALL_TERMS)
+    assert np.abs(gm - om_).max() <= 1e-5
+    assert rel_l2(ga, oa) <= 1e-5
+    assert rel_l2(gu, ou) <= 1e-5
+
+
+def test_continuous_and_discrete_adjoints_agree():
+    """The two GPU gradients of L = c . m(T) on the magnonic strip: the same
+    quantity up to the O(dt^4) difference of the two discretisations."""
+    p, om, omat, m0, _ = _magnonic_small()
+    dt, ns = 5e-14, 20
+    c = np.random.default_rng(6).standard_normal(m0.shape)
+    mesh = B.mesh_from_problem(p)
+    try:
+        m = _dev(p["m0"])
+        clk = B.nm_clock(0.0, dt, 0, 0, 0, 0.0)
+        B.nm_llg_step(mesh, m, clk, B.NM_RK4, B.NM_T_ALL, t_end=ns * dt)
+        lam = _dev(c)
+        gd = torch.zeros((3,) + om.cell_shape, device="cuda")
+        work = torch.empty(B.nm_adjoint_workspace_bytes(mesh, ns) // 4 + 1, device="cuda")
+        B.nm_adjoint_step(mesh, _dev(p["m0"]), 0.0, dt, ns, B.NM_T_ALL, lam, grad_hcell=gd, work=work)
+        a = _dev(c)
+        gc = torch.zeros_like(gd)
+        B.nm_adjoint_continuous(mesh, m, ns * dt, dt, ns, B.NM_T_ALL, a, grad_hcell=gc)
+        torch.cuda.synchronize()
+        m_back = m.cpu().numpy().astype(np.float64)
+        r_u = rel_l2(gc.cpu().numpy(), gd.cpu().numpy())
+        r_a = rel_l2(a.cpu().numpy(), lam.cpu().numpy())
+    finally:
+        B.nm_mesh_destroy(mesh)
+    assert r_u <= 1e-4 and r_a <= 1e-4
+    assert np.abs(m_back - m0).max() <= 1e-4
+
+
+def test_continuous_autograd_matches_the_discrete_gradient():
+    """The multi-time objective of the magnonic strip through both autograd
+    functions: the continuous one (final state only, backward integration)
+    gives the discrete one's field-map and initial-state gradients to
+    O(dt^4)."""
+    p, om, omat, m0, region = _magnonic_small()
+    nsteps, dt = 24, 5e-14
+    mesh = B.mesh_from_problem(p)
+    grads = []
+    try:
+        reg = torch.as_tensor(region, device="cuda")
+        for fn, extra in ((LLGTrajectory, (8, 2)), (LLGTrajectoryContinuous, (2,))):
+            theta = torch.zeros((3,) + om.cell_shape, device="cuda", requires_grad=True)
+            m0t = _dev(p["m0"]).requires_grad_(True)
+            traj = fn.apply(theta, m0t, mesh, dt, nsteps, *extra, B.NM_T_ALL)
+            L = -(traj[:, 2][:, reg] ** 2).mean(dim=1).mean()
+            L.backward()
+            grads.append((theta.grad.cpu().numpy().astype(np.float64), m0t.grad.cpu().numpy().astype(np.float64)))
+    finally:
+        B.nm_mesh_destroy(mesh)
+    (gd, md), (gc, mc) = grads
+    assert rel_l2(gc, gd) <= 1e-4
+    assert rel_l2(mc, md) <= 1e-4

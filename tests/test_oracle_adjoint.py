@@ -5,8 +5,8 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.adjoint import (cell_gather, llg_vjp, region_mz2_loss, rhs_vjp, rk4_gradient,
-                            rk4_step_adjoint)
+from oracle.adjoint import (cell_gather, continuous_adjoint, llg_vjp, region_mz2_loss, rhs_vjp,
+                            rk4_gradient, rk4_step_adjoint)
 from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, EXCHANGE, ZEEMAN
 
 from helpers import to_oracle
@@ -122,3 +122,58 @@ def test_cell_gather_is_transpose_of_field_map():
     mat2 = oracle.Material(**{**mat.__dict__, "h_cell": theta, "h_uniform": np.zeros(3)})
     Hz = oracle.heff(mesh, mat2, np.zeros_like(v), ZEEMAN)
     assert abs(np.sum(Hz * M * v) - np.sum(theta * cell_gather(mesh, mat2, v))) <= 1e-12 * np.sum(np.abs(Hz * M * v))
+
+
+# ---------------------------------------------------------------- continuous
+def _linear_final_loss(mesh, seed=2):
+    c = np.random.default_rng(seed).standard_normal((3,) + mesh.node_shape)
+    return c, (lambda m: float(np.sum(c * m)))
+
+
+def test_continuous_adjoint_converges_to_the_discrete_adjoint_at_fourth_order():
+    """Both are RK4 discretisations of the same gradient: the continuous one
+    (Eq. adjoint_system, backwards) differs from the exact gradient of the
+    discrete map by O(dt^4), so halving dt divides the gap by ~16; the
+    rebuilt initial state converges to m0 at least as fast."""
+    mesh, mat, m0 = _problem(n=(5, 4, 2), seed=52)
+    c, _ = _linear_final_loss(mesh)
+    span = 4e-13
+    gaps, back = [], []
+    for dt in (4e-14, 2e-14):
+        ns = int(round(span / dt))
+        lam, th, mT = rk4_gradient(mesh, mat, m0, dt, ns, lambda k, m: np.zeros_like(m), ALL_TERMS,
+                                   lam_end=c)
+        mb, a0, u0 = continuous_adjoint(mesh, mat, mT, span, dt, ns, c, ALL_TERMS)
+        gaps.append(np.linalg.norm(u0 - th) / np.linalg.norm(th) + np.linalg.norm(a0 - lam) / np.linalg.norm(lam))
+        back.append(np.abs(mb - m0).max())
+    assert gaps[0] < 1e-5 and 10.0 < gaps[0] / gaps[1] < 24.0
+    # forward then backward RK4: at least fourth order (the leading terms of
+    # the two sweeps partly cancel, so the ratio can exceed 16)
+    assert back[0] < 1e-5 and back[0] / back[1] > 10.0
+
+
+def test_continuous_adjoint_gradient_against_finite_differences():
+    """u(0) is the gradient of L = c . m(T) with respect to the field map."""
+    mesh, mat, m0 = _problem(n=(4, 3, 2), seed=53)
+    c, loss = _linear_final_loss(mesh, seed=3)
+    dt, ns = 1e-14, 20
+
+    def L(mat_):
+        m = m0.copy()
+        for k in range(ns):
+            m = oracle.rk4_step(mesh, mat_, m, k * dt, dt)
+        return loss(m)
+
+    m = m0.copy()
+    for k in range(ns):
+        m = oracle.rk4_step(mesh, mat, m, k * dt, dt)
+    _, _, u = continuous_adjoint(mesh, mat, m, ns * dt, dt, ns, c, ALL_TERMS)
+    h = 0.7958
+    for (j, c3, c2, c1) in [(0, 0, 1, 2), (1, 1, 2, 0), (2, 1, 0, 3)]:
+        hp = mat.h_cell.copy()
+        hm = mat.h_cell.copy()
+        hp[j, c3, c2, c1] += h
+        hm[j, c3, c2, c1] -= h
+        fd = (L(oracle.Material(**{**mat.__dict__, "h_cell": hp}))
+              - L(oracle.Material(**{**mat.__dict__, "h_cell": hm}))) / (2 * h)
+        assert abs(u[j, c3, c2, c1] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(u).max()), (j, u[j, c3, c2, c1], fd)
