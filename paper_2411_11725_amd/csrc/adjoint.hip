@@ -120,6 +120,22 @@ k_cadj_node(const float *__restrict__ y, const float *__restrict__ H, const floa
     }
 }
 
+// Clock of the continuous adjoint in the step controller: C->t_end holds the
+// start of the current backward step, C->t the stage time the field kernels
+// read.  op 0: start at t0; op 1: stage time = start + c h; op 2: next step.
+__global__ void k_cadj_clock(Ctrl *C, int op, double t0, double ch, double h) {
+    if (threadIdx.x != 0) return;
+    if (op == 0) {
+        C->t_end = t0;
+        C->t = t0;
+        C->done = 0;
+    } else if (op == 1) {
+        C->t = C->t_end + ch;
+    } else {
+        C->t_end += h;
+    }
+}
+
 // Stage s of a backward RK4 step of size h on (m, a): g = -(vjp + M Hv / vs)
 // is da/dt (Hv is the linear field of the scaled v); the increments are accumulated with weight b, and either the next
 // stage state (m + ch f, a + ch g) is written or, after the last stage, the
@@ -420,7 +436,7 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
 }
 
 // The adjoint system of Sec. 4 integrated backwards: classical RK4 steps of
-// h = -dt on (m, a, u).  Per stage the field H(y) gives f and the node-local
+// h = -dt on (m, a, u), one recorded graph replayed per step.  Per stage the field H(y) gives f and the node-local
 // part of (df/dm)^T a; the transpose of the linear field is the forward
 // linear field of v = M^-1 (df/dH)^T a (as in the discrete adjoint), and the
 // field-map density v is accumulated with the weight -h/6 b_s of u's
@@ -451,35 +467,70 @@ extern "C" nm_status nm_adjoint_continuous(nm_mesh *m, float *mag, double t_end,
     // discrete adjoint's co-vectors carry dt
     const double vs = std::ldexp(1.0, (int)std::floor(std::log2(dt)));
     if (gather) hipLaunchKernelGGL(k_vzero, g3, dim3(256), 0, st, vsum, n3);
-    for (int j = 0; j < nsteps; ++j) {
-        const double t = t_end + j * h;
-        for (int s = 0; s < 4; ++s) {
+    hipLaunchKernelGGL(k_cadj_clock, dim3(1), dim3(64), 0, st, m->ctrl, 0, t_end, 0.0, 0.0);
+    // one backward step; its stage times come from the controller, so one
+    // recorded graph serves every step
+    auto enqueue = [&]() -> hipError_t {
+        hipStream_t s0 = m->stream;
+        hipError_t e = hipSuccess;
+        for (int s = 0; s < 4 && e == hipSuccess; ++s) {
             const float *yin = s == 0 ? mag : ym;
             const float *ain = s == 0 ? a : ya;
+            hipLaunchKernelGGL(k_cadj_clock, dim3(1), dim3(64), 0, s0, m->ctrl, 1, 0.0, c[s] * h, 0.0);
             // H at the stage state and time
-            if (terms & NM_T_DEMAG)
-                NM_HIP(demag_forward_conv_inverse(m, yin, (terms & NM_T_ZEEMAN) ? 2 : 1), who);
+            if (terms & NM_T_DEMAG) e = demag_forward_conv_inverse(m, yin, (terms & NM_T_ZEEMAN) ? 2 : 1);
             StageSpec sp{};
             sp.mode = kModeField;
             sp.in = yin;
             sp.out = H;
-            sp.t0 = t + c[s] * h;
-            NM_HIP(launch_stencil(m, terms, sp), who);
-            hipLaunchKernelGGL(k_cadj_node, gn, dim3(256), 0, st, yin, H, ain, m->inv_mass, m->alpha_n, m->gp_n,
+            sp.use_ctrl = true;
+            if (e == hipSuccess) e = launch_stencil(m, terms, sp);
+            hipLaunchKernelGGL(k_cadj_node, gn, dim3(256), 0, s0, yin, H, ain, m->inv_mass, m->alpha_n, m->gp_n,
                                f, vjp, v, gather ? vsum : nullptr, (float)(-h / 6.0 * b[s] / vs), (float)vs, nn);
             if (lin) {
-                if (lin & NM_T_DEMAG) NM_HIP(demag_forward_conv_inverse(m, v, 1), who);
+                if ((lin & NM_T_DEMAG) && e == hipSuccess) e = demag_forward_conv_inverse(m, v, 1);
                 StageSpec sl{};
                 sl.mode = kModeField;
                 sl.in = v;
                 sl.out = Hv;
-                NM_HIP(launch_stencil(m, lin, sl), who);
+                if (e == hipSuccess) e = launch_stencil(m, lin, sl);
             }
-            hipLaunchKernelGGL(k_cadj_combine, g3, dim3(256), 0, st, f, vjp, Hv, m->inv_mass, lin ? 1 : 0,
-                               (float)(1.0 / vs), mag, a,
-                               accm, acca, ym, ya, (float)b[s], (float)((s < 3 ? c[s + 1] : 0.0) * h), s == 0 ? 1 : 0,
-                               s == 3 ? 1 : 0, (float)(h / 6.0), nn);
+            hipLaunchKernelGGL(k_cadj_combine, g3, dim3(256), 0, s0, f, vjp, Hv, m->inv_mass, lin ? 1 : 0,
+                               (float)(1.0 / vs), mag, a, accm, acca, ym, ya, (float)b[s],
+                               (float)((s < 3 ? c[s + 1] : 0.0) * h), s == 0 ? 1 : 0, s == 3 ? 1 : 0,
+                               (float)(h / 6.0), nn);
         }
+        hipLaunchKernelGGL(k_cadj_clock, dim3(1), dim3(64), 0, s0, m->ctrl, 2, 0.0, 0.0, h);
+        return e == hipSuccess ? hipGetLastError() : e;
+    };
+    if (m->prof) {
+        for (int j = 0; j < nsteps; ++j) NM_HIP(enqueue(), who);   // per-kernel events: direct launches
+    } else {
+        const bool same = m->cadj_gexec && m->cadj_terms == terms && m->cadj_dt == dt &&
+                          m->cadj_gather == gather && m->cadj_m == mag && m->cadj_a == a;
+        if (!same) {
+            if (m->cadj_gexec) {
+                (void)hipStreamSynchronize(st);
+                (void)hipGraphExecDestroy(m->cadj_gexec);
+                m->cadj_gexec = nullptr;
+            }
+            m->stream = m->cap_stream;
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
+            hipError_t e2 = e == hipSuccess ? enqueue() : e;
+            if (e == hipSuccess) e = hipStreamEndCapture(m->cap_stream, &graph);
+            m->stream = st;
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&m->cadj_gexec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            NM_HIP(e, who);
+            m->cadj_terms = terms;
+            m->cadj_dt = dt;
+            m->cadj_gather = gather;
+            m->cadj_m = mag;
+            m->cadj_a = a;
+        }
+        for (int j = 0; j < nsteps; ++j) NM_HIP(hipGraphLaunch(m->cadj_gexec, st), who);
     }
     if (gather)
         hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,

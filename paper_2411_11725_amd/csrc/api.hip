@@ -165,11 +165,11 @@ static void drop_graph(nm_mesh *m, bool wait = true) {
 }
 
 static void drop_adj_graph(nm_mesh *m, bool wait = true) {
-    if (m->adj_gexec) {
-        if (wait) (void)hipStreamSynchronize(m->stream);
-        (void)hipGraphExecDestroy(m->adj_gexec);
-    }
+    if ((m->adj_gexec || m->cadj_gexec) && wait) (void)hipStreamSynchronize(m->stream);
+    if (m->adj_gexec) (void)hipGraphExecDestroy(m->adj_gexec);
+    if (m->cadj_gexec) (void)hipGraphExecDestroy(m->cadj_gexec);
     m->adj_gexec = nullptr;
+    m->cadj_gexec = nullptr;
 }
 
 // the mesh's stream work must be complete (nm_mesh_destroy waits for it,
@@ -569,9 +569,10 @@ static int tail_slot(int batch) {
 }
 
 int batch_for(double est, int batch) {
+    if (est >= (double)batch) return batch;
     int b = 1;
-    while (b < batch && (double)b < est) b *= 2;
-    return std::min(b, batch);
+    while (2 * b <= batch && (double)(2 * b) <= est) b *= 2;
+    return b;
 }
 
 int next_batch(const nm_mesh *m, int batch) {
@@ -674,13 +675,8 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         if (nsteps < 1) nsteps = 1;
         if (nsteps > max_steps) nsteps = max_steps;
         for (long k = 0; k < nsteps;) {
-            // the last replay takes the smallest power of two covering the rest
-            int b = batch;
-            if (nsteps - k < batch) {
-                b = 1;
-                while (b < nsteps - k) b *= 2;
-                b = std::min(b, batch);
-            }
+            // the last replays take powers of two that add up to the rest
+            const int b = batch_for((double)(nsteps - k), batch);
             NM_HIP(step_batch(m, mag, NM_RK4, terms, b), "nm_llg_step");
             k += b;
         }

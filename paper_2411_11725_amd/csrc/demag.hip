@@ -454,8 +454,14 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     __shared__ float2 sh[TT > 1 ? NCX * L * NPB : 1];
     __shared__ float2 tl[L];
     const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
-    const int col = blockIdx.x * NPB + b;
-    const bool valid = col < P2 * KP && col % KP < K1;
+    // columns in mirror order: ky rows 0, 1, P2-1, 2, P2-2, ..., P2/2 (rows ky
+    // and P2-ky read the same stored tensor entries), blocks in contiguous
+    // ranges per XCD, so a row's mirror finds the tensor in the same L2
+    const int pos = (int)xcd_block(blockIdx.x, gridDim.x) * NPB + b;
+    const int slot = pos / KP, kxp = pos - slot * KP;
+    const int kyp = slot == 0 ? 0 : slot >= P2 - 1 ? P2 / 2 : (slot & 1) ? (slot + 1) / 2 : P2 - (slot + 1) / 2;
+    const int col = kyp * KP + kxp;
+    const bool valid = pos < P2 * KP && kxp < K1;
     const int colc = valid ? col : 0;   // pad / past-the-end lanes read column 0
     const long long plane = (long long)P2 * KP;
     // inputs z = (j + T a) + L1 n2, nonzero only for n2 < L2 / 2; 32-bit byte

@@ -133,6 +133,12 @@ struct nm_mesh {
     bool adj_gather;
     double adj_dt;
     float *adj_work;
+    // recorded step of the continuous adjoint and its key
+    hipGraphExec_t cadj_gexec;
+    unsigned cadj_terms;
+    double cadj_dt;
+    bool cadj_gather;
+    const float *cadj_m, *cadj_a;
     int g_method;
     unsigned g_terms;
     float *g_mag;
@@ -198,11 +204,12 @@ hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t,
 hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
 hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat from the raw copies
-// attempts for the next replay of a DP45 integration: the smallest power of
-// two (at most batch) covering what the host mirror of the controller says
-// is left by step count and by time at the proposed step
+// attempts for the next replay of a DP45 integration: the full batch while
+// the host mirror of the controller says at least that many steps are left
+// (by step count and by time at the proposed step), else the largest power
+// of two not above what is left, so that no attempt of the replay is idle
 int next_batch(const nm_mesh *m, int batch);
-int batch_for(double est, int batch);   // smallest power of two >= est, within 1 .. batch
+int batch_for(double est, int batch);   // batch if est >= batch, else the largest power of two <= est (>= 1)
 void mesh_release(nm_mesh *m);             // free a mesh whose stream work has completed
 hipError_t launch_rk4_advance(nm_mesh *m);
 
