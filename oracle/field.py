@@ -18,14 +18,18 @@ Energies (J):
   anisotropy E_an = -sum_c Ku_c sum_ab M^e_ab (m_a.e_c)(m_b.e_c)
   Zeeman     E_z  = -mu0 sum_c Ms_c V/8 H_ext,c . sum_a m_{c+a}
   demag      E_d  = -(mu0/2) sum_c V Ms_c mbar_c . H_c
+  DMI        E_dmi = sum_c D_c int_c [m_z div m - (m . grad) m_z]
+             (interfacial antisymmetric exchange with the interface normal
+             along z, integrated exactly with the element matrices
+             G_k[a, b] = int phi_a d_k phi_b, k = x, y)
 """
 import numpy as np
 
 from .mesh import MU0
 from .newell import newell_octant
 
-EXCHANGE, DEMAG, ANISOTROPY, ZEEMAN = 1, 2, 4, 8
-ALL_TERMS = 15
+EXCHANGE, DEMAG, ANISOTROPY, ZEEMAN, DMI = 1, 2, 4, 8, 16
+ALL_TERMS = 31
 
 
 # ---------------------------------------------------------------------------
@@ -84,6 +88,24 @@ def _anisotropy_gradient(mesh, mat, m, g):
         for q in range(len(mesh.corners)):
             acc += Me[p, q] * proj[q]
         mesh.corner(g, a)[...] += -2.0 * mat.Ku * acc * e
+
+
+def _dmi_gradient(mesh, mat, m, g):
+    """dE/dm of E = sum_c D_c sum_ab [m_az G_x m_bx - m_ax G_x m_bz
+    + m_az G_y m_by - m_ay G_y m_bz] (G = G_k[a, b]), with
+    A_k = G_k - G_k^T:
+        dE/dm_a,x = -sum_b A_x[a, b] m_b,z,  dE/dm_a,y = -sum_b A_y[a, b] m_b,z,
+        dE/dm_a,z = sum_b (A_x[a, b] m_b,x + A_y[a, b] m_b,y)."""
+    G = mesh.element_dmi()
+    Ax, Ay = G[0] - G[0].T, G[1] - G[1].T
+    for p, a in enumerate(mesh.corners):
+        acc = np.zeros((3,) + mesh.cell_shape)
+        for q, b in enumerate(mesh.corners):
+            mb = mesh.corner(m, b)
+            acc[0] -= Ax[p, q] * mb[2]
+            acc[1] -= Ay[p, q] * mb[2]
+            acc[2] += Ax[p, q] * mb[0] + Ay[p, q] * mb[1]
+        mesh.corner(g, a)[...] += mat.D * acc
 
 
 def _cell_source_gradient(mesh, mat, Hc, g):
@@ -218,6 +240,8 @@ def gradient(mesh, mat, m, terms=ALL_TERMS, t=0.0, pad=None):
         _exchange_gradient(mesh, mat, m, g)
     if terms & ANISOTROPY and mat.Ku is not None:
         _anisotropy_gradient(mesh, mat, m, g)
+    if terms & DMI and mat.D is not None:
+        _dmi_gradient(mesh, mat, m, g)
     if terms & ZEEMAN:
         _cell_source_gradient(mesh, mat, external_cell_field(mesh, mat, t), g)
     if terms & DEMAG:
@@ -236,7 +260,7 @@ def energies(mesh, mat, m, terms=ALL_TERMS, t=0.0):
     """Energies in J as a dict: exchange, demag, anisotropy, zeeman, total."""
     m = np.asarray(m, dtype=np.float64)
     K, Me = mesh.element_matrices()
-    out = {"exchange": 0.0, "demag": 0.0, "anisotropy": 0.0, "zeeman": 0.0}
+    out = {"exchange": 0.0, "demag": 0.0, "anisotropy": 0.0, "zeeman": 0.0, "dmi": 0.0}
     if terms & EXCHANGE:
         e = 0.0
         for p, a in enumerate(mesh.corners):
@@ -259,5 +283,15 @@ def energies(mesh, mat, m, terms=ALL_TERMS, t=0.0):
         Hc = demag_cell_field(mesh, mat, m)
         mbar = cell_average(mesh, m)
         out["demag"] = -0.5 * MU0 * mesh.V * np.sum(mat.Ms * np.sum(mbar * Hc, axis=0))
-    out["total"] = out["exchange"] + out["demag"] + out["anisotropy"] + out["zeeman"]
+    if terms & DMI and mat.D is not None:
+        G = mesh.element_dmi()
+        e = 0.0
+        for p, a in enumerate(mesh.corners):
+            ma = mesh.corner(m, a)
+            for q, b in enumerate(mesh.corners):
+                mb = mesh.corner(m, b)
+                e += np.sum(mat.D * (G[0, p, q] * (ma[2] * mb[0] - ma[0] * mb[2])
+                                     + G[1, p, q] * (ma[2] * mb[1] - ma[1] * mb[2])))
+        out["dmi"] = e
+    out["total"] = out["exchange"] + out["demag"] + out["anisotropy"] + out["zeeman"] + out["dmi"]
     return out

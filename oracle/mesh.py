@@ -116,6 +116,57 @@ class Mesh:
                 M[p, q] = mm[0] * mm[1] * mm[2]
         return K, M
 
+    def element_dmi(self):
+        """G_k[a, b] = int_cell phi_a d(phi_b)/dx_k for k = x, y (the
+        antisymmetric-exchange element matrices).  Along k the 1D integral of
+        psi_a psi_b' is +-1/2 (the sign of psi_b'), the other axes give the 1D
+        mass factors; under the film basis the z factor is h3."""
+        h = self.h
+        nc = len(self.corners)
+        G = np.zeros((2, nc, nc))
+        for p, a in enumerate(self.corners):
+            for q, b in enumerate(self.corners):
+                for k in range(2):
+                    v = 0.5 if b[k] == 1 else -0.5
+                    for l in range(3):
+                        if l == k:
+                            continue
+                        if l == 2 and self.basis == "film":
+                            v *= h[2]
+                        else:
+                            v *= h[l] * (2.0 if a[l] == b[l] else 1.0) / 6.0
+                    G[k, p, q] = v
+        return G
+
+    def element_dmi_quadrature(self):
+        """The same G_k by 2-point Gauss quadrature of the reference functions."""
+        g = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
+        w = np.array([0.5, 0.5])
+        dims = 3 if self.basis == "3d" else 2
+
+        def psi(i, x):
+            return 1 - i + (2 * i * x - x)
+
+        def phi(i, x):
+            return np.prod([psi(i[k], x[k]) for k in range(dims)])
+
+        def dphi(i, x, k):
+            out = (2 * i[k] - 1) / self.h[k]
+            for l in range(dims):
+                if l != k:
+                    out *= psi(i[l], x[l])
+            return out
+        nc = len(self.corners)
+        G = np.zeros((2, nc, nc))
+        for q in product(range(2), repeat=3):
+            x = [g[q[0]], g[q[1]], g[q[2]]]
+            wt = w[q[0]] * w[q[1]] * w[q[2]] * self.V
+            for p, a in enumerate(self.corners):
+                for r, b in enumerate(self.corners):
+                    for k in range(2):
+                        G[k, p, r] += wt * phi(a, x) * dphi(b, x, k)
+        return G
+
     def element_matrices_quadrature(self):
         """Same matrices by explicit 2-point Gauss quadrature (as the paper's form
         compiler does, Sec. 5.1); used by the tests as an independent route."""
@@ -183,6 +234,7 @@ class Material:
     drive_amp: np.ndarray = field(default_factory=lambda: np.zeros(3))
     drive_freq: float = 0.0
     drive_phase: float = 0.0
+    D: Optional[np.ndarray] = None      # interfacial DMI constant per cell, J/m^2
 
     def as_f64(self):
         def c(a):
@@ -192,4 +244,4 @@ class Material:
                         h_cell=c(self.h_cell), h_uniform=c(self.h_uniform),
                         drive_mask=c(self.drive_mask), drive_amp=c(self.drive_amp),
                         drive_freq=float(self.drive_freq),
-                        drive_phase=float(self.drive_phase))
+                        drive_phase=float(self.drive_phase), D=c(self.D))

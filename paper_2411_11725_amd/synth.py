@@ -39,7 +39,7 @@ def _f32(a):
 def make_problem(n, h, Ms, A, alpha, gamma=2.211e5, m0="random", seed=0,
                  Ku=None, easy="random", h_uniform=(0.0, 0.0, 0.0),
                  h_cell=None, drive_mask=None, drive_amp=(0.0, 0.0, 0.0),
-                 drive_freq=0.0, drive_phase=0.0):
+                 drive_freq=0.0, drive_phase=0.0, D=None):
     """Return a dict of float32 arrays describing one problem.
 
     Cell arrays have shape (N3, N2, N1), cell vectors (3, N3, N2, N1) and the
@@ -83,6 +83,7 @@ def make_problem(n, h, Ms, A, alpha, gamma=2.211e5, m0="random", seed=0,
     out["drive_amp"] = np.asarray(drive_amp, dtype=np.float32)
     out["drive_freq"] = float(drive_freq)
     out["drive_phase"] = float(drive_phase)
+    out["D"] = None if D is None else cellv(D)
     return out
 
 
@@ -135,10 +136,11 @@ def as_film(p):
 
 
 def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
-                 hetero=True, ku_range=(0.0, 5e5)):
+                 hetero=True, ku_range=(0.0, 5e5), dmi=False):
     """Small heterogeneous problem used by the parity tests: every term on,
     per-cell Ms, A, alpha, Ku ~ U[ku_range] (a negative Ku makes the cell
-    easy-plane), easy axes and applied field."""
+    easy-plane), easy axes and applied field; with dmi, an interfacial DMI
+    constant D ~ U[-3e-3, 3e-3] J/m^2 per cell."""
     rng = np.random.default_rng(seed)
     n1, n2, n3 = n
     cells = (n3, n2, n1)
@@ -146,10 +148,11 @@ def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
     A = rng.uniform(5e-12, 2e-11, size=cells) if hetero else 1.3e-11
     alpha = rng.uniform(0.01, 0.5, size=cells) if hetero else 0.1
     hc = rng.uniform(-5e4, 5e4, size=(3,) + cells) if field else None
+    D = rng.uniform(-3e-3, 3e-3, size=cells) if dmi else None
     return make_problem(n, h, Ms, A, alpha, seed=seed + 1,
                         Ku=("uniform",) + tuple(ku_range) if anis else None,
                         easy="random", h_uniform=(1e4, -2e4, 3e4) if field else (0, 0, 0),
-                        h_cell=hc)
+                        h_cell=hc, D=D)
 
 
 def serving_requests(count, seed=104, rate=200.0, nmin=32, nmax=512, nzmax=8, h=3e-9):

@@ -13,7 +13,7 @@ def to_oracle(p):
         Ku=f(p["Ku"]), easy=f(p["easy"]), h_cell=f(p["h_cell"]),
         h_uniform=f(p["h_uniform"]), drive_mask=f(p["drive_mask"]),
         drive_amp=f(p["drive_amp"]), drive_freq=p["drive_freq"],
-        drive_phase=p["drive_phase"])
+        drive_phase=p["drive_phase"], D=f(p.get("D")))
     return mesh, mat, np.asarray(p["m0"], dtype=np.float64)
 
 

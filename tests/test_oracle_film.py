@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, EXCHANGE, ZEEMAN
+from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, DMI, EXCHANGE, ZEEMAN
 
 from helpers import rel_l2, to_oracle
 from paper_2411_11725_amd import synth
@@ -42,9 +42,9 @@ def test_film_element_matrices_match_gauss_quadrature():
     assert np.allclose(M.sum(axis=1), mesh.V / 4.0, atol=1e-14)
 
 
-@pytest.mark.parametrize("terms", [EXCHANGE, ANISOTROPY, ZEEMAN, DEMAG, ALL_TERMS])
+@pytest.mark.parametrize("terms", [EXCHANGE, ANISOTROPY, ZEEMAN, DEMAG, DMI, ALL_TERMS])
 def test_film_field_equals_3d_field_of_z_uniform_m(terms):
-    film, mesh3, mat, m = _film(ku_range=(-5e5, 5e5))
+    film, mesh3, mat, m = _film(ku_range=(-5e5, 5e5), dmi=True)
     m3 = np.concatenate([m, m], axis=1)          # both node layers of the cell layer
     H2 = oracle.heff(film, mat, m, terms, t=1e-11)
     H3 = oracle.heff(mesh3, mat, m3, terms, t=1e-11)
@@ -52,7 +52,7 @@ def test_film_field_equals_3d_field_of_z_uniform_m(terms):
     assert rel_l2(H2, H3[:, 1:2]) < 1e-12
     e2 = oracle.energies(film, mat, m, terms, t=1e-11)
     e3 = oracle.energies(mesh3, mat, m3, terms, t=1e-11)
-    for k in ("exchange", "demag", "anisotropy", "zeeman", "total"):
+    for k in ("exchange", "demag", "anisotropy", "zeeman", "dmi", "total"):
         assert abs(e2[k] - e3[k]) <= 1e-12 * max(abs(e3["total"]), abs(e3[k]), 1e-30)
 
 
