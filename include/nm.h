@@ -55,7 +55,9 @@ enum {
     NM_T_DEMAG = 2,        /* cuboid-cell FFT demagnetisation, Sec. 3.2 */
     NM_T_ANIS = 4,         /* uniaxial -int Ku (m.e)^2 */
     NM_T_ZEEMAN = 8,       /* -mu0 int Ms m.H_ext */
-    NM_T_ALL = 15
+    NM_T_DMI = 16,         /* interfacial antisymmetric exchange (interface
+                            * normal z): int D [m_z div m - (m.grad) m_z] */
+    NM_T_ALL = 31
 };
 
 /* Time integrators (Sec. 5.3). */
@@ -100,6 +102,7 @@ typedef struct {
     float drive_amp[3];       /* drive amplitude (A/m) */
     double drive_freq;        /* Hz */
     double drive_phase;       /* rad */
+    const float *D;           /* optional, J/m^2, interfacial DMI constant */
 } nm_material;
 
 /* Adaptive / fixed stepping parameters. */
@@ -174,8 +177,8 @@ nm_status nm_demag_cell_field(nm_mesh *mesh, const float *m, float *h_cell_out);
 nm_status nm_llg_rhs(nm_mesh *mesh, const float *m, float *dmdt, unsigned terms, double t);
 
 /* Energies in J: e[0] exchange, e[1] demag, e[2] anisotropy, e[3] Zeeman,
- * e[4] total (host array).  Synchronises the stream. */
-nm_status nm_energy(nm_mesh *mesh, const float *m, unsigned terms, double t, double e[5]);
+ * e[4] total, e[5] DMI (host array of 6).  Synchronises the stream. */
+nm_status nm_energy(nm_mesh *mesh, const float *m, unsigned terms, double t, double e[6]);
 
 /* Advance m (device, in place) from clk->t to t_end with at most max_steps
  * steps (RK4: steps of clk->dt, the last one shortened to land on t_end;

@@ -135,13 +135,13 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
 
 static size_t footprint(const Sizes &s) {
     size_t b = 0;
-    b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive
+    b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive, D
     b += sizeof(float) * s.nc * (4 + 4);                      // cellP, wstat
     b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
     b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
     b += sizeof(float) * 4 * s.nc;                              // demag cell field / source
     b += sizeof(float) * 3 * s.nn * 10;                         // y[2], acc, k[7]
-    b += sizeof(Ctrl) + sizeof(ErrPartial) * s.partials + sizeof(double) * (4 * s.eblocks + 4);
+    b += sizeof(Ctrl) + sizeof(ErrPartial) * s.partials + sizeof(double) * (5 * s.eblocks + 5);
     return b;
 }
 
@@ -180,7 +180,7 @@ static void free_mesh(nm_mesh *m) {
     drop_graph(m, false);
     drop_adj_graph(m, false);
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
-    void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->wc, m->inv_mass,
+    void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->Dc, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
                     m->ctrl, m->partials, m->ered, m->cellP, m->wstat};
     for (void *p : ptrs) dev_free(p, m->pool);
@@ -248,6 +248,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     m->has_anis = mat->Ku != nullptr;
     m->has_hcell = mat->h_cell != nullptr;
     m->has_drive = mat->drive_mask != nullptr;
+    m->has_dmi = mat->D != nullptr;
     for (int k = 0; k < 3; ++k) {
         m->h_uniform[k] = mat->h_uniform[k];
         m->drive_amp[k] = mat->drive_amp[k];
@@ -266,6 +267,12 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
         m->Kp[mask] = (float)(ss[0] * mm[1] * mm[2] + mm[0] * ss[1] * mm[2] + mm[0] * mm[1] * ss[2]);
         m->Mp[mask] = (float)(mm[0] * mm[1] * mm[2]);
     }
+    for (int i = 0; i < 4; ++i) {
+        const double my = d->h[1] * ((i & 1) ? 1.0 : 2.0) / 6.0, mx = d->h[0] * ((i & 1) ? 1.0 : 2.0) / 6.0;
+        const double mz = d->h[2] * ((i >> 1) ? 1.0 : 2.0) / 6.0;
+        m->gx[i] = (float)(my * mz);
+        m->gy[i] = (float)(mx * mz);
+    }
 
     m->pool = thread_pool();
     hipError_t e = hipGetDevice(&m->device);
@@ -281,6 +288,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->Ku, nc);
     if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->easy, 3 * nc);
     if (e == hipSuccess && m->has_drive) e = dalloc(m, &m->drive_mask, nc);
+    if (e == hipSuccess && m->has_dmi) e = dalloc(m, &m->Dc, nc);
     if (e == hipSuccess) e = dalloc(m, &m->inv_mass, nn);
     if (e == hipSuccess) e = dalloc(m, &m->alpha_n, nn);
     if (e == hipSuccess) e = dalloc(m, &m->gp_n, nn);
@@ -293,7 +301,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     for (int j = 0; j < 7 && e == hipSuccess; ++j) e = dalloc(m, &m->k[j], 3 * nn);
     if (e == hipSuccess) e = dalloc(m, &m->ctrl, 1);
     if (e == hipSuccess) e = dalloc(m, &m->partials, s.partials);
-    if (e == hipSuccess) e = dalloc(m, &m->ered, 4 * s.eblocks + 4);
+    if (e == hipSuccess) e = dalloc(m, &m->ered, 5 * s.eblocks + 5);
     if (e == hipSuccess) e = host_alloc((void **)&m->ctrl_host, sizeof(Ctrl), m->pool);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -313,6 +321,8 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
         e = hipMemcpyAsync(m->h_cell, mat->h_cell, sizeof(float) * 3 * nc, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && m->has_drive)
         e = hipMemcpyAsync(m->drive_mask, mat->drive_mask, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && m->has_dmi)
+        e = hipMemcpyAsync(m->Dc, mat->D, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
     // alpha is only needed here: stage it in acc (3 * nn >= nc floats)
     if (e == hipSuccess) e = hipMemcpyAsync(m->acc, mat->alpha, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) {
@@ -456,7 +466,7 @@ extern "C" nm_status nm_demag_cell_field(nm_mesh *m, const float *mag, float *ho
     return NM_OK;
 }
 
-extern "C" nm_status nm_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]) {
+extern "C" nm_status nm_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[6]) {
     NM_REQUIRE(m && mag && e, NM_EINVAL, "nm_energy: NULL argument");
     nm_status st = check_terms(m, terms, "nm_energy");
     if (st != NM_OK) return st;

@@ -89,13 +89,18 @@ struct nm_mesh {
 
     // owned material copies (cell arrays) and derived quantities
     float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;
+    float *Dc;               // interfacial DMI constant per cell (when given)
     float *wc;               // mu0 Ms_c V / 8: weight of a cell-constant field
     float4 *cellP;           // packed per cell: {2A with the sign of Ku, sqrt|Ku| e}
     float4 *wstat;           // per cell: mu0 Ms V/8 {h_uniform + h_cell, drive mask}
     float h_uniform[3], drive_amp[3];
     double drive_freq, drive_phase;
-    bool has_anis, has_hcell, has_drive;
+    bool has_anis, has_hcell, has_drive, has_dmi;
     float Kp[8], Mp[8];      // element matrices by axis-difference pattern
+    // DMI: the antisymmetric part of int phi_a d_k phi_b between nodes that
+    // differ by d is d_k gx[(d_y != 0) + 2 (d_z != 0)] (k = x) and
+    // d_y gy[(d_x != 0) + 2 (d_z != 0)] (k = y): products of 1D mass factors
+    float gx[4], gy[4];
 
     // nodal coefficients
     float *inv_mass, *alpha_n, *gp_n;
@@ -200,7 +205,7 @@ struct StageSpec {
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp);
 dim3 stencil_grid(const nm_mesh *m);   // blocks of the fused node kernel
-hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]);
+hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[6]);
 hipError_t launch_dp45_control(nm_mesh *m);
 hipError_t launch_dp45_finish(nm_mesh *m, float *mstate);
 hipError_t launch_cell_pack(nm_mesh *m);   // cellP, wstat from the raw copies

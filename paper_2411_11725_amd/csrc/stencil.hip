@@ -8,6 +8,8 @@
 //               the differences keep float32 accurate near uniform states)
 //   anisotropy  -2 Ku_c e_c sum_b M^e_ab (m_b . e_c)
 //   cell fields -mu0 Ms_c V/8 H_c  (Zeeman and the demag cell field)
+//   interfacial DMI (antisymmetric exchange, Sec. 2)
+//               D_c sum_b (-A_x m_b,z, -A_y m_b,z, A_x m_b,x + A_y m_b,y)_ab
 // with a = local index of n in cell c.  K^e and M^e of a cuboid cell depend
 // only on which axes a and b differ in, so 8 numbers each describe them.
 // Mass lumping (Eq. mass_lumping) then gives H_n = -g_n / M_n, and the LLG
@@ -29,6 +31,8 @@ struct StencilParams {
     int drive;                     // add the drive (the w component times sin and its amplitude)
     int W;                         // LDS window length per z offset: 256 + 2 NX + 2
     int faces;                     // K^e couples face neighbours (cells are not cubes)
+    const float *Dc;               // DMI constant per cell, or NULL
+    float gx[4], gy[4];            // DMI weights (see the node kernel)
     float rNX, rNY;                // 1 / NX, 1 / NY
     // energy kernel: raw cell data
     const float *wc, *A2, *Ku, *easy, *hcell, *dmask, *hd;
@@ -157,7 +161,7 @@ __device__ __forceinline__ int small_div(int a, int d, float rd) {
 #ifndef NM_NODE_WAVES
 #define NM_NODE_WAVES 3
 #endif
-template <int MODE, int STAGE, int NIT>
+template <int MODE, int STAGE, int NIT, bool DMI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
 k_node(StencilParams P, StageArgs S) {
     // consecutive node ranges on one XCD: the halo rows of a block were
@@ -254,6 +258,12 @@ k_node(StencilParams P, StageArgs S) {
             cw[q] = fx[i1] * fy[i2] * fz[i3];
             cp[q] = ldo(P.cellP, co[q]);
         }
+    }
+    // DMI constants weighted like the cells (0 outside the mesh)
+    float dq[8];
+    if constexpr (DMI) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) dq[q] = cw[q] * ldo(P.Dc, co[q] >> 2);
     }
     if (P.src) {
 #pragma unroll
@@ -401,6 +411,28 @@ k_node(StencilParams P, StageArgs S) {
                     }
                 }
         }
+        if constexpr (DMI) {
+            // A_k(a, b) = G_k(a, b) - G_k(b, a) = d_k times the 1D mass factors
+            // of the other two axes (gx, gy indexed by which of them differ):
+            // the same in every cell holding both nodes, so per neighbour d it
+            // is weighted by the sum of D over those cells
+#pragma unroll
+            for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    float ds = 0.f;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (shares(dx, q & 1) && shares(dy, (q >> 1) & 1) && shares(dz, q >> 2)) ds += dq[q];
+                    const float wx = dx == 0 ? 0.f : ds * (float)dx * P.gx[(dy != 0) + 2 * (dz != 0)];
+                    const float wy = dy == 0 ? 0.f : ds * (float)dy * P.gy[(dx != 0) + 2 * (dz != 0)];
+                    const float4 b = vb[(dy + 1) * 3 + dx + 1];
+                    g0 -= wx * b.z;
+                    g1 -= wy * b.z;
+                    g2 += wx * b.x + wy * b.y;
+                }
+        }
     }
     if (an) {
         const float m7 = P.Mp[7];
@@ -480,7 +512,7 @@ dim3 stencil_grid(const nm_mesh *m) { return dim3((unsigned)((m->n_nodes + 255) 
 __global__ void __launch_bounds__(256) k_energy_cells(StencilParams P, const float *__restrict__ m,
                                                       double t, double *__restrict__ part) {
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
-    float eex = 0.f, ean = 0.f, ez = 0.f, ed = 0.f;
+    float eex = 0.f, ean = 0.f, ez = 0.f, ed = 0.f, edm = 0.f;
     if (c < P.nc) {
         const int cx = (int)(c % P.N1);
         const long long r = c / P.N1;
@@ -536,25 +568,39 @@ __global__ void __launch_bounds__(256) k_energy_cells(StencilParams P, const flo
         }
         if ((P.terms & NM_T_DEMAG) && P.hd)
             ed = -0.5f * w * (ms0 * P.hd[c] + ms1 * P.hd[P.nc + c] + ms2 * P.hd[2 * P.nc + c]);
+        if ((P.terms & NM_T_DMI) && P.Dc) {
+            // D sum_ab [G_x(a,b) (m_az m_bx - m_ax m_bz) + G_y(a,b) (m_az m_by - m_ay m_bz)],
+            // G_k(a,b) = (b_k - 1/2) gk[...] (1D mass factors of the other axes)
+            float s = 0.f;
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b) {
+                    const int d = a ^ b;
+                    const float gxv = ((b & 1) ? 0.5f : -0.5f) * P.gx[((d >> 1) & 1) + 2 * ((d >> 2) & 1)];
+                    const float gyv = (((b >> 1) & 1) ? 0.5f : -0.5f) * P.gy[(d & 1) + 2 * ((d >> 2) & 1)];
+                    s += gxv * (v[a][2] * v[b][0] - v[a][0] * v[b][2]) + gyv * (v[a][2] * v[b][1] - v[a][1] * v[b][2]);
+                }
+            edm = P.Dc[c] * s;
+        }
     }
-    __shared__ double s[4][256];
+    __shared__ double s[5][256];
     const int t0 = threadIdx.x;
     s[0][t0] = eex;
     s[1][t0] = ed;
     s[2][t0] = ean;
     s[3][t0] = ez;
+    s[4][t0] = edm;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t0 < w)
-            for (int k = 0; k < 4; ++k) s[k][t0] += s[k][t0 + w];
+            for (int k = 0; k < 5; ++k) s[k][t0] += s[k][t0 + w];
         __syncthreads();
     }
-    if (t0 < 4) part[(long long)t0 * gridDim.x + blockIdx.x] = s[t0][0];
+    if (t0 < 5) part[(long long)t0 * gridDim.x + blockIdx.x] = s[t0][0];
 }
 
 __global__ void k_energy_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
     __shared__ double s[256];
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         double acc = 0.0;
         for (int i = threadIdx.x; i < nb; i += 256) acc += part[(long long)k * nb + i];
         s[threadIdx.x] = acc;
@@ -722,6 +768,11 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     P.drive = ((terms & NM_T_ZEEMAN) && m->has_drive) ? 1 : 0;
     P.W = 256 + 2 * m->NX + 2;
     P.faces = (m->Kp[1] != 0.f || m->Kp[2] != 0.f || m->Kp[4] != 0.f) ? 1 : 0;
+    P.Dc = ((terms & NM_T_DMI) && m->has_dmi) ? m->Dc : nullptr;
+    for (int i = 0; i < 4; ++i) {
+        P.gx[i] = m->gx[i];
+        P.gy[i] = m->gy[i];
+    }
     P.rNX = 1.f / (float)m->NX;
     P.rNY = 1.f / (float)m->NY;
     P.wc = m->wc;
@@ -751,15 +802,31 @@ static int window_items(int NX) {
     return need <= 5 ? 5 : need <= 7 ? 7 : need <= 10 ? 10 : need <= 13 ? 13 : 0;
 }
 
+// the DMI term is a separate instantiation, so meshes without it keep the
+// register budget of the other terms; with it the 13-item window would spill
+// at 3 waves per SIMD, and those rows read their neighbours directly
+template <int MODE, int STAGE, bool DMI>
+static void launch_node_t(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
+    switch (window_items(m->NX)) {
+        case 5: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 5, DMI>), grid, dim3(256), 0, P, S); break;
+        case 7: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 7, DMI>), grid, dim3(256), 0, P, S); break;
+        case 10: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 10, DMI>), grid, dim3(256), 0, P, S); break;
+        case 13:
+            if constexpr (!DMI) {
+                NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 13, false>), grid, dim3(256), 0, P, S);
+                break;
+            }
+            [[fallthrough]];
+        default: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 0, DMI>), grid, dim3(256), 0, P, S); break;
+    }
+}
+
 template <int MODE, int STAGE>
 static void launch_node(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
-    switch (window_items(m->NX)) {
-        case 5: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 5>), grid, dim3(256), 0, P, S); break;
-        case 7: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 7>), grid, dim3(256), 0, P, S); break;
-        case 10: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 10>), grid, dim3(256), 0, P, S); break;
-        case 13: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 13>), grid, dim3(256), 0, P, S); break;
-        default: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 0>), grid, dim3(256), 0, P, S); break;
-    }
+    if (P.Dc)
+        launch_node_t<MODE, STAGE, true>(m, grid, P, S);
+    else
+        launch_node_t<MODE, STAGE, false>(m, grid, P, S);
 }
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
@@ -811,22 +878,23 @@ hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
     return hipGetLastError();
 }
 
-hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[5]) {
+hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[6]) {
     StencilParams P = make_params(m, terms);
     const unsigned grid = (unsigned)((m->n_cells + 255) / 256);
     if ((int)grid > m->n_eblocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_energy_cells, dim3(grid), dim3(256), 0, m->stream, P, mag, t, m->ered);
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(256), 0, m->stream, m->ered, (int)grid,
-                       m->ered + 4LL * m->n_eblocks);
+                       m->ered + 5LL * m->n_eblocks);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    double host[4];
-    err = hipMemcpyAsync(host, m->ered + 4LL * m->n_eblocks, sizeof(host), hipMemcpyDeviceToHost,
+    double host[5];
+    err = hipMemcpyAsync(host, m->ered + 5LL * m->n_eblocks, sizeof(host), hipMemcpyDeviceToHost,
                          m->stream);
     if (err == hipSuccess) err = hipStreamSynchronize(m->stream);
     if (err != hipSuccess) return err;
     for (int k = 0; k < 4; ++k) e[k] = host[k];
-    e[4] = host[0] + host[1] + host[2] + host[3];
+    e[5] = host[4];
+    e[4] = host[0] + host[1] + host[2] + host[3] + host[4];
     return hipSuccess;
 }
 

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from oracle.adjoint import (cell_gather, continuous_adjoint, llg_vjp, region_mz2_loss, rhs_vjp,
                             rk4_gradient, rk4_step_adjoint)
-from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, EXCHANGE, ZEEMAN
+from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, DMI, EXCHANGE, ZEEMAN
 
 from helpers import to_oracle
 from paper_2411_11725_amd import synth
@@ -18,8 +18,8 @@ def _llg(m, H, alpha_n, gp):
     return -gp * mxh - alpha_n * gp * np.cross(m, mxh, axis=0)
 
 
-def _problem(n=(4, 3, 2), seed=51):
-    p = synth.small_random(n, (2e-9, 2.5e-9, 3e-9), seed=seed)
+def _problem(n=(4, 3, 2), seed=51, dmi=False):
+    p = synth.small_random(n, (2e-9, 2.5e-9, 3e-9), seed=seed, dmi=dmi)
     return to_oracle(p)
 
 
@@ -41,22 +41,25 @@ def test_llg_vjp_against_finite_differences():
     assert abs(np.sum(jh * w) - np.sum(dH * u)) <= 1e-10 * abs(np.sum(dH * u))
 
 
-def test_linear_field_operator_is_self_adjoint_in_the_mass_metric():
-    """M H_lin is the negative Hessian of the quadratic energies: symmetric."""
-    mesh, mat, _ = _problem()
+@pytest.mark.parametrize("dmi", [False, True])
+def test_linear_field_operator_is_self_adjoint_in_the_mass_metric(dmi):
+    """M H_lin is the negative Hessian of the quadratic energies: symmetric
+    (the DMI element matrices are not, but their energy's Hessian is)."""
+    mesh, mat, _ = _problem(dmi=dmi)
     M = oracle.lumped_mass(mesh, mat)
     rng = np.random.default_rng(2)
     a = rng.standard_normal((3,) + mesh.node_shape)
     b = rng.standard_normal((3,) + mesh.node_shape)
-    lin = EXCHANGE | ANISOTROPY | DEMAG
+    lin = EXCHANGE | ANISOTROPY | DEMAG | DMI
     lhs = np.sum(M * oracle.heff(mesh, mat, a, lin) * b)
     rhs = np.sum(a * M * oracle.heff(mesh, mat, b, lin))
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
-@pytest.mark.parametrize("terms", [ALL_TERMS, EXCHANGE | DEMAG])
-def test_rhs_vjp_dot_product(terms):
-    mesh, mat, m = _problem()
+@pytest.mark.parametrize("terms,dmi", [(ALL_TERMS, False), (EXCHANGE | DEMAG, False), (ALL_TERMS, True),
+                                      (DMI, True)])
+def test_rhs_vjp_dot_product(terms, dmi):
+    mesh, mat, m = _problem(dmi=dmi)
     rng = np.random.default_rng(3)
     w = rng.standard_normal(m.shape)
     v = rng.standard_normal(m.shape)
