@@ -42,6 +42,12 @@ WORKLOADS = {
     # longer fits the 256 MB Infinity Cache
     "block_large": dict(tag="block_256x256x64", desc="3D block 256x256x64 cells (2 nm), alpha=1 relaxation, per-cell Ku, DP45 rtol 1e-5",
                         make="block_large", terms=("exchange", "demag", "anisotropy"), dt0=1e-14),
+    # the block with interfacial DMI (D = 3 mJ/m^2 in every cell): the node
+    # kernel's DMI instantiation on the same mesh
+    "block_dmi": dict(tag="block_128x128x32_dmi",
+                      desc="3D block 128x128x32 cells (2 nm), alpha=1 relaxation, per-cell Ku, interfacial DMI "
+                           "D=3 mJ/m^2, DP45 rtol 1e-5",
+                      make="block_dmi", terms=("exchange", "demag", "anisotropy", "dmi"), dt0=1e-14),
     # the same film under the thin-film basis (one node layer, Sec. 3.3)
     "film_basis": dict(tag="film_256x64x1_filmbasis",
                        desc="thin film 256x64x1 cells (3.9x3.9x3 nm), thin-film basis (one node layer), "
@@ -75,6 +81,8 @@ DP45_READS = 19.0 / 6.0
 def make_workload(synth, W):
     if W["make"] == "block_large":
         return synth.block(n=(256, 256, 64))
+    if W["make"] == "block_dmi":
+        return synth.block(D=3e-3)
     if W["make"] == "film_basis":
         return synth.as_film(synth.film())
     if W["make"] == "film_large":
@@ -84,9 +92,10 @@ def make_workload(synth, W):
     return getattr(synth, W["make"])()
 
 
-def byte_model(n, pad, nn, zeeman, stage_writes=DP45_WRITES, stage_reads=DP45_READS):
+def byte_model(n, pad, nn, zeeman, stage_writes=DP45_WRITES, stage_reads=DP45_READS, dmi=False):
     """Algorithmic bytes per launch of each kernel slot (inputs + outputs once).
-    zeeman: the static applied field is part of the cell-field source."""
+    zeeman: the static applied field is part of the cell-field source; dmi:
+    the node kernel also reads D per cell."""
     n1, n2, n3 = n
     p1, p2, p3 = pad
     k1 = p1 // 2 + 1
@@ -108,7 +117,7 @@ def byte_model(n, pad, nn, zeeman, stage_writes=DP45_WRITES, stage_reads=DP45_RE
     # per cell: packed {2A, u} and the float4 source; per node: stage input,
     # state, coefficients (1/M, gamma', alpha), the stage outputs written,
     # earlier k_j read
-    cell = 16 * nc + 16 * nc
+    cell = 16 * nc + 16 * nc + (4 * nc if dmi else 0)
     out["stencil"] = cell + 12 * nn * (1 + 1 + 1 + stage_writes + stage_reads)
     return out
 
@@ -144,7 +153,7 @@ def cpu_baseline(p, terms_mask, evals=4):
                           Ku=f(p["Ku"]), easy=f(p["easy"]), h_cell=f(p["h_cell"]),
                           h_uniform=f(p["h_uniform"]), drive_mask=f(p["drive_mask"]),
                           drive_amp=f(p["drive_amp"]), drive_freq=p["drive_freq"],
-                          drive_phase=p["drive_phase"])
+                          drive_phase=p["drive_phase"], D=f(p.get("D")))
     m = f(p["m0"])
     t0 = time.perf_counter()
     demag_cell_field(mesh, mat, m)            # tensor and its spectrum: set-up, not timed
@@ -338,7 +347,7 @@ def main():
     W = WORKLOADS[args.workload]
     p = make_workload(synth, W)
     tmask = {"exchange": B.NM_T_EXCHANGE, "demag": B.NM_T_DEMAG, "anisotropy": B.NM_T_ANIS,
-             "zeeman": B.NM_T_ZEEMAN}
+             "zeeman": B.NM_T_ZEEMAN, "dmi": B.NM_T_DMI}
     terms = sum(tmask[t] for t in W["terms"])
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -370,7 +379,7 @@ def main():
     prof = B.nm_profile_read(mesh)
     B.nm_profile_enable(mesh, False)
 
-    bm = byte_model(p["n"], pad, nn, "zeeman" in W["terms"])
+    bm = byte_model(p["n"], pad, nn, "zeeman" in W["terms"], dmi="dmi" in W["terms"])
     kernels = {}
     for slot, (ms, cnt) in prof.items():
         if cnt == 0 or slot not in bm:

@@ -18,6 +18,10 @@ Workloads (every value in SI; mT fields are converted with H = B / mu0):
                   alpha 1e-3 ramped linearly to 0.5 over the outer 16 cells of
                   every in-plane edge, per-cell field map (init 0), 1 mT drive
                   along +y at 10 GHz on the cells 16 <= x < 20
+  two_phase_chain a chain of cells along x, 60 nm of a soft phase then 30 nm
+                  of a hard phase (A 1e-11, K 1e6, Ms 1e6; the soft phase
+                  differs in the named ones of A 2.5e-12, K 1e5, Ms 1.5e6),
+                  easy axis z, alpha 1, a wall in the soft phase
 """
 import math
 
@@ -99,9 +103,9 @@ def film(seed=102, n=(256, 64, 1)):
                         h_uniform=(-25e-3 / MU0_SI, 4e-3 / MU0_SI, 0.0))
 
 
-def block(n=(128, 128, 32), seed=103):
+def block(n=(128, 128, 32), seed=103, D=None):
     return make_problem(n, (2e-9, 2e-9, 2e-9), 1.0e6, 1.5e-11, 1.0, seed=seed,
-                        Ku=("uniform", 0.0, 5e5), easy="random")
+                        Ku=("uniform", 0.0, 5e5), easy="random", D=D)
 
 
 def magnonic(n=(256, 128, 1), seed=105):
@@ -176,3 +180,45 @@ def serving_requests(count, seed=104, rate=200.0, nmin=32, nmax=512, nzmax=8, h=
                          seed=int(rng.integers(1 << 31)))
         out.append((t, p))
     return out
+
+
+# two-phase depinning: phase 2 (hard) is the same in every case, phase 1
+# (soft) takes the soft value of each parameter the case names
+DEPIN_HARD = dict(A=1.0e-11, K=1.0e6, Ms=1.0e6)
+DEPIN_SOFT = dict(A=2.5e-12, K=1.0e5, Ms=1.5e6)
+DEPIN_CASES = ("A/K/Ms", "A/K", "A/Ms", "A", "K/Ms", "K")
+
+
+def depinning_phases(case):
+    """((A1, K1, Ms1), (A2, K2, Ms2)) of a two-phase case such as "A/K"."""
+    names = case.split("/")
+    if case not in DEPIN_CASES:
+        raise ValueError("unknown two-phase case %r" % case)
+    p1 = tuple(DEPIN_SOFT[k] if k in names else DEPIN_HARD[k] for k in ("A", "K", "Ms"))
+    p2 = tuple(DEPIN_HARD[k] for k in ("A", "K", "Ms"))
+    return p1, p2
+
+
+def two_phase_chain(case, hx=1e-9, hyz=4e-9, soft_len=60e-9, hard_len=30e-9):
+    """N1 x 1 x 1 cells of hx x hyz x hyz along x: the soft phase, then the
+    hard phase; easy axis +z in both, alpha 1, no applied field.  m0 is a
+    wall in the plane x = 0 (m = (0, sin theta, cos theta)) from theta = pi
+    at x = 0 to theta = 0, of width sqrt(A1/K1), centred two widths before
+    the interface.  Extra key "n_soft": cells of the soft phase."""
+    (A1, K1, M1), (A2, K2, M2) = depinning_phases(case)
+    n1 = int(round(soft_len / hx))
+    n2 = int(round(hard_len / hx))
+    soft = np.arange(n1 + n2) < n1
+    cells = (1, 1, n1 + n2)
+    sel = lambda a, b: np.broadcast_to(np.where(soft, a, b), cells)
+    w = math.sqrt(A1 / K1)
+    x = np.arange(n1 + n2 + 1) * hx
+    theta = 2.0 * np.arctan(np.exp(-(x - (n1 * hx - 2.0 * w)) / w))
+    m = np.zeros((3, 2, 2, n1 + n2 + 1))
+    m[1] = np.sin(theta)
+    m[2] = np.cos(theta)
+    p = make_problem((n1 + n2, 1, 1), (hx, hyz, hyz), sel(M1, M2), sel(A1, A2), 1.0, m0=(0.0, 0.0, 1.0),
+                     Ku=sel(K1, K2), easy=(0.0, 0.0, 1.0))
+    p["m0"] = _f32(m)
+    p["n_soft"] = n1
+    return p

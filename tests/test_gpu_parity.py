@@ -327,11 +327,11 @@ def test_dp45_film_replay_and_independent_parity():
     assert np.abs(mean(g) - mean(indep)).max() <= 1e-4
 
 
-@pytest.mark.parametrize("name", ["film", "block"])
+@pytest.mark.parametrize("name", ["film", "block", "block_dmi"])
 def test_full_size_workload_field(name):
-    """Every node of the full-size workloads (256x64x1 film, 128x128x32 block)
-    in the launch configuration the benchmark uses."""
-    p = getattr(synth, name)()
+    """Every node of the full-size workloads (256x64x1 film, 128x128x32 block,
+    the block with DMI) in the launch configuration the benchmark uses."""
+    p = synth.block(D=3e-3) if name == "block_dmi" else getattr(synth, name)()
     terms = ALL_TERMS
     g = _field(p, terms)
     om, omat, om0 = to_oracle(p)
