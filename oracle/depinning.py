@@ -5,8 +5,8 @@ TEST INFRASTRUCTURE, NOT PRODUCT CODE.
 The second validation case of the paper (Sec. "Validation", Tab. sp_dw)
 pushes a domain wall from a soft phase into a hard phase and reports the
 field at which it leaves the interface, for walls where A, K and Ms jump
-across the boundary.  The system here is a chain of cells along x, soft
-phase then hard phase, uniaxial anisotropy along z in both, a uniform field
+across the boundary.  The system here is a chain of cells along x (m
+uniform across it), soft phase then hard phase, uniaxial anisotropy along z in both, a uniform field
 -H z, and exchange + anisotropy + Zeeman (no demag, as in the one-dimensional
 model the closed form describes).  Two routes to the depinning field:
 

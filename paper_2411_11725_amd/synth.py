@@ -18,7 +18,7 @@ Workloads (every value in SI; mT fields are converted with H = B / mu0):
                   alpha 1e-3 ramped linearly to 0.5 over the outer 16 cells of
                   every in-plane edge, per-cell field map (init 0), 1 mT drive
                   along +y at 10 GHz on the cells 16 <= x < 20
-  two_phase_chain a chain of cells along x, 60 nm of a soft phase then 30 nm
+  two_phase_chain a chain of cells along x (2 across), 60 nm of a soft phase then 30 nm
                   of a hard phase (A 1e-11, K 1e6, Ms 1e6; the soft phase
                   differs in the named ones of A 2.5e-12, K 1e5, Ms 1.5e6),
                   easy axis z, alpha 1, a wall in the soft phase
@@ -199,25 +199,30 @@ def depinning_phases(case):
     return p1, p2
 
 
-def two_phase_chain(case, hx=1e-9, hyz=4e-9, soft_len=60e-9, hard_len=30e-9):
-    """N1 x 1 x 1 cells of hx x hyz x hyz along x: the soft phase, then the
-    hard phase; easy axis +z in both, alpha 1, no applied field.  m0 is a
+def two_phase_chain(case, hx=1e-9, hyz=None, soft_len=60e-9, hard_len=30e-9):
+    """N1 x 2 x 1 cells of hx x hyz x hyz along x (two across, the fewest
+    the library takes; hyz defaults to hx): the soft phase, then the hard
+    phase; easy axis +z in both, alpha 1, no applied field.  With cells much
+    longer across than along the chain, a narrow wall lowers its energy by a
+    checkerboard of its in-plane part across the section (a spurious mode of
+    the under-resolved section), so the chains use cubic cells.  m0 is a
     wall in the plane x = 0 (m = (0, sin theta, cos theta)) from theta = pi
     at x = 0 to theta = 0, of width sqrt(A1/K1), centred two widths before
     the interface.  Extra key "n_soft": cells of the soft phase."""
     (A1, K1, M1), (A2, K2, M2) = depinning_phases(case)
+    hyz = hx if hyz is None else hyz
     n1 = int(round(soft_len / hx))
     n2 = int(round(hard_len / hx))
     soft = np.arange(n1 + n2) < n1
-    cells = (1, 1, n1 + n2)
+    cells = (1, 2, n1 + n2)
     sel = lambda a, b: np.broadcast_to(np.where(soft, a, b), cells)
     w = math.sqrt(A1 / K1)
     x = np.arange(n1 + n2 + 1) * hx
     theta = 2.0 * np.arctan(np.exp(-(x - (n1 * hx - 2.0 * w)) / w))
-    m = np.zeros((3, 2, 2, n1 + n2 + 1))
+    m = np.zeros((3, 2, 3, n1 + n2 + 1))
     m[1] = np.sin(theta)
     m[2] = np.cos(theta)
-    p = make_problem((n1 + n2, 1, 1), (hx, hyz, hyz), sel(M1, M2), sel(A1, A2), 1.0, m0=(0.0, 0.0, 1.0),
+    p = make_problem((n1 + n2, 2, 1), (hx, hyz, hyz), sel(M1, M2), sel(A1, A2), 1.0, m0=(0.0, 0.0, 1.0),
                      Ku=sel(K1, K2), easy=(0.0, 0.0, 1.0))
     p["m0"] = _f32(m)
     p["n_soft"] = n1

@@ -21,7 +21,7 @@ SPACINGS = (1e-9, 0.5e-9)
 
 def main():
     lines = ["# case hx_m closed_form_T oracle_lo_T oracle_hi_T  (mu0 H_p; chain of synth.two_phase_chain,",
-             "# 60 nm soft + 30 nm hard, cross-section 4 nm; written by tests/golden/make_depinning.py)"]
+             "# 60 nm soft + 30 nm hard, cubic cells; written by tests/golden/make_depinning.py)"]
     for hx in SPACINGS:
         for case in synth.DEPIN_CASES:
             p = synth.two_phase_chain(case, hx=hx)

@@ -6,7 +6,9 @@ energy written here from scratch (finite differences on a 0.05 nm grid,
 scipy's L-BFGS), including the interface angle of the pinned wall; the
 oracle's discrete threshold against the closed form as the cells shrink
 (second-order convergence, and the K-only case, whose threshold does not
-depend on the cell size); the stored fixture against a fresh oracle run."""
+depend on the cell size); the stored fixture against a fresh oracle run;
+and the restriction to states uniform across the chain's section against the
+unrestricted LLG dynamics."""
 import os
 
 import numpy as np
@@ -112,3 +114,25 @@ def test_fixture_matches_a_fresh_oracle_run():
     b, bc2 = _discrete("K/Ms", 1e-9)
     assert bc == pytest.approx(bc2, rel=1e-6)
     assert lo <= b <= hi
+
+
+@pytest.mark.parametrize("hyz,grows", [(1e-9, False), (4e-9, True)])
+def test_uniform_section_is_stable_only_for_cubic_cells(hyz, grows):
+    """The discrete threshold minimises over states uniform across the chain's
+    section.  With cubic cells a perturbation of the pinned wall decays under
+    the LLG dynamics (so that restriction holds); with cells four times
+    longer across, a checkerboard of the in-plane part across the section
+    lowers the energy of the narrow wall and grows."""
+    import dataclasses
+
+    import oracle
+    p = synth.two_phase_chain("A/Ms", hx=1e-9, hyz=hyz, soft_len=20e-9, hard_len=10e-9)
+    mesh, mat, m0 = to_oracle(p)
+    matb = dataclasses.replace(mat, h_uniform=np.array([0.0, 0.0, -0.29 / oracle.MU0]))
+    rng = np.random.default_rng(0)
+    m = m0 + 1e-3 * rng.standard_normal(m0.shape)
+    m /= np.linalg.norm(m, axis=0)
+    for k in range(1500):
+        m = oracle.rk4_step(mesh, matb, m, k * 1e-13, 1e-13, dp.TERMS)
+    spread = np.abs(m - m[:, :1, :1]).max()
+    assert (spread > 0.1) if grows else (spread < 1e-5)
