@@ -227,3 +227,44 @@ def two_phase_chain(case, hx=1e-9, hyz=None, soft_len=60e-9, hard_len=30e-9):
     p["m0"] = _f32(m)
     p["n_soft"] = n1
     return p
+
+
+def embed_in_vacuum(p, n_big, offset, seed=109):
+    """The problem p placed at cell offset (o1, o2, o3) inside a mesh of n_big
+    cells whose other cells are vacuum (Ms = 0, A = 0, Ku = 0, no field,
+    alpha 0.1, easy axis z, D = 0).  Nodes touching the core keep p's m0;
+    the rest get random unit vectors (seed), which the method must ignore."""
+    n1, n2, n3 = p["n"]
+    o1, o2, o3 = offset
+    N1, N2, N3 = n_big
+    if o1 + n1 > N1 or o2 + n2 > N2 or o3 + n3 > N3 or min(offset) < 0:
+        raise ValueError("the core does not fit")
+    cs = (slice(o3, o3 + n3), slice(o2, o2 + n2), slice(o1, o1 + n1))
+    ns = (slice(o3, o3 + n3 + 1), slice(o2, o2 + n2 + 1), slice(o1, o1 + n1 + 1))
+    big = (N3, N2, N1)
+
+    def cell(a, fill):
+        if a is None:
+            return None
+        a = np.asarray(a, dtype=np.float64)
+        lead = a.shape[:-3]
+        out = np.broadcast_to(np.asarray(fill, dtype=np.float64).reshape(lead + (1, 1, 1)) if lead else fill,
+                              lead + big).copy()
+        out[(Ellipsis,) + cs] = a
+        return _f32(out)
+
+    q = dict(p)
+    q["n"] = tuple(n_big)
+    q["Ms"] = cell(p["Ms"], 0.0)
+    q["A"] = cell(p["A"], 0.0)
+    q["alpha"] = cell(p["alpha"], 0.1)
+    q["Ku"] = cell(p["Ku"], 0.0)
+    q["easy"] = cell(p["easy"], (0.0, 0.0, 1.0))
+    q["h_cell"] = cell(p["h_cell"], (0.0, 0.0, 0.0))
+    q["drive_mask"] = cell(p["drive_mask"], 0.0)
+    q["D"] = cell(p.get("D"), 0.0)
+    rng = np.random.default_rng(seed)
+    m = random_unit_vectors((N3 + 1) * (N2 + 1) * (N1 + 1), rng).reshape(3, N3 + 1, N2 + 1, N1 + 1)
+    m[(slice(None),) + ns] = p["m0"]
+    q["m0"] = _f32(m)
+    return q
