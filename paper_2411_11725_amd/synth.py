@@ -268,3 +268,19 @@ def embed_in_vacuum(p, n_big, offset, seed=109):
     m[(slice(None),) + ns] = p["m0"]
     q["m0"] = _f32(m)
     return q
+
+
+def wall_chain(hx=0.5e-9, length=60e-9, A=1e-11, K=1e6, Ms=1e6):
+    """A uniform chain of N1 x 2 x 1 cubic cells along x (easy axis +z,
+    alpha 1) holding a wall in the plane x = 0 at its middle: m = (0, sin,
+    cos) of theta = 2 atan(exp(-(x - L/2) / sqrt(A / K)))."""
+    n1 = int(round(length / hx))
+    w = math.sqrt(A / K)
+    x = np.arange(n1 + 1) * hx
+    theta = 2.0 * np.arctan(np.exp(-(x - 0.5 * n1 * hx) / w))
+    m = np.zeros((3, 2, 3, n1 + 1))
+    m[1] = np.sin(theta)
+    m[2] = np.cos(theta)
+    p = make_problem((n1, 2, 1), (hx, hx, hx), Ms, A, 1.0, m0=(0.0, 0.0, 1.0), Ku=K, easy=(0.0, 0.0, 1.0))
+    p["m0"] = _f32(m)
+    return p
