@@ -1,4 +1,4 @@
-"""Glue between the seeded problems and the oracle (tests only)."""
+"""Glue between the seeded problems and the oracle, and closed forms the tests share (tests only)."""
 import numpy as np
 
 import oracle
@@ -21,3 +21,20 @@ def rel_l2(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def aharoni_factor(a, b, c):
+    """Demagnetising factor along c of a uniformly magnetised rectangular
+    prism of edges 2a x 2b x 2c (A. Aharoni, J. Appl. Phys. 83, 3432 (1998),
+    the closed form of the body-averaged field)."""
+    r = np.sqrt(a * a + b * b + c * c)
+    ab, bc, ac = np.sqrt(a * a + b * b), np.sqrt(b * b + c * c), np.sqrt(a * a + c * c)
+    t = ((b * b - c * c) / (2 * b * c) * np.log((r - a) / (r + a))
+         + (a * a - c * c) / (2 * a * c) * np.log((r - b) / (r + b))
+         + b / (2 * c) * np.log((ab + a) / (ab - a)) + a / (2 * c) * np.log((ab + b) / (ab - b))
+         + c / (2 * a) * np.log((bc - b) / (bc + b)) + c / (2 * b) * np.log((ac - a) / (ac + a))
+         + 2 * np.arctan(a * b / (c * r)) + (a ** 3 + b ** 3 - 2 * c ** 3) / (3 * a * b * c)
+         + (a * a + b * b - 2 * c * c) / (3 * a * b * c) * r + c / (a * b) * (ac + bc)
+         - (ab ** 3 + bc ** 3 + ac ** 3) / (3 * a * b * c))
+    return t / np.pi
+

@@ -5,7 +5,7 @@ import pytest
 import oracle
 from oracle.newell import GL_BANDS, NEWELL_RADIUS, newell_far, newell_near
 
-from helpers import rel_l2, to_oracle
+from helpers import aharoni_factor, rel_l2, to_oracle
 from paper_2411_11725_amd import synth
 
 
@@ -154,3 +154,24 @@ def test_fft_tensor_spectrum_is_real():
     oc = oracle.newell_octant(n, (2e-9, 2.5e-9, 3e-9))
     Nk = np.fft.fftn(padded_tensor(oc, n, (12, 10, 8)), axes=(1, 2, 3))
     assert np.abs(Nk.imag).max() <= 1e-12 * np.abs(Nk.real).max()
+
+
+@pytest.mark.parametrize("n,h", [((6, 4, 3), (2e-9, 2.5e-9, 3e-9)), ((12, 5, 1), (3e-9, 2e-9, 1.5e-9)),
+                                 ((3, 3, 9), (2e-9, 2e-9, 2e-9))])
+def test_box_mean_field_matchesaharoni_factor(n, h):
+    """A uniformly magnetised box of cells: the mean cell field along each
+    axis is -N M with N the prism's closed-form demagnetising factor (the
+    cell-averaged tensor sums to the body-averaged one exactly), through the
+    Newell near field, the quadrature far field and the FFT convolution."""
+    mesh = oracle.Mesh(n, h)
+    cs = mesh.cell_shape
+    mat = oracle.Material(Ms=np.full(cs, 1e6), A=np.zeros(cs), alpha=np.zeros(cs))
+    half = [n[i] * h[i] / 2 for i in range(3)]
+    assert aharoni_factor(1.0, 1.0, 1.0) == pytest.approx(1 / 3, rel=1e-14)
+    for axis in range(3):
+        m = np.zeros((3,) + mesh.node_shape)
+        m[axis] = 1.0
+        H = oracle.demag_cell_field(mesh, mat, m)
+        others = [half[(axis + 1) % 3], half[(axis + 2) % 3]]
+        want = aharoni_factor(others[0], others[1], half[axis])
+        assert abs(-H[axis].mean() / 1e6 - want) <= 1e-11
