@@ -180,3 +180,36 @@ def test_continuous_adjoint_gradient_against_finite_differences():
         fd = (L(oracle.Material(**{**mat.__dict__, "h_cell": hp}))
               - L(oracle.Material(**{**mat.__dict__, "h_cell": hm}))) / (2 * h)
         assert abs(u[j, c3, c2, c1] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.abs(u).max()), (j, u[j, c3, c2, c1], fd)
+
+
+def test_macrospin_field_gradient_is_the_closed_form():
+    """One cell in a uniform state under a field H z (a macrospin): the polar
+    angle follows tan(theta/2) = tan(theta0/2) exp(-alpha gamma' H t), so
+    L = <m_z(T)> has dL/dH = sin(theta) * 2 u alpha gamma' T / (1 + u^2),
+    u = tan(theta(T)/2); the discrete adjoint's field-map gradient matches it
+    up to the O(dt^4) of RK4."""
+    mesh = oracle.Mesh((1, 1, 1), (2e-9, 2e-9, 2e-9))
+    cs = mesh.cell_shape
+    alpha, gamma, H, th0 = 0.5, 2.211e5, 1e5, 1.0
+    hc = np.zeros((3,) + cs)
+    hc[2] = H
+    mat = oracle.Material(Ms=np.full(cs, 8e5), A=np.full(cs, 1e-11), alpha=np.full(cs, alpha),
+                          gamma=gamma, h_cell=hc)
+    m0 = np.zeros((3,) + mesh.node_shape)
+    m0[0], m0[2] = np.sin(th0), np.cos(th0)
+    dt, nsteps = 1e-13, 200
+    T = dt * nsteps
+
+    def dloss(k, m):
+        g = np.zeros_like(m)
+        if k == nsteps:
+            g[2] = 1.0 / m[2].size
+        return g
+
+    _, dth, mT = rk4_gradient(mesh, mat, m0, dt, nsteps, dloss, EXCHANGE | ZEEMAN)
+    gp = gamma / (1 + alpha ** 2)
+    u = np.tan(th0 / 2) * np.exp(-alpha * gp * H * T)
+    theta = 2 * np.arctan(u)
+    assert abs(mT[2].mean() - np.cos(theta)) <= 1e-10
+    want = np.sin(theta) * 2 * u * alpha * gp * T / (1 + u * u)
+    assert abs(dth[2].sum() - want) <= 1e-7 * abs(want)
