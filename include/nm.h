@@ -46,7 +46,7 @@ typedef enum {
     NM_ENONFINITE = -5,    /* the state or the step error became NaN/Inf */
     NM_ESTEPSIZE = -6,     /* adaptive step fell below dt_min */
     NM_EBUDGET = -7,       /* a solve can never fit in the server's memory budget */
-    NM_EUNSUPPORTED = -8   /* valid request this build does not handle */
+    NM_EUNSUPPORTED = -8   /* valid request the library does not handle */
 } nm_status;
 
 /* Energy / field terms (bit mask). */
