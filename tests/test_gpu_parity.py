@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, EXCHANGE, ZEEMAN
-from helpers import rel_l2, to_oracle
+from helpers import aharoni_factor, rel_l2, to_oracle
 from paper_2411_11725_amd import binding as B
 from paper_2411_11725_amd import synth
 
@@ -339,3 +339,26 @@ def test_full_size_workload_field(name):
     assert rel_l2(g, want) <= 1e-5
     f = _field(p, terms, kind="rhs")
     assert rel_l2(f, oracle.llg_rhs(om, omat, om0)) <= 1e-5
+
+
+@pytest.mark.parametrize("n,h", [((128, 128, 32), (2e-9, 2e-9, 2e-9)), ((256, 64, 1), (3.9e-9, 3.9e-9, 3e-9)),
+                                 ((60, 20, 45), (2e-9, 3e-9, 1.5e-9))])
+def test_box_mean_field_matches_aharoni(n, h):
+    """A uniformly magnetised box at the workloads' sizes: the mean cell field
+    along each axis is -N M with N the prism's closed-form demagnetising
+    factor (Aharoni), a property of the exact convolution at any size."""
+    p = synth.make_problem(n, h, 1e6, 1e-11, 0.1, m0=(1.0, 0.0, 0.0))
+    mesh = B.mesh_from_problem(p)
+    half = [n[i] * h[i] / 2 for i in range(3)]
+    try:
+        for axis in range(3):
+            m0 = np.zeros_like(p["m0"])
+            m0[axis] = 1.0
+            out = torch.empty((3,) + (n[2], n[1], n[0]), dtype=torch.float32, device="cuda")
+            B.nm_demag_cell_field(mesh, _dev(m0), out)
+            torch.cuda.synchronize()
+            got = -float(out[axis].double().mean()) / 1e6
+            want = aharoni_factor(half[(axis + 1) % 3], half[(axis + 2) % 3], half[axis])
+            assert abs(got - want) <= 2e-6, (axis, got, want)
+    finally:
+        B.nm_mesh_destroy(mesh)
