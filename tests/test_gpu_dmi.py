@@ -50,10 +50,11 @@ def _field(p, terms, kind="heff", t=0.0):
         B.nm_mesh_destroy(mesh)
 
 
-@pytest.mark.parametrize("n1", [20, 100, 200, 350, 450])
+@pytest.mark.parametrize("n1", [20, 83, 84, 100, 168, 169, 200, 296, 297, 350, 424, 425, 450])
 def test_dmi_field_matches_oracle(n1):
-    """Rows of 21 to 451 nodes: the 5-, 7- and 10-item LDS windows and the
-    direct-load form (which the DMI kernels also use for 13-item rows)."""
+    """Rows of 21 to 451 nodes, on both sides of every window-size switch:
+    the 5-, 7- and 10-item LDS windows and the direct-load form (which the
+    DMI kernels also use for 13-item rows)."""
     p = _dmi((n1, 5, 3))
     om, omat, m0 = to_oracle(p)
     assert rel_l2(_field(p, B.NM_T_DMI), oracle.heff(om, omat, m0, DMI)) <= 1e-5

@@ -203,11 +203,12 @@ def test_every_tile_width_gives_the_same_field(n):
     assert rel_l2(outs[0], oracle.heff(om, omat, om0, ALL_TERMS)) <= 1e-5
 
 
-@pytest.mark.parametrize("n1", [20, 100, 200, 350, 450])
+@pytest.mark.parametrize("n1", [20, 83, 84, 100, 168, 169, 200, 296, 297, 350, 424, 425, 450])
 def test_long_rows_match_oracle(n1):
     """Rows from 21 to 451 nodes: every LDS window size of the node kernel
-    (5, 7, 10 and 13 items per thread), its direct-load form for rows too
-    long for a window, and the x passes up to 512-point half rows."""
+    (5, 7, 10 and 13 items per thread) on both sides of each switch (rows of
+    84/85, 169/170, 297/298 and 425/426 nodes), its direct-load form for rows
+    too long for a window, and the x passes up to 512-point half rows."""
     p = synth.small_random((n1, 5, 3), (2e-9, 3e-9, 2.5e-9), seed=51, ku_range=(-5e5, 5e5))
     om, omat, om0 = to_oracle(p)
     g = _field(p, ALL_TERMS)
