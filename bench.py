@@ -1,6 +1,7 @@
 """Benchmark: LLG cell-updates/s of the fused HIP hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload block|film|cube]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload block|block_large|block_dmi|film|film_basis|film_large|film_large_basis|cube]
 
 A step is one accepted Dormand-Prince 5(4) step (6 new right-hand sides with
 first-same-as-last) of the whole hot path: demag FFT convolution, local terms,
@@ -324,7 +325,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU: the hot path is a single-GPU build "
+        print("bench.py runs on one GPU: the hot path runs on a single GPU "
               "(multi-GPU sharding is design only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
