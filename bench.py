@@ -141,7 +141,7 @@ def counter_traffic(kernel, tag):
     return float(b.group(1))
 
 
-def cpu_baseline(p, terms_mask, evals=4):
+def cpu_baseline(p, terms_mask, evals=14):
     """Oracle right-hand-side evaluations of the same workload on the host."""
     import numpy as np
 
