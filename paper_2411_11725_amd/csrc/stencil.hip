@@ -31,6 +31,7 @@ struct StencilParams {
     int drive;                     // add the drive (the w component times sin and its amplitude)
     int W;                         // LDS window length per z offset: 256 + 2 NX + 2
     int faces;                     // K^e couples face neighbours (cells are not cubes)
+    unsigned zcols;                // node kernel: 256-node ranges per node layer
     const float *Dc;               // DMI constant per cell, or NULL
     float gx[4], gy[4];            // DMI weights (see the node kernel)
     float rNX, rNY;                // 1 / NX, 1 / NY
@@ -161,12 +162,23 @@ __device__ __forceinline__ int small_div(int a, int d, float rd) {
 #ifndef NM_NODE_WAVES
 #define NM_NODE_WAVES 3
 #endif
+constexpr unsigned kNodeZGroup = 32;
 template <int MODE, int STAGE, int NIT, bool DMI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
 k_node(StencilParams P, StageArgs S) {
-    // consecutive node ranges on one XCD: the halo rows of a block were
-    // fetched into that XCD's L2 by its neighbours
-    const unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    // consecutive block numbers on one XCD walk groups of kNodeZGroup
+    // 256-node ranges (a few rows of one node layer) layer by layer: the next
+    // layer's blocks find two of their three window layers and one of their
+    // two cell layers in that XCD's L2, while each block still reads
+    // contiguous rows.  zcols: ranges per layer; ranges past zcols NZ keep
+    // their place.
+    unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    if (kNodeZGroup > 0 && lb < P.zcols * (unsigned)P.NZ) {
+        const unsigned gi = lb / (kNodeZGroup * (unsigned)P.NZ);
+        const unsigned w = min(kNodeZGroup, P.zcols - gi * kNodeZGroup);
+        const unsigned rem = lb - gi * kNodeZGroup * (unsigned)P.NZ;
+        lb = (rem / w) * P.zcols + gi * kNodeZGroup + rem % w;
+    }
     const int tid = (int)threadIdx.x;
     const int n0 = (int)lb * 256;
     const int n = n0 + tid;
@@ -768,6 +780,7 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     P.drive = ((terms & NM_T_ZEEMAN) && m->has_drive) ? 1 : 0;
     P.W = 256 + 2 * m->NX + 2;
     P.faces = (m->Kp[1] != 0.f || m->Kp[2] != 0.f || m->Kp[4] != 0.f) ? 1 : 0;
+    P.zcols = m->NZ > 1 ? stencil_grid(m).x / (unsigned)m->NZ : 0u;
     P.Dc = ((terms & NM_T_DMI) && m->has_dmi) ? m->Dc : nullptr;
     for (int i = 0; i < 4; ++i) {
         P.gx[i] = m->gx[i];
