@@ -360,7 +360,9 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     const int tid = threadIdx.x;
     const long long plane = (long long)P2 * KP;
     const int ncols = P2 * KP;
-    const int col0 = blockIdx.x * TB;
+    // neighbouring column tiles on one XCD: a tile is narrower than a cache
+    // line, and the tiles next to it read the rest of each line from L2
+    const int col0 = (int)xcd_block(blockIdx.x, gridDim.x) * TB;
     // tiles of <= 16 columns never cross a ky row (KP is a multiple of 16)
     const int kx0 = col0 % KP;
     auto valid = [&](int b) {
@@ -551,7 +553,9 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     __shared__ float2 tl[L / 2 + 1];
     const int tid = threadIdx.x;
     const long long cstride = (long long)L * KP;
-    const int col0 = blockIdx.x * TB;
+    // neighbouring column tiles on one XCD: a tile is narrower than a cache
+    // line, and the tiles next to it read the rest of each line from L2
+    const int col0 = (int)xcd_block(blockIdx.x, gridDim.x) * TB;
     static_assert((L * NP) % 256 == 0, "whole iterations");
     constexpr int NI = L * NP / 256;
     float2 v[NI];
