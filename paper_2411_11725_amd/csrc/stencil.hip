@@ -139,8 +139,9 @@ __device__ __forceinline__ int small_div(int a, int d, float rd) {
 // W = 256 + 2 NX + 2 nodes, stored as float4 {m_x, m_y, m_z, 0}; NIT items of
 // the 3W per thread, read at clamped indices.  The neighbour at offsets
 // (dx, dy, dz) of the block's thread t then sits at (dz + 1) W + t + NX + 1 +
-// dy NX + dx.  Every value is fetched from the caches once per block instead
-// of by each of its 27 readers.  With NIT = 0 (rows too long for the window)
+// dy NX + dx (a single node layer, the film basis, keeps one window: its dz
+// neighbours are the layer itself).  Every value is fetched from the caches
+// once per block instead of by each of its 27 readers.  With NIT = 0 (rows too long for the window)
 // every thread reads its 27 neighbours itself, at clamped indices.  A
 // neighbour outside the mesh only enters through cells outside it, whose
 // weight is 0, so whatever finite value its slot holds is harmless.
@@ -185,6 +186,7 @@ k_node(StencilParams P, StageArgs S) {
     const Ctrl *C = S.ctrl;
     const int nn = (int)P.nn;
     const int NX = P.NX, NY = P.NY, NZ = P.NZ, W = P.W;
+    const int WS = NZ > 1 ? W : 0;   // LDS offset between the dz windows
     const float *in0 = S.in, *in1 = S.in + nn, *in2 = S.in + 2 * nn;
 
     // ---- LDS window of the stage input (issued first)
@@ -192,7 +194,8 @@ k_node(StencilParams P, StageArgs S) {
     float wv[NIT > 0 ? NIT : 1][3];
     if constexpr (NIT > 0) {
         // window p starts at n0 - NX - 1 + (p - 1) NXY; NXY = 0 with one node
-        // layer (the film basis), whose z neighbours are the layer itself
+        // layer (the film basis), whose z neighbours are the layer itself:
+        // the three windows coincide and only the first is kept (WS = 0)
         const int NXY = NZ > 1 ? NX * NY : 0;
         const int D = NXY - W;
         const int g0 = n0 - NX - 1 - NXY;          // = that start minus p W
@@ -307,11 +310,11 @@ k_node(StencilParams P, StageArgs S) {
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             const int j = tid + 256 * it;
-            if (j < 3 * W) sw[j] = make_float4(wv[it][0], wv[it][1], wv[it][2], 0.f);
+            if (j < (NZ > 1 ? 3 : 1) * W) sw[j] = make_float4(wv[it][0], wv[it][1], wv[it][2], 0.f);
         }
         // row starts (dx = -1) of the 9 (dz, dy) neighbour rows in the window
 #pragma unroll
-        for (int k = 0; k < 9; ++k) lrow[k] = tid + NX + (k / 3) * W + (k % 3 - 1) * NX;
+        for (int k = 0; k < 9; ++k) lrow[k] = tid + NX + (k / 3) * WS + (k % 3 - 1) * NX;
         __syncthreads();
     } else {
         int cx[3], cy[3], cz[3];
@@ -808,10 +811,11 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     return P;
 }
 
-// window items per thread: the smallest of 5, 7, 10, 13 covering 3 W; rows
-// longer than that (NX > 425) read their neighbours directly
-static int window_items(int NX) {
-    const int need = (3 * (256 + 2 * NX + 2) + 255) / 256;
+// window items per thread: the smallest of 5, 7, 10, 13 covering the 3 W of
+// the dz windows (one W with a single node layer); longer rows (NX > 425,
+// or NX > 1535 with one layer) read their neighbours directly
+static int window_items(int NX, int NZ) {
+    const int need = ((NZ > 1 ? 3 : 1) * (256 + 2 * NX + 2) + 255) / 256;
     return need <= 5 ? 5 : need <= 7 ? 7 : need <= 10 ? 10 : need <= 13 ? 13 : 0;
 }
 
@@ -820,7 +824,7 @@ static int window_items(int NX) {
 // at 3 waves per SIMD, and those rows read their neighbours directly
 template <int MODE, int STAGE, bool DMI>
 static void launch_node_t(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
-    switch (window_items(m->NX)) {
+    switch (window_items(m->NX, m->NZ)) {
         case 5: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 5, DMI>), grid, dim3(256), 0, P, S); break;
         case 7: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 7, DMI>), grid, dim3(256), 0, P, S); break;
         case 10: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 10, DMI>), grid, dim3(256), 0, P, S); break;
