@@ -739,8 +739,8 @@ static hipError_t demag_pipeline(nm_mesh *m, const float *mag, const Ctrl *ctrl,
 
 // ------------------------------------------------------------ tile tuner
 // Block widths of the register-FFT passes, chosen per padded shape by timing
-// every width on the mesh itself (a warm-up and 5 launches each; the fastest
-// total wins) and cached per (P1, P2, P3, N2, N3, device).  Small meshes run
+// every width on the mesh itself (a warm-up and 5 launches, three times
+// each) and cached per (P1, P2, P3, N2, N3, device).  Small meshes run
 // only a few dozen blocks per pass, where narrower blocks finish sooner;
 // large ones keep the widest.  Every width computes each column identically,
 // so the choice never changes results.
@@ -793,33 +793,38 @@ hipError_t tune_passes(nm_mesh *m) {
         if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
         return r;
     };
+    // each width timed three times, interleaved, keeping its fastest; the
+    // widest tile wins unless a narrower one is at least 5% faster (single
+    // timings of a few launches are noisy, and a narrower tile that wins by
+    // noise in isolation can lose inside the pipeline)
+    auto pick = [&](int nw, auto run_v, int *best) -> hipError_t {
+        float t[3] = {1e30f, 1e30f, 1e30f};
+        hipError_t r = hipSuccess;
+        for (int rep = 0; rep < 3 && r == hipSuccess; ++rep)
+            for (int v = 0; v < nw && r == hipSuccess; ++v) {
+                float ms = 0.f;
+                r = time_it([&]() -> hipError_t { return run_v(v); }, &ms);
+                if (r == hipSuccess) t[v] = fminf(t[v], ms);
+            }
+        int b = 0;
+        for (int v = 1; v < nw; ++v)
+            if (t[v] < 0.95f * t[b]) b = v;
+        *best = b;
+        return r;
+    };
     int best_y = 0, best_z = 0;
-    float ty = 1e30f, tz = 1e30f;
-    for (int v = 0; v < widths(m->P2) && e == hipSuccess; ++v) {
-        m->tune_y = v;
-        float ms = 0.f;
-        e = time_it([&]() -> hipError_t {
+    if (e == hipSuccess)
+        e = pick(widths(m->P2), [&](int v) -> hipError_t {
+            m->tune_y = v;
             NM_DISPATCH_COL(m->P2, launch_y_pair, m, tw, nullptr);
             return hipGetLastError();
-        }, &ms);
-        if (e == hipSuccess && ms < ty) {
-            ty = ms;
-            best_y = v;
-        }
-    }
-    if (m->P3 <= 256)
-        for (int v = 0; v < widths(m->P3) && e == hipSuccess; ++v) {
+        }, &best_y);
+    if (e == hipSuccess && m->P3 <= 256)
+        e = pick(widths(m->P3), [&](int v) -> hipError_t {
             m->tune_z = v;
-            float ms = 0.f;
-            e = time_it([&]() -> hipError_t {
-                NM_DISPATCH_COL(m->P3, launch_zconv, m, tw, nullptr);
-                return hipGetLastError();
-            }, &ms);
-            if (e == hipSuccess && ms < tz) {
-                tz = ms;
-                best_z = v;
-            }
-        }
+            NM_DISPATCH_COL(m->P3, launch_zconv, m, tw, nullptr);
+            return hipGetLastError();
+        }, &best_z);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     m->tune_y = best_y;
