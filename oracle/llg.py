@@ -86,9 +86,12 @@ def dp45_attempt(mesh, mat, m, t, dt, k1=None, terms=ALL_TERMS, alpha_n=None):
 
 
 def dp45_solve(mesh, mat, m0, t0, t_end, dt0, rtol=1e-5, atol=1e-5,
-               terms=ALL_TERMS, dt_min=1e-20, dt_max=np.inf, max_attempts=100000):
+               terms=ALL_TERMS, dt_min=1e-20, dt_max=np.inf, max_attempts=100000,
+               max_accepted=None, return_dt=False):
     """Adaptive DP45 from t0 to t_end; returns (m, log) with log the list of
-    (t, dt, accepted) for every attempt."""
+    (t, dt, accepted) for every attempt, and with return_dt also the step the
+    controller proposes next (to continue the integration in a later call).
+    max_accepted: stop after that many accepted steps."""
     m = np.array(m0, dtype=np.float64)
     t, dt = float(t0), float(dt0)
     a = nodal_alpha(mesh, mat)
@@ -96,8 +99,9 @@ def dp45_solve(mesh, mat, m0, t0, t_end, dt0, rtol=1e-5, atol=1e-5,
     k1 = None
     log = []
     rejected_last = False
+    n_acc = 0
     for _ in range(max_attempts):
-        if t >= t_end:
+        if t >= t_end or (max_accepted is not None and n_acc >= max_accepted):
             break
         dt = min(dt, t_end - t, dt_max)
         y, err, k7 = dp45_attempt(mesh, mat, m, t, dt, k1, terms, a)
@@ -115,12 +119,15 @@ def dp45_solve(mesh, mat, m0, t0, t_end, dt0, rtol=1e-5, atol=1e-5,
             if rejected_last:
                 fac = min(fac, 1.0)
             rejected_last = False
+            n_acc += 1
         else:
             log.append((t, dt, False))
             rejected_last = True
         dt = dt * fac
         if dt < dt_min:
             raise FloatingPointError("step size below dt_min")
+    if return_dt:
+        return m, log, dt
     return m, log
 
 
