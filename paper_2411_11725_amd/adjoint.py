@@ -51,7 +51,7 @@ class LLGTrajectory(torch.autograd.Function):
             raise ValueError("nsteps, ckpt_every and sample_every must be >= 1")
         if ckpt_every % sample_every or nsteps % sample_every:
             raise ValueError("ckpt_every and nsteps must be multiples of sample_every")
-        theta = theta.detach().contiguous()
+        theta = theta.detach().clone().contiguous()   # kept for the backward pass
         B.nm_mesh_set_field(mesh, theta)
         m = m0.detach().clone().contiguous()
         ckpts, samples = [], []
@@ -66,18 +66,21 @@ class LLGTrajectory(torch.autograd.Function):
             k = nxt
         ctx.mesh = mesh
         ctx.args = (dt, nsteps, ckpt_every, sample_every, terms, t0)
-        ctx.save_for_backward(*ckpts)
-        ctx.theta_shape = theta.shape
+        ctx.save_for_backward(theta, *ckpts)
         return torch.stack(samples)
 
     @staticmethod
     def backward(ctx, grad_samples):
         dt, nsteps, ckpt_every, sample_every, terms, t0 = ctx.args
-        ckpts = ctx.saved_tensors
+        theta, *ckpts = ctx.saved_tensors
         mesh = ctx.mesh
+        # the adjoint recomputes the forward segments from the mesh's field
+        # map: restore this trajectory's one (another forward pass on the
+        # same mesh may have replaced it since)
+        B.nm_mesh_set_field(mesh, theta)
         g = grad_samples.contiguous()
         lam = torch.zeros_like(ckpts[0])
-        gth = torch.zeros(ctx.theta_shape, dtype=torch.float32, device=lam.device)
+        gth = torch.zeros(theta.shape, dtype=torch.float32, device=lam.device)
         for si in range(len(ckpts) - 1, -1, -1):
             k0 = si * ckpt_every
             nseg = min(ckpt_every, nsteps - k0)
@@ -93,7 +96,7 @@ class LLGTrajectoryContinuous(torch.autograd.Function):
     def forward(ctx, theta, m0, mesh, dt, nsteps, sample_every, terms, t0=0.0):
         if nsteps < 1 or sample_every < 1 or nsteps % sample_every:
             raise ValueError("nsteps must be a positive multiple of sample_every >= 1")
-        theta = theta.detach().contiguous()
+        theta = theta.detach().clone().contiguous()   # kept for the backward pass
         B.nm_mesh_set_field(mesh, theta)
         m = m0.detach().clone().contiguous()
         samples = []
@@ -103,18 +106,18 @@ class LLGTrajectoryContinuous(torch.autograd.Function):
             samples.append(m.clone())
         ctx.mesh = mesh
         ctx.args = (dt, nsteps, sample_every, terms, t0)
-        ctx.save_for_backward(m)
-        ctx.theta_shape = theta.shape
+        ctx.save_for_backward(theta, m)
         return torch.stack(samples)
 
     @staticmethod
     def backward(ctx, grad_samples):
         dt, nsteps, sample_every, terms, t0 = ctx.args
-        (m_end,) = ctx.saved_tensors
+        theta, m_end = ctx.saved_tensors
+        B.nm_mesh_set_field(ctx.mesh, theta)   # this trajectory's field map
         g = grad_samples.contiguous()
         m = m_end.clone()
         a = torch.zeros_like(m)
-        gth = torch.zeros(ctx.theta_shape, dtype=torch.float32, device=m.device)
+        gth = torch.zeros(theta.shape, dtype=torch.float32, device=m.device)
         for si in range(nsteps // sample_every - 1, -1, -1):
             a += g[si]
             B.nm_adjoint_continuous(ctx.mesh, m, t0 + (si + 1) * sample_every * dt, dt, sample_every, terms, a,

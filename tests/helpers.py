@@ -38,3 +38,19 @@ def aharoni_factor(a, b, c):
          - (ab ** 3 + bc ** 3 + ac ** 3) / (3 * a * b * c))
     return t / np.pi
 
+
+
+def gpu_replay_steps(B, mesh, m, steps, terms, rtol=1e-5, atol=1e-5):
+    """Make the GPU take a given list of accepted DP45 steps (t, dt) (the
+    oracle's own): one call per step, starting at t with the proposal dt and
+    ending at t + dt.  Returns the clock of the last call; every attempt must
+    have been accepted."""
+    rej = 0
+    clk = None
+    for t, dt in steps:
+        clk = B.nm_clock(t, dt, 0, 0, 0, 0.0)
+        B.nm_llg_step(mesh, m, clk, B.NM_DP45, terms, t_end=t + dt, rtol=rtol, atol=atol, max_steps=1)
+        rej += clk.rejected
+        assert clk.accepted == 1, (t, dt, clk.accepted)
+    assert rej == 0, "the GPU rejected %d of the oracle's accepted steps" % rej
+    return clk

@@ -189,3 +189,35 @@ def test_continuous_autograd_matches_the_discrete_gradient():
     (gd, md), (gc, mc) = grads
     assert rel_l2(gc, gd) <= 1e-4
     assert rel_l2(mc, md) <= 1e-4
+
+
+@pytest.mark.parametrize("fn", ["discrete", "continuous"])
+def test_backward_uses_its_own_field_map(fn):
+    """Two trajectories with different field maps on one mesh, then the
+    backward pass of the first only: its gradient is the oracle's for its own
+    field map (the second forward pass replaced the mesh's map in between)."""
+    p, om, omat, m0, region = _magnonic_small()
+    nsteps, dt = 24, 5e-14
+    rng = np.random.default_rng(8)
+    th = [rng.uniform(-3e3, 3e3, size=(3,) + om.cell_shape).astype(np.float32) for _ in range(2)]
+    mesh = B.mesh_from_problem(p)
+    try:
+        reg = torch.as_tensor(region, device="cuda")
+        losses, thetas = [], []
+        for k in range(2):
+            theta = _dev(th[k]).requires_grad_(True)
+            if fn == "discrete":
+                traj = LLGTrajectory.apply(theta, _dev(p["m0"]), mesh, dt, nsteps, 8, 1, B.NM_T_ALL)
+            else:
+                traj = LLGTrajectoryContinuous.apply(theta, _dev(p["m0"]), mesh, dt, nsteps, 1, B.NM_T_ALL)
+            losses.append(-(traj[:, 2][:, reg] ** 2).mean(dim=1).mean())
+            thetas.append(theta)
+        losses[0].backward()
+        g = thetas[0].grad.cpu().numpy().astype(np.float64)
+        assert thetas[1].grad is None
+    finally:
+        B.nm_mesh_destroy(mesh)
+    omat.h_cell = th[0].astype(np.float64)
+    _, dloss = region_mz2_loss(om, region, nsteps)
+    _, dth_o, _ = rk4_gradient(om, omat, m0, dt, nsteps, dloss, ALL_TERMS)
+    assert rel_l2(g, dth_o) <= 1e-4

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 import oracle
 from oracle.adjoint import continuous_adjoint, rk4_step_adjoint
 from oracle.field import ALL_TERMS, DMI
-from helpers import rel_l2, to_oracle
+from helpers import gpu_replay_steps, rel_l2, to_oracle
 from paper_2411_11725_amd import binding as B
 from paper_2411_11725_amd import synth
 
@@ -136,11 +136,15 @@ def test_dmi_rk4_trajectory_matches_oracle():
 
 
 def test_dmi_dp45_replay_matches_oracle():
-    """The first adaptive steps on a DMI film, node by node, with the oracle
-    taking the GPU's accepted steps."""
+    """The first adaptive steps on a DMI film: the GPU controller takes the
+    oracle's steps (to the accuracy of the float32 error estimate), and the
+    GPU replaying the oracle's accepted steps matches it node by node."""
     p = synth.make_problem((32, 16, 1), (3e-9, 3e-9, 1e-9), 8e5, 1.3e-11, 0.1,
                            m0=(0.0, 0.1 / np.sqrt(1.01), 1.0 / np.sqrt(1.01)), D=np.full((1, 16, 32), 2e-3))
     p = synth.as_film(p)
+    om, omat, m0 = to_oracle(p)
+    want, olog = oracle.dp45_solve(om, omat, m0, 0.0, 1e-9, 1e-14, rtol=1e-5, atol=1e-5, max_accepted=6)
+    so = [(t, dt) for t, dt, ok in olog if ok]
     mesh = B.mesh_from_problem(p)
     log = torch.zeros(3 * 64, dtype=torch.float64, device="cuda")
     try:
@@ -148,14 +152,15 @@ def test_dmi_dp45_replay_matches_oracle():
         clk = B.nm_clock(0.0, 1e-14, 0, 0, 0, 0.0)
         B.nm_llg_step(mesh, m, clk, B.NM_DP45, B.NM_T_ALL, t_end=1e-9, rtol=1e-5, atol=1e-5,
                       log=log, max_steps=6)
+        m = _dev(p["m0"])
+        gpu_replay_steps(B, mesh, m, so, B.NM_T_ALL)
         g = m.cpu().numpy().astype(np.float64)
     finally:
         B.nm_mesh_destroy(mesh)
     L = log.cpu().numpy().reshape(-1, 3)[: clk.accepted + clk.rejected]
     steps = [(t, dt) for t, dt, ok in L if ok > 0.5]
-    assert clk.accepted == 6 and len(steps) == 6
-    om, omat, m0 = to_oracle(p)
-    want = oracle.dp45_replay(om, omat, m0, steps)
+    assert clk.accepted == 6 and len(steps) == 6 and len(so) == 6
+    assert np.allclose(np.array(steps), np.array(so), rtol=1e-3, atol=0)
     assert np.abs(g - want).max() <= 1e-6
 
 

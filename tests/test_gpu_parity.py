@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from oracle.field import ALL_TERMS, ANISOTROPY, DEMAG, EXCHANGE, ZEEMAN
-from helpers import aharoni_factor, rel_l2, to_oracle
+from helpers import aharoni_factor, gpu_replay_steps, rel_l2, to_oracle
 from paper_2411_11725_amd import binding as B
 from paper_2411_11725_amd import synth
 
@@ -252,24 +252,38 @@ def test_rk4_calls_queue_without_waiting_and_keep_the_clock():
     assert np.abs(g - want).max() <= 1e-5
 
 
-def _film_dp45(max_steps, t_end=0.05e-9):
-    p = synth.make_problem((32, 16, 1), (3.9e-9, 3.9e-9, 3e-9), 8e5, 1.3e-11, 0.02,
-                           m0=(np.cos(0.17), np.sin(0.17), 0.0),
-                           h_uniform=(-25e-3 / synth.MU0_SI, 4e-3 / synth.MU0_SI, 0.0))
+def _film_problem():
+    return synth.make_problem((32, 16, 1), (3.9e-9, 3.9e-9, 3e-9), 8e5, 1.3e-11, 0.02,
+                              m0=(np.cos(0.17), np.sin(0.17), 0.0),
+                              h_uniform=(-25e-3 / synth.MU0_SI, 4e-3 / synth.MU0_SI, 0.0))
+
+
+def _film_dp45(max_steps, t_end=0.05e-9, dt0=1e-14):
+    p = _film_problem()
     mesh = B.mesh_from_problem(p)
     log = torch.zeros(3 * 4000, dtype=torch.float64, device="cuda")
     try:
         m = _dev(p["m0"])
-        clk = B.nm_clock(0.0, 1e-14, 0, 0, 0, 0.0)
+        clk = B.nm_clock(0.0, dt0, 0, 0, 0, 0.0)
         B.nm_llg_step(mesh, m, clk, B.NM_DP45, B.NM_T_ALL, t_end=t_end, rtol=1e-5, atol=1e-5,
                       log=log, max_steps=max_steps)
         g = m.cpu().numpy().astype(np.float64)
     finally:
         B.nm_mesh_destroy(mesh)
     L = log.cpu().numpy().reshape(-1, 3)[: clk.accepted + clk.rejected]
-    steps = [(t, dt) for t, dt, ok in L if ok > 0.5]
-    assert len(steps) == clk.accepted
-    return p, g, steps, clk
+    assert sum(1 for x in L if x[2] > 0.5) == clk.accepted
+    return p, g, [(t, dt, ok > 0.5) for t, dt, ok in L], clk
+
+
+def _replay(p, steps):
+    """The GPU state after taking the given accepted steps (t, dt)."""
+    mesh = B.mesh_from_problem(p)
+    try:
+        m = _dev(p["m0"])
+        gpu_replay_steps(B, mesh, m, steps, B.NM_T_ALL)
+        return m.cpu().numpy().astype(np.float64)
+    finally:
+        B.nm_mesh_destroy(mesh)
 
 
 def test_dp45_split_calls_follow_the_same_steps():
@@ -277,7 +291,7 @@ def test_dp45_split_calls_follow_the_same_steps():
     (every last replay of a call is a smaller graph): the same accepted steps
     and the same state, up to the rounding of the first stage recomputed at
     each call."""
-    p, g1, steps1, clk1 = _film_dp45(max_steps=1 << 40, t_end=0.01e-9)
+    p, g1, log1, clk1 = _film_dp45(max_steps=1 << 40, t_end=0.01e-9)
     mesh = B.mesh_from_problem(p)
     try:
         m = _dev(p["m0"])
@@ -298,34 +312,58 @@ def test_dp45_split_calls_follow_the_same_steps():
     assert np.abs(g2 - g1).max() <= 1e-5
 
 
-def test_dp45_replay_first_steps_pointwise():
-    """Replay parity, node by node, while the steps are inside the stability
-    region of the exchange modes (the first accepted steps)."""
-    p, g, steps, clk = _film_dp45(max_steps=5)
-    assert clk.accepted == 5
+def test_dp45_controller_log_matches_oracle():
+    """The GPU controller's attempt log (t, dt, accepted) against the float64
+    oracle's own adaptive run from a step far too large (a forced rejection,
+    the no-growth step after it, then the error-driven steps): the same
+    accept / reject pattern; t and dt agree to the accuracy of the float32
+    error estimate (a cancelling combination of the stage derivatives whose
+    rounding reaches ~1e-4 of the norm, a fifth of that in the step)."""
+    n_att = 24
+    p, _, log, clk = _film_dp45(max_steps=1 << 40, t_end=0.05e-9, dt0=2e-11)
     om, omat, om0 = to_oracle(p)
-    want = oracle.dp45_replay(om, omat, om0, steps)
+    _, olog = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 2e-11, rtol=1e-5, atol=1e-5, max_attempts=n_att)
+    assert len(log) >= n_att and len(olog) == n_att
+    assert not olog[0][2] and sum(1 for x in olog if not x[2]) >= 1
+    assert [x[2] for x in log[:n_att]] == [x[2] for x in olog]
+    worst = max(max(abs(a[0] - b[0]) / max(b[0], b[1]), abs(a[1] - b[1]) / b[1])
+                for a, b in zip(log[:n_att], olog))
+    assert worst <= 1e-3, worst
+
+
+def test_dp45_replay_first_steps_pointwise():
+    """Replay parity, node by node: the GPU takes the oracle's first accepted
+    steps (inside the stability region of the exchange modes)."""
+    p = _film_problem()
+    om, omat, om0 = to_oracle(p)
+    want, olog = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 1e-14, rtol=1e-5, atol=1e-5, max_accepted=5)
+    steps = [(t, dt) for t, dt, ok in olog if ok]
+    assert len(steps) == 5
+    g = _replay(p, steps)
     assert np.abs(g - want).max() <= 1e-6
 
 
 def test_dp45_film_replay_and_independent_parity():
-    """Full adaptive run with a field step.  Replay mode: the oracle takes the
-    GPU's accepted steps.  Once the controller sits at the stability limit of
-    the stiff exchange modes, rounding-level noise in those modes grows to the
-    tolerance scale in either precision (the oracle's own adaptive run breaks
-    the problem's inversion symmetry by ~7e-4 the same way), so the
+    """Full adaptive run with a field step.  Replay mode: the GPU takes the
+    oracle's accepted steps.  Once the controller sits at the stability limit
+    of the stiff exchange modes, rounding-level noise in those modes grows to
+    the tolerance scale in either precision (the oracle's own adaptive run
+    breaks the problem's inversion symmetry by ~7e-4 the same way), so the
     comparison is made on the film average <m> (the observable of this
-    workload); node values are only held to the tolerance scale."""
-    p, g, steps, clk = _film_dp45(max_steps=1 << 40)
-    assert clk.accepted > 5
-    assert abs(sum(dt for _, dt in steps) - 0.05e-9) < 1e-22
+    workload); node values are only held to the tolerance scale.
+    Independent mode: both run their own controllers."""
+    p = _film_problem()
     om, omat, om0 = to_oracle(p)
-    want = oracle.dp45_replay(om, omat, om0, steps)
+    want, olog = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 1e-14, rtol=1e-5, atol=1e-5)
+    steps = [(t, dt) for t, dt, ok in olog if ok]
+    assert len(steps) > 5
+    g = _replay(p, steps)
     mean = lambda a: a.mean(axis=(1, 2, 3))
     assert np.abs(mean(g) - mean(want)).max() <= 1e-6
     assert np.abs(g - want).max() <= 2e-3
-    indep, _ = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 1e-14, rtol=1e-5, atol=1e-5)
-    assert np.abs(mean(g) - mean(indep)).max() <= 1e-4
+    _, gi, _, clk = _film_dp45(max_steps=1 << 40)
+    assert abs(clk.t - 0.05e-9) <= 1e-22
+    assert np.abs(mean(gi) - mean(want)).max() <= 1e-4
 
 
 @pytest.mark.parametrize("name", ["film", "block", "block_dmi"])

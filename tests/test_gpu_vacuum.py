@@ -10,7 +10,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from oracle.field import ALL_TERMS
-from helpers import rel_l2, to_oracle
+from helpers import gpu_replay_steps, rel_l2, to_oracle
 from paper_2411_11725_amd import binding as B
 from paper_2411_11725_amd import synth
 
@@ -122,7 +122,9 @@ def test_dp45_error_norm_runs_over_magnetic_nodes_only():
     would scale it by sqrt(168/720) and every step by ~16%).  The error
     estimate is a cancelling combination of the stage derivatives, which
     amplifies the rounding differences of the two meshes' FFTs to ~1e-4 in
-    the step sizes.  The oracle replays the embedded run's steps."""
+    the step sizes.  The oracle's own run of the embedded magnet takes the
+    same steps, and the GPU replaying the oracle's steps matches it node by
+    node."""
     p, q = _pair()
     gp, sp = _dp45(p, 5)
     gq, sq = _dp45(q, 5)
@@ -130,7 +132,17 @@ def test_dp45_error_norm_runs_over_magnetic_nodes_only():
     assert np.allclose(np.array(sq), np.array(sp), rtol=1e-3, atol=0)
     assert np.abs(_core_nodes(gq) - gp).max() <= 1e-4   # the same states at ~1e-4 different times
     om, omat, m0 = to_oracle(q)
-    assert np.abs(gq - oracle.dp45_replay(om, omat, m0, sq)).max() <= 1e-6
+    want, olog = oracle.dp45_solve(om, omat, m0, 0.0, 1e-9, 1e-14, rtol=1e-5, atol=1e-5, max_accepted=5)
+    so = [(t, dt) for t, dt, ok in olog if ok]
+    assert np.allclose(np.array(sq), np.array(so), rtol=1e-3, atol=0)
+    mesh = B.mesh_from_problem(q)
+    try:
+        m = _dev(q["m0"])
+        gpu_replay_steps(B, mesh, m, so, B.NM_T_ALL)
+        gr = m.cpu().numpy().astype(np.float64)
+    finally:
+        B.nm_mesh_destroy(mesh)
+    assert np.abs(gr - want).max() <= 1e-6
 
 
 def test_porous_mesh_matches_oracle():

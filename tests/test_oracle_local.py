@@ -24,8 +24,9 @@ def _problem(n=(5, 4, 3), h=(2e-9, 3e-9, 2.5e-9), seed=3, **kw):
 
 
 def test_lst2_exchange_diagonal_coefficient():
-    """Sec. 5.1, Lst. form_code prints the diagonal entry of the generated
-    exchange element: 0.2222..*(dx0 dx1/dx2 + dx0 dx2/dx1 + dx1 dx2/dx0)."""
+    """Sec. 5.1, Lst. form_code: the printed coefficient (2/9, to 15 digits)
+    of a node's own value in the generated exchange element, times the sum
+    of h_i h_j / h_k over the axis permutations."""
     with open(os.path.join(GOLDEN, "lst2_exchange_diagonal.txt")) as fh:
         coef = [float(l.split()[1]) for l in fh if l.startswith("coefficient")][0]
     rng = np.random.default_rng(0)
