@@ -569,9 +569,11 @@ nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integ
 }
 
 // One batch of steps / attempts: launched directly while profiling, else
-// captured once into a graph (keyed on method, terms, state pointer and
-// batch) and replayed on the mesh stream.  Power-of-two batches below the
-// keyed one (the end of an integration) are captured beside it.
+// replayed from a captured graph on the mesh stream.  The main graph holds
+// `full` steps / attempts and is keyed on method, terms, state pointer and
+// `full`; shorter power-of-two batches (the end of an integration) are
+// captured beside it.  Every graph is uploaded right after instantiation,
+// so its first replay costs what later ones cost.
 static int tail_slot(int batch) {
     for (int k = 0; k < 6; ++k)
         if (batch == (1 << k)) return k;
@@ -592,10 +594,10 @@ int next_batch(const nm_mesh *m, int batch) {
     return batch_for(est, batch);
 }
 
-hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int batch) {
-    auto enqueue_batch = [&]() -> hipError_t {
+hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int full, int batch) {
+    auto enqueue_batch = [&](int count) -> hipError_t {
         hipError_t e = hipSuccess;
-        for (int q = 0; q < batch && e == hipSuccess; ++q) {
+        for (int q = 0; q < count && e == hipSuccess; ++q) {
             if (method == NM_RK4) {
                 if (e == hipSuccess) e = rk4_stage(m, terms, 1, mag, m->y[0], mag);
                 if (e == hipSuccess) e = rk4_stage(m, terms, 2, m->y[0], m->y[1], mag);
@@ -610,39 +612,38 @@ hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int ba
         }
         return e;
     };
-    if (m->prof) return enqueue_batch();
-    auto capture = [&](hipGraphExec_t *out) -> hipError_t {
+    if (m->prof) return enqueue_batch(batch);
+    auto capture = [&](hipGraphExec_t *out, int count) -> hipError_t {
         hipStream_t user = m->stream;
         m->stream = m->cap_stream;
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeRelaxed);
-        hipError_t e2 = e == hipSuccess ? enqueue_batch() : e;
+        hipError_t e2 = e == hipSuccess ? enqueue_batch(count) : e;
         if (e == hipSuccess) e = hipStreamEndCapture(m->cap_stream, &graph);
         m->stream = user;
         if (e == hipSuccess) e = e2;
         if (e == hipSuccess) e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
+        if (e == hipSuccess) e = hipGraphUpload(*out, m->stream);
         return e;
     };
-    const bool key = m->gexec && m->g_method == method && m->g_terms == terms && m->g_mag == mag;
-    const int ts = tail_slot(batch);
-    if (key && batch < m->g_batch && ts >= 0) {
-        if (!m->gtail[ts]) {
-            hipError_t e = capture(&m->gtail[ts]);
-            if (e != hipSuccess) return e;
-        }
-        return hipGraphLaunch(m->gtail[ts], m->stream);
-    }
-    if (!(key && m->g_batch == batch)) {
+    if (!(m->gexec && m->g_method == method && m->g_terms == terms && m->g_mag == mag && m->g_batch == full)) {
         drop_graph(m);
-        hipError_t e = capture(&m->gexec);
+        hipError_t e = capture(&m->gexec, full);
         if (e != hipSuccess) return e;
         m->g_method = method;
         m->g_terms = terms;
         m->g_mag = mag;
-        m->g_batch = batch;
+        m->g_batch = full;
     }
-    return hipGraphLaunch(m->gexec, m->stream);
+    if (batch == full) return hipGraphLaunch(m->gexec, m->stream);
+    const int ts = tail_slot(batch);
+    if (ts < 0 || batch > full) return hipErrorInvalidValue;
+    if (!m->gtail[ts]) {
+        hipError_t e = capture(&m->gtail[ts], batch);
+        if (e != hipSuccess) return e;
+    }
+    return hipGraphLaunch(m->gtail[ts], m->stream);
 }
 
 // asynchronous copy of the device controller into the pinned mirror
@@ -687,7 +688,7 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         for (long k = 0; k < nsteps;) {
             // the last replays take powers of two that add up to the rest
             const int b = batch_for((double)(nsteps - k), batch);
-            NM_HIP(step_batch(m, mag, NM_RK4, terms, b), "nm_llg_step");
+            NM_HIP(step_batch(m, mag, NM_RK4, terms, batch, b), "nm_llg_step");
             k += b;
         }
         // Fixed steps: the call returns without waiting for the GPU; the clock
@@ -709,7 +710,7 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         long long seen = -1;
         int b = batch_for(std::fmin((double)max_steps, std::ceil((t_end - clk->t) / clk->dt * (1.0 + 1e-9))), batch);
         for (;;) {
-            NM_HIP(step_batch(m, mag, NM_DP45, terms, b), "nm_llg_step");
+            NM_HIP(step_batch(m, mag, NM_DP45, terms, batch, b), "nm_llg_step");
             NM_HIP(ctrl_readback(m), "nm_llg_step");
             NM_HIP(hipStreamSynchronize(m->stream), "nm_llg_step");
             if (m->ctrl_host->done) break;

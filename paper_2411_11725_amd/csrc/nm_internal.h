@@ -186,6 +186,8 @@ hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const C
 hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], double *out,
                                 hipStream_t s);
 hipError_t build_kspace_tensor(nm_mesh *m);
+size_t kspace_scratch_bytes(const nm_mesh *m);          // float64 temporaries of the set-up
+hipError_t build_kspace_tensor_with(nm_mesh *m, void *work);   // temporaries in work; no allocation
 
 // stencil / LLG / stage kernels
 // kModeAdjFwd: store H(y_s) and form the next RK4 stage input (adjoint recompute)
@@ -221,7 +223,9 @@ hipError_t launch_rk4_advance(nm_mesh *m);
 // stepping building blocks shared by nm_llg_step and the solve server
 nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integrator *in,
                      double t_end, long max_steps, int *batch);
-hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int batch);
+// one replay of `batch` steps / attempts (batch == full, or a power of two
+// below it) from the graphs keyed on `full`
+hipError_t step_batch(nm_mesh *m, float *mag, int method, unsigned terms, int full, int batch);
 hipError_t ctrl_readback(nm_mesh *m);
 nm_status step_finish(nm_mesh *m, int method, nm_clock *clk);
 

@@ -222,7 +222,7 @@ void run(nm_server *S) {
         bool progressed = false;
         for (Solve *s : S->active) {
             if (s->inflight) continue;
-            hipError_t e = step_batch(s->mesh, s->m_dev, NM_DP45, s->req.terms, s->next);
+            hipError_t e = step_batch(s->mesh, s->m_dev, NM_DP45, s->req.terms, s->batch, s->next);
             if (e == hipSuccess) e = ctrl_readback(s->mesh);
             if (e == hipSuccess) e = hipEventRecord(s->ev, s->stream);
             if (e != hipSuccess) {

@@ -314,21 +314,29 @@ def test_dp45_split_calls_follow_the_same_steps():
 
 def test_dp45_controller_log_matches_oracle():
     """The GPU controller's attempt log (t, dt, accepted) against the float64
-    oracle's own adaptive run from a step far too large (a forced rejection,
-    the no-growth step after it, then the error-driven steps): the same
-    accept / reject pattern; t and dt agree to the accuracy of the float32
-    error estimate (a cancelling combination of the stage derivatives whose
-    rounding reaches ~1e-4 of the norm, a fifth of that in the step)."""
-    n_att = 24
+    oracle's own adaptive run from a step far too large: two rejections, the
+    no-growth step after them, then error-driven steps; the same accept /
+    reject pattern, and t and dt to the accuracy of the float32 error
+    estimate (a cancelling combination of the stage derivatives whose
+    rounding reaches ~1e-5 of the norm, a fifth of that in the step; 2.5e-6
+    measured).  The comparison covers the first 6 attempts: at the steps
+    that follow (~1.87e-12 s) the film's stiff exchange modes lie outside
+    the Dormand-Prince stability region, and their rounding noise grows ~8x
+    per step until the error estimate sees it, after 2-3 more steps in
+    float32 and ~10 more in float64 (the oracle's own run is rejected there),
+    so the two logs part by construction, not by a fault of either."""
+    n_att = 6
     p, _, log, clk = _film_dp45(max_steps=1 << 40, t_end=0.05e-9, dt0=2e-11)
     om, omat, om0 = to_oracle(p)
     _, olog = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 2e-11, rtol=1e-5, atol=1e-5, max_attempts=n_att)
     assert len(log) >= n_att and len(olog) == n_att
-    assert not olog[0][2] and sum(1 for x in olog if not x[2]) >= 1
-    assert [x[2] for x in log[:n_att]] == [x[2] for x in olog]
+    assert [x[2] for x in olog] == [False, False, True, True, True, True]
+    assert [bool(x[2]) for x in log[:n_att]] == [x[2] for x in olog]
+    # the no-growth rule: the step after the accepted retry keeps its size
+    assert log[3][1] == log[2][1]
     worst = max(max(abs(a[0] - b[0]) / max(b[0], b[1]), abs(a[1] - b[1]) / b[1])
                 for a, b in zip(log[:n_att], olog))
-    assert worst <= 1e-3, worst
+    assert worst <= 2e-5, worst
 
 
 def test_dp45_replay_first_steps_pointwise():
@@ -345,25 +353,29 @@ def test_dp45_replay_first_steps_pointwise():
 
 def test_dp45_film_replay_and_independent_parity():
     """Full adaptive run with a field step.  Replay mode: the GPU takes the
-    oracle's accepted steps.  Once the controller sits at the stability limit
-    of the stiff exchange modes, rounding-level noise in those modes grows to
-    the tolerance scale in either precision (the oracle's own adaptive run
-    breaks the problem's inversion symmetry by ~7e-4 the same way), so the
-    comparison is made on the film average <m> (the observable of this
-    workload); node values are only held to the tolerance scale.
-    Independent mode: both run their own controllers."""
+    accepted steps of the oracle's run with steps capped at 4e-13 s, inside
+    the stability region of the film's exchange modes (uncapped, the
+    controller first takes steps outside it, where float32 rounding noise
+    grows ~8x per step), compared node by node and through the film average.
+    Independent mode: the GPU's own uncapped run against the oracle's, both
+    with their own controllers; the film average agrees at the tolerance
+    scale."""
     p = _film_problem()
     om, omat, om0 = to_oracle(p)
-    want, olog = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 1e-14, rtol=1e-5, atol=1e-5)
+    want, olog = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 1e-14, rtol=1e-5, atol=1e-5, dt_max=4e-13)
     steps = [(t, dt) for t, dt, ok in olog if ok]
-    assert len(steps) > 5
+    assert len(steps) > 100
     g = _replay(p, steps)
     mean = lambda a: a.mean(axis=(1, 2, 3))
-    assert np.abs(mean(g) - mean(want)).max() <= 1e-6
-    assert np.abs(g - want).max() <= 2e-3
+    free, _ = oracle.dp45_solve(om, omat, om0, 0.0, 0.05e-9, 1e-14, rtol=1e-5, atol=1e-5)
     _, gi, _, clk = _film_dp45(max_steps=1 << 40)
+    print("replay of %d capped steps: <m> %.2e, nodes %.2e; independent <m> %.2e"
+          % (len(steps), np.abs(mean(g) - mean(want)).max(), np.abs(g - want).max(),
+             np.abs(mean(gi) - mean(free)).max()), flush=True)
+    assert np.abs(mean(g) - mean(want)).max() <= 1e-6
+    assert np.abs(g - want).max() <= 1e-5
     assert abs(clk.t - 0.05e-9) <= 1e-22
-    assert np.abs(mean(gi) - mean(want)).max() <= 1e-4
+    assert np.abs(mean(gi) - mean(free)).max() <= 1e-4
 
 
 @pytest.mark.parametrize("name", ["film", "block", "block_dmi"])
