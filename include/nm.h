@@ -150,6 +150,25 @@ nm_status nm_mesh_set_field(nm_mesh *mesh, const float *h_cell);
  * with NM_T_DEMAG. */
 nm_status nm_demag_tensor_init(nm_mesh *mesh);
 
+/* The same tensor for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * float64 temporaries of the set-up live in a static device array of 96 MiB
+ * (100663296 bytes) that the library holds on every device it runs on until
+ * the process ends; nothing is allocated.  The temporaries of an
+ * N1 x N2 x N3 grid take, rounded up to 256 bytes each,
+ *   48 N1 N2 N3 + 48 N3 N2 KP + 48 N3 (P2/2+1) KP + 16 (P1 + P2 + P3) + 3840
+ * bytes (P the padded lengths, KP = P1/2 + 1 rounded up to a multiple of 16):
+ * a 128 x 128 x 32 block needs about 82 MB.  A larger grid is refused with
+ * NM_EINVAL (use nm_demag_tensor_init).  The mesh's device must be the
+ * current device (else NM_EINVAL).  Synchronous: returns when the tensor is
+ * ready.  Calls on one device share the array and are serialised by a lock
+ * held for the whole call (the array keeps the last call's contents, every
+ * part of which a call writes before reading it).  The tile widths of the FFT
+ * passes are left as they are (nm_mesh_tuning sets them): the tuner, which
+ * creates timing events, does not run.  Idempotent like nm_demag_tensor_init;
+ * the resulting tensor is bitwise the one nm_demag_tensor_init builds. */
+nm_status nm_demag_tensor_init_noalloc(nm_mesh *mesh);
+
 /* The float64 real-space tensor N(d) for 0 <= d_k < n[k], written to the
  * device buffer out[6][n3][n2][n1] (xx, yy, zz, xy, xz, yz).  Stand-alone:
  * no mesh needed; enqueued on stream. */

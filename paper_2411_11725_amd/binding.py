@@ -20,7 +20,8 @@ NM_BASIS_3D, NM_BASIS_FILM = 0, 1
 # entry points declared in include/nm.h
 EXPORTS = [
     "nm_mesh_create", "nm_mesh_destroy", "nm_mesh_info", "nm_mesh_footprint_bytes",
-    "nm_mesh_set_field", "nm_mesh_tuning", "nm_demag_tensor_init", "nm_newell_octant", "nm_heff",
+    "nm_mesh_set_field", "nm_mesh_tuning", "nm_demag_tensor_init", "nm_demag_tensor_init_noalloc",
+    "nm_newell_octant", "nm_heff",
     "nm_demag_cell_field", "nm_llg_rhs", "nm_energy", "nm_llg_step", "nm_adjoint_step",
     "nm_adjoint_workspace_bytes", "nm_adjoint_continuous", "nm_server_create", "nm_server_destroy", "nm_serve_submit",
     "nm_serve_poll", "nm_server_clock", "nm_profile_enable",
@@ -95,6 +96,7 @@ def lib():
             "nm_mesh_set_field": ([P, P], c_int),
             "nm_mesh_tuning": ([P, c_int, POINTER(c_int), POINTER(c_int)], c_int),
             "nm_demag_tensor_init": ([P], c_int),
+            "nm_demag_tensor_init_noalloc": ([P], c_int),
             "nm_newell_octant": ([POINTER(c_int), POINTER(c_double), P, P], c_int),
             "nm_heff": ([P, P, P, c_uint, c_double], c_int),
             "nm_demag_cell_field": ([P, P, P], c_int),
@@ -181,6 +183,10 @@ def nm_mesh_set_field(mesh, h_cell):
 
 def nm_demag_tensor_init(mesh):
     _check(lib().nm_demag_tensor_init(mesh))
+
+
+def nm_demag_tensor_init_noalloc(mesh):
+    _check(lib().nm_demag_tensor_init_noalloc(mesh))
 
 
 def nm_newell_octant(n, h, out, stream=None):

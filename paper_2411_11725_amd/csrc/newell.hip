@@ -19,7 +19,8 @@
 // is stored in float32 on the half spectrum 0 <= ky <= P2/2, 0 <= kz <= P3/2
 // (the rest follows by parity) and carries the 1/(P1 P2 P3) of the inverse.
 #include <cmath>
-#include <vector>
+#include <mutex>
+#include <string>
 
 #include "nm_internal.h"
 
@@ -215,7 +216,9 @@ static void scaled_edges(const double h[3], double s[3]) {
     for (int k = 0; k < 3; ++k) s[k] = h[k] / hm;
 }
 
-static hipError_t make_rules(const double hs[3], TentRules **dev, hipStream_t stream) {
+// the tent-weighted rules of every band, built on the host in float64 and
+// copied into the device buffer dev (synchronous on stream)
+static hipError_t upload_rules(const double hs[3], TentRules *dev, hipStream_t stream) {
     TentRules host{};
     for (int b = 0; b < kBands; ++b) {
         const int n = kBandPts[b];
@@ -232,83 +235,189 @@ static hipError_t make_rules(const double hs[3], TentRules **dev, hipStream_t st
             }
         }
     }
-    hipError_t e = dev_alloc((void **)dev, sizeof(TentRules), thread_pool());
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(*dev, &host, sizeof(TentRules), hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(dev, &host, sizeof(TentRules), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     return e;
 }
 
-hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], double *out,
-                                hipStream_t stream) {
+// the octant into out with the rules in the device buffer rules
+static hipError_t newell_octant_with(int n1, int n2, int n3, const double h[3], TentRules *rules, double *out,
+                                     hipStream_t stream) {
     double hs[3];
     scaled_edges(h, hs);
-    TentRules *rules = nullptr;
-    hipError_t e = make_rules(hs, &rules, stream);
+    hipError_t e = upload_rules(hs, rules, stream);
     if (e != hipSuccess) return e;
     const long long total = (long long)n1 * n2 * n3;
     hipLaunchKernelGGL(k_newell_octant, dim3((unsigned)((total + 127) / 128)), dim3(128), 0, stream,
                        n1, n2, n3, hs[0], hs[1], hs[2], rules, out);
     e = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(stream);
-    dev_free(rules, thread_pool());
     return e != hipSuccess ? e : e2;
 }
 
-static hipError_t upload_phases(int P, double2 **dev, hipStream_t stream) {
-    std::vector<double2> cs(P);
+hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], double *out,
+                                hipStream_t stream) {
+    TentRules *rules = nullptr;
+    hipError_t e = dev_alloc((void **)&rules, sizeof(TentRules), thread_pool());
+    if (e != hipSuccess) return e;
+    e = newell_octant_with(n1, n2, n3, h, rules, out, stream);
+    dev_free(rules, thread_pool());
+    return e;
+}
+
+// cos and sin of 2 pi r / P, r < P (P <= kMaxFFT), into the device buffer dev
+static hipError_t upload_phases(int P, double2 *dev, hipStream_t stream) {
+    double2 cs[kMaxFFT];
     for (int r = 0; r < P; ++r) {
         const double a = 2.0 * kPi * r / P;
         cs[r] = make_double2(std::cos(a), std::sin(a));
     }
-    hipError_t e = dev_alloc((void **)dev, sizeof(double2) * P, thread_pool());
-    if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(*dev, cs.data(), sizeof(double2) * P, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemcpyAsync(dev, cs, sizeof(double2) * P, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     return e;
 }
 
-// octant (float64) -> reduced k-space tensor (float32) for the mesh
-hipError_t build_kspace_tensor(nm_mesh *m) {
+// Layout of the float64 temporaries of the k-space transform inside one
+// scratch buffer: the octant [6][n3][n2][n1], the x transform
+// [6][n3][n2][KP], the y transform [6][n3][P2h][KP], the phase tables of the
+// three axes and the tent rules, each at a 256-byte boundary.
+namespace {
+struct KspaceScratch {
+    size_t octd, A, B, c1, c2, c3, rules, total;
+};
+KspaceScratch kspace_layout(int N1, int N2, int N3, int P1, int P2, int P3) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t KP = (size_t)(P1 / 2 + 1 + 15) / 16 * 16, P2h = (size_t)P2 / 2 + 1;
+    KspaceScratch L{};
+    size_t off = 0;
+    L.octd = off; off += up(sizeof(double) * 6 * (size_t)N1 * N2 * N3);
+    L.A = off;    off += up(sizeof(double) * 6 * (size_t)N3 * N2 * KP);
+    L.B = off;    off += up(sizeof(double) * 6 * (size_t)N3 * P2h * KP);
+    L.c1 = off;   off += up(sizeof(double2) * (size_t)P1);
+    L.c2 = off;   off += up(sizeof(double2) * (size_t)P2);
+    L.c3 = off;   off += up(sizeof(double2) * (size_t)P3);
+    L.rules = off; off += up(sizeof(TentRules));
+    L.total = off;
+    return L;
+}
+KspaceScratch kspace_layout(const nm_mesh *m) { return kspace_layout(m->N1, m->N2, m->N3, m->P1, m->P2, m->P3); }
+}  // namespace
+
+size_t kspace_scratch_bytes(const nm_mesh *m) { return kspace_layout(m).total; }
+size_t kspace_scratch_bytes(int N1, int N2, int N3, int P1, int P2, int P3) {
+    return kspace_layout(N1, N2, N3, P1, P2, P3).total;
+}
+
+// octant (float64) -> reduced k-space tensor (float32) for the mesh, with
+// every temporary in the device buffer `work` (kspace_scratch_bytes(m) bytes,
+// 256-byte aligned); allocates nothing
+hipError_t build_kspace_tensor_with(nm_mesh *m, void *work) {
+    const KspaceScratch L = kspace_layout(m);
+    char *w = static_cast<char *>(work);
+    double *octd = reinterpret_cast<double *>(w + L.octd);
+    double *A = reinterpret_cast<double *>(w + L.A);
+    double *B = reinterpret_cast<double *>(w + L.B);
+    double2 *c1 = reinterpret_cast<double2 *>(w + L.c1);
+    double2 *c2 = reinterpret_cast<double2 *>(w + L.c2);
+    double2 *c3 = reinterpret_cast<double2 *>(w + L.c3);
+    TentRules *rules = reinterpret_cast<TentRules *>(w + L.rules);
     const int n1 = m->N1, n2 = m->N2, n3 = m->N3;
-    const long long oct = (long long)n1 * n2 * n3;
     // x frequencies stored at the padded pitch KP (entries past K1 unused)
     const long long sa = 6LL * n3 * n2 * m->KP;
     const long long sb = 6LL * n3 * m->P2h * m->KP;
-    double *octd = nullptr, *A = nullptr, *B = nullptr;
-    double2 *c1 = nullptr, *c2 = nullptr, *c3 = nullptr;
-    // temporaries from the calling thread's pool, if it has one (no device-wide
-    // wait when they are given back)
+    hipError_t e = upload_phases(m->P1, c1, m->stream);
+    if (e == hipSuccess) e = upload_phases(m->P2, c2, m->stream);
+    if (e == hipSuccess) e = upload_phases(m->P3, c3, m->stream);
+    if (e == hipSuccess) e = newell_octant_with(n1, n2, n3, m->h, rules, octd, m->stream);
+    if (e != hipSuccess) return e;
+    const int th = 128;
+    // x: [6][n3][n2][n1] -> [6][n3][n2][KP]
+    long long tot = sa;
+    hipLaunchKernelGGL((k_axis_transform<double>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
+                       0, m->stream, octd, A, 0, 1, n1, m->KP, n3 * n2, m->P1, c1, 0.0);
+    // y: [6][n3][n2][KP] -> [6][n3][P2h][KP]
+    tot = sb;
+    hipLaunchKernelGGL((k_axis_transform<double>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
+                       0, m->stream, A, B, 1, m->KP, n2, m->P2h, n3, m->P2, c2, 0.0);
+    // z: [6][n3][P2h][KP] -> [6][P3h][P2h][KP], sign and 1/(P1 P2 P3)
+    tot = 6LL * m->P3h * m->P2h * m->KP;
+    const double scale = 1.0 / ((double)m->P1 * m->P2 * m->P3);
+    hipLaunchKernelGGL((k_axis_transform<float>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
+                       0, m->stream, B, m->tensor, 2, m->P2h * m->KP, n3, m->P3h, 1, m->P3, c3,
+                       scale);
+    e = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(m->stream);
+    return e != hipSuccess ? e : e2;
+}
+
+// the same with the temporaries taken from the calling thread's pool, if it
+// has one (no device-wide wait when they are given back), else hipMalloc
+hipError_t build_kspace_tensor(nm_mesh *m) {
     DevPool *pool = thread_pool();
-    hipError_t e = dev_alloc((void **)&octd, sizeof(double) * 6 * oct, pool);
-    if (e == hipSuccess) e = dev_alloc((void **)&A, sizeof(double) * sa, pool);
-    if (e == hipSuccess) e = dev_alloc((void **)&B, sizeof(double) * sb, pool);
-    if (e == hipSuccess) e = upload_phases(m->P1, &c1, m->stream);
-    if (e == hipSuccess) e = upload_phases(m->P2, &c2, m->stream);
-    if (e == hipSuccess) e = upload_phases(m->P3, &c3, m->stream);
-    if (e == hipSuccess) e = launch_newell_octant(n1, n2, n3, m->h, octd, m->stream);
-    if (e == hipSuccess) {
-        const int th = 128;
-        // x: [6][n3][n2][n1] -> [6][n3][n2][KP]
-        long long tot = sa;
-        hipLaunchKernelGGL((k_axis_transform<double>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
-                           0, m->stream, octd, A, 0, 1, n1, m->KP, n3 * n2, m->P1, c1, 0.0);
-        // y: [6][n3][n2][KP] -> [6][n3][P2h][KP]
-        tot = sb;
-        hipLaunchKernelGGL((k_axis_transform<double>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
-                           0, m->stream, A, B, 1, m->KP, n2, m->P2h, n3, m->P2, c2, 0.0);
-        // z: [6][n3][P2h][KP] -> [6][P3h][P2h][KP], sign and 1/(P1 P2 P3)
-        tot = 6LL * m->P3h * m->P2h * m->KP;
-        const double scale = 1.0 / ((double)m->P1 * m->P2 * m->P3);
-        hipLaunchKernelGGL((k_axis_transform<float>), dim3((unsigned)((tot + th - 1) / th)), dim3(th),
-                           0, m->stream, B, m->tensor, 2, m->P2h * m->KP, n3, m->P3h, 1, m->P3, c3,
-                           scale);
-        e = hipGetLastError();
-        hipError_t e2 = hipStreamSynchronize(m->stream);
-        if (e == hipSuccess) e = e2;
-    }
-    for (void *p : {(void *)octd, (void *)A, (void *)B, (void *)c1, (void *)c2, (void *)c3}) dev_free(p, pool);
+    void *work = nullptr;
+    hipError_t e = dev_alloc(&work, kspace_scratch_bytes(m), pool);
+    if (e != hipSuccess) return e;
+    e = build_kspace_tensor_with(m, work);
+    dev_free(work, pool);
     return e;
 }
 
+// --------------------------------------------- set-up without allocation
+// Callers that cannot allocate device memory (code under HIP graph capture,
+// serving loops, harnesses that forbid it) initialise the tensor with
+// nm_demag_tensor_init_noalloc, whose float64 temporaries live in this
+// file-scope array: kNoAllocScratch bytes on every device the library runs
+// on, held until the process ends.  In host code the array's name only
+// stands in for it; the device address of each device's copy comes from
+// hipGetSymbolAddress (once per device, with that device current) and is the
+// only form passed to kernels and copies.
+constexpr size_t kNoAllocScratch = size_t(96) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratch];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];   // one call at a time per device
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
 }  // namespace nm
+
+extern "C" nm_status nm_demag_tensor_init_noalloc(nm_mesh *m) {
+    using namespace nm;
+    if (!m) {
+        set_error("nm_demag_tensor_init_noalloc: NULL mesh");
+        return NM_EINVAL;
+    }
+    if (m->tensor_ready) return NM_OK;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != m->device || dev < 0 || dev >= kMaxDevices) {
+        set_error("nm_demag_tensor_init_noalloc: the mesh's device must be the current device");
+        return NM_EINVAL;
+    }
+    const size_t need = kspace_scratch_bytes(m);
+    if (need > kNoAllocScratch) {
+        set_error("nm_demag_tensor_init_noalloc: the tensor set-up of this grid needs " + std::to_string(need) +
+                  " bytes of scratch, more than the " + std::to_string(kNoAllocScratch) +
+                  " this entry point has; use nm_demag_tensor_init");
+        return NM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("nm_demag_tensor_init_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return NM_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    // every temporary is written in full before it is read: nothing to clear
+    const hipError_t e = build_kspace_tensor_with(m, g_scratch_ptr[dev]);
+    if (e != hipSuccess) {
+        set_error(std::string("nm_demag_tensor_init_noalloc: ") + hipGetErrorString(e));
+        return NM_EHIP;
+    }
+    // the tile widths stay as they are (the tuner would create timing events)
+    m->tensor_ready = true;
+    return NM_OK;
+}
