@@ -245,7 +245,7 @@ def serving_bench(B, synth, count, t_end, nmax, max_active, n_streams=4, attempt
                 time.sleep(2e-4)
             tickets.append(B.nm_serve_submit(srv, q, t_end=t_end))
         t_last = t0
-        for tk, nn in zip(tickets, nns):
+        for i, (tk, nn) in enumerate(zip(tickets, nns)):
             m = np.empty(3 * nn, dtype=np.float32)
             r = B.nm_serve_poll(srv, tk, timeout_ms=600000, m_out=m)
             if r is None or r.status != B.NM_OK:
@@ -253,6 +253,8 @@ def serving_bench(B, synth, count, t_end, nmax, max_active, n_streams=4, attempt
             outs_b.append(m)
             lat_b.append(r.t_done - r.t_submit)
             t_last = max(t_last, r.t_done)
+            if (i + 1) % 64 == 0:
+                print("serving: batched %d/%d polled" % (i + 1, count), file=sys.stderr, flush=True)
         wall_b = t_last - t0
         print("serving: batched %d solves in %.2f s" % (count, wall_b), file=sys.stderr, flush=True)
     finally:
@@ -271,6 +273,8 @@ def serving_bench(B, synth, count, t_end, nmax, max_active, n_streams=4, attempt
         B.nm_mesh_destroy(mesh)
         lat_p.append(time.perf_counter() - t0 - ta)
         diff = max(diff, float(np.abs(mp - mb).max()))
+        if len(lat_p) % 64 == 0:
+            print("serving: plain loop %d/%d done" % (len(lat_p), count), file=sys.stderr, flush=True)
     wall_p = time.perf_counter() - t0
     print("serving: plain loop %d solves in %.2f s" % (count, wall_p), file=sys.stderr, flush=True)
     pct = lambda a, q: float(np.percentile(np.asarray(a), q))

@@ -55,10 +55,19 @@ enum {
     NM_T_DEMAG = 2,        /* cuboid-cell FFT demagnetisation, Sec. 3.2 */
     NM_T_ANIS = 4,         /* uniaxial -int Ku (m.e)^2 */
     NM_T_ZEEMAN = 8,       /* -mu0 int Ms m.H_ext */
-    NM_T_DMI = 16,         /* interfacial antisymmetric exchange (interface
-                            * normal z): int D [m_z div m - (m.grad) m_z] */
-    NM_T_ALL = 31
+    NM_T_DMI = 16,         /* antisymmetric exchange (Sec. 2), of the kind
+                            * nm_material.dmi_type names: interfacial
+                            * (normal z) int D [m_z div m - (m.grad) m_z], or
+                            * bulk int D m . curl m */
+    NM_T_CUBIC = 32,       /* cubic anisotropy int Kc (a1^2 a2^2 + a2^2 a3^2 +
+                            * a3^2 a1^2), a_i = m . c_i, by the 2-point Gauss
+                            * rule per axis (Sec. 5.1's quadrature of the
+                            * integrand) */
+    NM_T_ALL = 63
 };
+
+/* Kinds of antisymmetric exchange (nm_material.dmi_type). */
+enum { NM_DMI_INTERFACIAL = 0, NM_DMI_BULK = 1 };
 
 /* Time integrators (Sec. 5.3). */
 enum { NM_RK4 = 1, NM_DP45 = 2 };
@@ -102,7 +111,11 @@ typedef struct {
     float drive_amp[3];       /* drive amplitude (A/m) */
     double drive_freq;        /* Hz */
     double drive_phase;       /* rad */
-    const float *D;           /* optional, J/m^2, interfacial DMI constant */
+    const float *D;           /* optional, J/m^2, DMI constant */
+    int dmi_type;             /* NM_DMI_INTERFACIAL (0) or NM_DMI_BULK */
+    const float *Kc;          /* optional, J/m^3, cubic anisotropy constant; with cubic */
+    const float *cubic;       /* optional, 6*N: cubic axes c1 (3*N) then c2 (3*N),
+                               * orthonormal per cell; c3 = c1 x c2; with Kc */
 } nm_material;
 
 /* Adaptive / fixed stepping parameters. */

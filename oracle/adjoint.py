@@ -21,7 +21,7 @@ Ingredients, written out from the definitions:
 """
 import numpy as np
 
-from .field import ZEEMAN, heff, lumped_mass, nodal_alpha
+from .field import CUBIC, ZEEMAN, heff, lumped_mass, nodal_alpha
 from .mesh import MU0
 
 
@@ -48,6 +48,10 @@ def cell_gather(mesh, mat, v):
 
 def rhs_vjp(mesh, mat, y, t, w, terms, alpha_n=None):
     """(df/dm^T w, dL/dtheta contribution) of f(y, t) for the co-vector w."""
+    if terms & CUBIC and mat.Kc is not None:
+        # the backward field reuses the forward one, which holds for the
+        # quadratic energies only; the quartic cubic term is not covered
+        raise NotImplementedError("the adjoint covers the quadratic energy terms")
     if alpha_n is None:
         alpha_n = nodal_alpha(mesh, mat)
     gp = mat.gamma / (1.0 + alpha_n ** 2)

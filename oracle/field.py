@@ -18,18 +18,24 @@ Energies (J):
   anisotropy E_an = -sum_c Ku_c sum_ab M^e_ab (m_a.e_c)(m_b.e_c)
   Zeeman     E_z  = -mu0 sum_c Ms_c V/8 H_ext,c . sum_a m_{c+a}
   demag      E_d  = -(mu0/2) sum_c V Ms_c mbar_c . H_c
-  DMI        E_dmi = sum_c D_c int_c [m_z div m - (m . grad) m_z]
-             (interfacial antisymmetric exchange with the interface normal
-             along z, integrated exactly with the element matrices
-             G_k[a, b] = int phi_a d_k phi_b, k = x, y)
+  DMI        interfacial (the interface normal along z):
+             E_dmi = sum_c D_c int_c [m_z div m - (m . grad) m_z];
+             bulk: E_dmi = sum_c D_c int_c m . (curl m);
+             both antisymmetric exchange (Sec. 2), integrated exactly with
+             the element matrices G_k[a, b] = int phi_a d_k phi_b
+  cubic      E_c = sum_c Kc_c int_c (a1^2 a2^2 + a2^2 a3^2 + a3^2 a1^2),
+             a_i = m^h . c_i with the cell's cubic axes c1, c2, c3 = c1 x c2;
+             quartic in m, integrated by the 2-point Gauss rule per axis (the
+             form compiler's quadrature of the integrand, Sec. 5.1; the rule
+             that is exact for every quadratic term of the Q1 functions)
 """
 import numpy as np
 
 from .mesh import MU0
 from .newell import newell_octant
 
-EXCHANGE, DEMAG, ANISOTROPY, ZEEMAN, DMI = 1, 2, 4, 8, 16
-ALL_TERMS = 31
+EXCHANGE, DEMAG, ANISOTROPY, ZEEMAN, DMI, CUBIC = 1, 2, 4, 8, 16, 32
+ALL_TERMS = 63
 
 
 # ---------------------------------------------------------------------------
@@ -91,21 +97,55 @@ def _anisotropy_gradient(mesh, mat, m, g):
 
 
 def _dmi_gradient(mesh, mat, m, g):
-    """dE/dm of E = sum_c D_c sum_ab [m_az G_x m_bx - m_ax G_x m_bz
-    + m_az G_y m_by - m_ay G_y m_bz] (G = G_k[a, b]), with
-    A_k = G_k - G_k^T:
+    """dE/dm of the DMI energy, with A_k = G_k - G_k^T.
+
+    Interfacial: E = sum_c D_c sum_ab [m_az G_x m_bx - m_ax G_x m_bz
+    + m_az G_y m_by - m_ay G_y m_bz] (G = G_k[a, b]):
         dE/dm_a,x = -sum_b A_x[a, b] m_b,z,  dE/dm_a,y = -sum_b A_y[a, b] m_b,z,
-        dE/dm_a,z = sum_b (A_x[a, b] m_b,x + A_y[a, b] m_b,y)."""
-    G = mesh.element_dmi()
-    Ax, Ay = G[0] - G[0].T, G[1] - G[1].T
+        dE/dm_a,z = sum_b (A_x[a, b] m_b,x + A_y[a, b] m_b,y).
+    Bulk: E = sum_c D_c sum_ab eps_jkl m_aj G_k[a, b] m_bl:
+        dE/dm_a,j = sum_b eps_jkl A_k[a, b] m_b,l."""
+    G = mesh.element_first_derivative()
+    A = [G[k] - G[k].T for k in range(3)]
     for p, a in enumerate(mesh.corners):
         acc = np.zeros((3,) + mesh.cell_shape)
         for q, b in enumerate(mesh.corners):
             mb = mesh.corner(m, b)
-            acc[0] -= Ax[p, q] * mb[2]
-            acc[1] -= Ay[p, q] * mb[2]
-            acc[2] += Ax[p, q] * mb[0] + Ay[p, q] * mb[1]
+            if mat.dmi_type == "bulk":
+                for j in range(3):
+                    k, l = (j + 1) % 3, (j + 2) % 3
+                    acc[j] += A[k][p, q] * mb[l] - A[l][p, q] * mb[k]
+            else:
+                acc[0] -= A[0][p, q] * mb[2]
+                acc[1] -= A[1][p, q] * mb[2]
+                acc[2] += A[0][p, q] * mb[0] + A[1][p, q] * mb[1]
         mesh.corner(g, a)[...] += mat.D * acc
+
+
+def _cubic_axes(mat):
+    c1, c2 = mat.cubic[0], mat.cubic[1]
+    return c1, c2, np.cross(c1, c2, axis=0)
+
+
+def cubic_density_gradient(mc, axes):
+    """f = a1^2 a2^2 + a2^2 a3^2 + a3^2 a1^2 (a_i = m . c_i) and df/dm
+    = sum_i 2 a_i (a_j^2 + a_k^2) c_i, for (3, ...) arrays."""
+    a = [np.sum(mc * c, axis=0) for c in axes]
+    f = a[0] ** 2 * a[1] ** 2 + a[1] ** 2 * a[2] ** 2 + a[2] ** 2 * a[0] ** 2
+    df = sum(2.0 * a[i] * (a[(i + 1) % 3] ** 2 + a[(i + 2) % 3] ** 2) * axes[i] for i in range(3))
+    return f, df
+
+
+def _cubic_gradient(mesh, mat, m, g):
+    """dE/dm_a = sum_g w_g phi_a(x_g) Kc df/dm(m^h(x_g)) over the 2-point
+    Gauss points of each cell, m^h(x_g) = sum_b phi_b(x_g) m_b."""
+    axes = _cubic_axes(mat)
+    corners = [mesh.corner(m, b) for b in mesh.corners]
+    for w, phi in mesh.gauss_points():
+        mg = sum(phi[q] * corners[q] for q in range(len(corners)))
+        _, df = cubic_density_gradient(mg, axes)
+        for p, a in enumerate(mesh.corners):
+            mesh.corner(g, a)[...] += w * phi[p] * mat.Kc * df
 
 
 def _cell_source_gradient(mesh, mat, Hc, g):
@@ -242,6 +282,8 @@ def gradient(mesh, mat, m, terms=ALL_TERMS, t=0.0, pad=None):
         _anisotropy_gradient(mesh, mat, m, g)
     if terms & DMI and mat.D is not None:
         _dmi_gradient(mesh, mat, m, g)
+    if terms & CUBIC and mat.Kc is not None:
+        _cubic_gradient(mesh, mat, m, g)
     if terms & ZEEMAN:
         _cell_source_gradient(mesh, mat, external_cell_field(mesh, mat, t), g)
     if terms & DEMAG:
@@ -260,7 +302,7 @@ def energies(mesh, mat, m, terms=ALL_TERMS, t=0.0):
     """Energies in J as a dict: exchange, demag, anisotropy, zeeman, total."""
     m = np.asarray(m, dtype=np.float64)
     K, Me = mesh.element_matrices()
-    out = {"exchange": 0.0, "demag": 0.0, "anisotropy": 0.0, "zeeman": 0.0, "dmi": 0.0}
+    out = {"exchange": 0.0, "demag": 0.0, "anisotropy": 0.0, "zeeman": 0.0, "dmi": 0.0, "cubic": 0.0}
     if terms & EXCHANGE:
         e = 0.0
         for p, a in enumerate(mesh.corners):
@@ -284,14 +326,29 @@ def energies(mesh, mat, m, terms=ALL_TERMS, t=0.0):
         mbar = cell_average(mesh, m)
         out["demag"] = -0.5 * MU0 * mesh.V * np.sum(mat.Ms * np.sum(mbar * Hc, axis=0))
     if terms & DMI and mat.D is not None:
-        G = mesh.element_dmi()
+        G = mesh.element_first_derivative()
         e = 0.0
         for p, a in enumerate(mesh.corners):
             ma = mesh.corner(m, a)
             for q, b in enumerate(mesh.corners):
                 mb = mesh.corner(m, b)
-                e += np.sum(mat.D * (G[0, p, q] * (ma[2] * mb[0] - ma[0] * mb[2])
-                                     + G[1, p, q] * (ma[2] * mb[1] - ma[1] * mb[2])))
+                if mat.dmi_type == "bulk":
+                    # eps_jkl m_aj G_k m_bl
+                    e += np.sum(mat.D * sum(G[(j + 1) % 3, p, q] * ma[j] * mb[(j + 2) % 3]
+                                            - G[(j + 2) % 3, p, q] * ma[j] * mb[(j + 1) % 3]
+                                            for j in range(3)))
+                else:
+                    e += np.sum(mat.D * (G[0, p, q] * (ma[2] * mb[0] - ma[0] * mb[2])
+                                         + G[1, p, q] * (ma[2] * mb[1] - ma[1] * mb[2])))
         out["dmi"] = e
-    out["total"] = out["exchange"] + out["demag"] + out["anisotropy"] + out["zeeman"] + out["dmi"]
+    if terms & CUBIC and mat.Kc is not None:
+        axes = _cubic_axes(mat)
+        corners = [mesh.corner(m, b) for b in mesh.corners]
+        e = 0.0
+        for w, phi in mesh.gauss_points():
+            f, _ = cubic_density_gradient(sum(phi[q] * corners[q] for q in range(len(corners))), axes)
+            e += w * np.sum(mat.Kc * f)
+        out["cubic"] = e
+    out["total"] = (out["exchange"] + out["demag"] + out["anisotropy"] + out["zeeman"] + out["dmi"]
+                    + out["cubic"])
     return out

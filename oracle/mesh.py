@@ -118,15 +118,20 @@ class Mesh:
 
     def element_dmi(self):
         """G_k[a, b] = int_cell phi_a d(phi_b)/dx_k for k = x, y (the
-        antisymmetric-exchange element matrices).  Along k the 1D integral of
-        psi_a psi_b' is +-1/2 (the sign of psi_b'), the other axes give the 1D
-        mass factors; under the film basis the z factor is h3."""
+        interfacial antisymmetric-exchange element matrices)."""
+        return self.element_first_derivative()[:2]
+
+    def element_first_derivative(self):
+        """G_k[a, b] = int_cell phi_a d(phi_b)/dx_k for k = x, y, z.  Along k
+        the 1D integral of psi_a psi_b' is +-1/2 (the sign of psi_b'), the
+        other axes give the 1D mass factors; under the film basis the z factor
+        is h3 and the z derivative vanishes."""
         h = self.h
         nc = len(self.corners)
-        G = np.zeros((2, nc, nc))
+        G = np.zeros((3, nc, nc))
         for p, a in enumerate(self.corners):
             for q, b in enumerate(self.corners):
-                for k in range(2):
+                for k in range(3 if self.basis == "3d" else 2):
                     v = 0.5 if b[k] == 1 else -0.5
                     for l in range(3):
                         if l == k:
@@ -139,7 +144,11 @@ class Mesh:
         return G
 
     def element_dmi_quadrature(self):
-        """The same G_k by 2-point Gauss quadrature of the reference functions."""
+        """The same G_k (k = x, y) by 2-point Gauss quadrature of the reference functions."""
+        return self.element_first_derivative_quadrature()[:2]
+
+    def element_first_derivative_quadrature(self):
+        """G_k (k = x, y, z) by 2-point Gauss quadrature of the reference functions."""
         g = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
         w = np.array([0.5, 0.5])
         dims = 3 if self.basis == "3d" else 2
@@ -157,15 +166,30 @@ class Mesh:
                     out *= psi(i[l], x[l])
             return out
         nc = len(self.corners)
-        G = np.zeros((2, nc, nc))
+        G = np.zeros((3, nc, nc))
         for q in product(range(2), repeat=3):
             x = [g[q[0]], g[q[1]], g[q[2]]]
             wt = w[q[0]] * w[q[1]] * w[q[2]] * self.V
             for p, a in enumerate(self.corners):
                 for r, b in enumerate(self.corners):
-                    for k in range(2):
+                    for k in range(dims):
                         G[k, p, r] += wt * phi(a, x) * dphi(b, x, k)
         return G
+
+    def gauss_points(self):
+        """2-point Gauss rule per axis on a cell (Sec. 5.1: the form compiler
+        integrates over the elements by Gauss quadrature): a list of
+        (weight, [phi_a(x_g) for each local vertex a]); the weights sum to V.
+        Under the film basis the functions are constant along z, whose points
+        then coincide in pairs."""
+        g = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
+        dims = 3 if self.basis == "3d" else 2
+        out = []
+        for q in product(range(2), repeat=3):
+            x = [g[q[0]], g[q[1]], g[q[2]]]
+            vals = [np.prod([(x[k] if a[k] else 1.0 - x[k]) for k in range(dims)]) for a in self.corners]
+            out.append((self.V / 8.0, vals))
+        return out
 
     def element_matrices_quadrature(self):
         """Same matrices by explicit 2-point Gauss quadrature (as the paper's form
@@ -234,7 +258,10 @@ class Material:
     drive_amp: np.ndarray = field(default_factory=lambda: np.zeros(3))
     drive_freq: float = 0.0
     drive_phase: float = 0.0
-    D: Optional[np.ndarray] = None      # interfacial DMI constant per cell, J/m^2
+    D: Optional[np.ndarray] = None      # DMI constant per cell, J/m^2
+    dmi_type: str = "interfacial"       # or "bulk"
+    Kc: Optional[np.ndarray] = None     # cubic anisotropy constant K1 per cell, J/m^3
+    cubic: Optional[np.ndarray] = None  # cubic axes c1, c2 per cell, (2, 3, N3, N2, N1); c3 = c1 x c2
 
     def as_f64(self):
         def c(a):
@@ -244,4 +271,5 @@ class Material:
                         h_cell=c(self.h_cell), h_uniform=c(self.h_uniform),
                         drive_mask=c(self.drive_mask), drive_amp=c(self.drive_amp),
                         drive_freq=float(self.drive_freq),
-                        drive_phase=float(self.drive_phase), D=c(self.D))
+                        drive_phase=float(self.drive_phase), D=c(self.D), dmi_type=self.dmi_type,
+                        Kc=c(self.Kc), cubic=c(self.cubic))

@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnm.so")
 
 NM_OK, NM_EINVAL, NM_ENOMEM, NM_EHIP, NM_ENOTREADY = 0, -1, -2, -3, -4
 NM_ENONFINITE, NM_ESTEPSIZE, NM_EBUDGET, NM_EUNSUPPORTED = -5, -6, -7, -8
-NM_T_EXCHANGE, NM_T_DEMAG, NM_T_ANIS, NM_T_ZEEMAN, NM_T_DMI, NM_T_ALL = 1, 2, 4, 8, 16, 31
+NM_T_EXCHANGE, NM_T_DEMAG, NM_T_ANIS, NM_T_ZEEMAN, NM_T_DMI, NM_T_CUBIC, NM_T_ALL = 1, 2, 4, 8, 16, 32, 63
+NM_DMI_INTERFACIAL, NM_DMI_BULK = 0, 1
 NM_RK4, NM_DP45 = 1, 2
 NM_BASIS_3D, NM_BASIS_FILM = 0, 1
 
@@ -39,7 +40,8 @@ class nm_material(ctypes.Structure):
     _fields_ = [("Ms", c_void_p), ("A", c_void_p), ("alpha", c_void_p), ("Ku", c_void_p),
                 ("easy", c_void_p), ("h_cell", c_void_p), ("h_uniform", c_float * 3),
                 ("drive_mask", c_void_p), ("drive_amp", c_float * 3),
-                ("drive_freq", c_double), ("drive_phase", c_double), ("D", c_void_p)]
+                ("drive_freq", c_double), ("drive_phase", c_double), ("D", c_void_p),
+                ("dmi_type", c_int), ("Kc", c_void_p), ("cubic", c_void_p)]
 
 
 class nm_integrator(ctypes.Structure):
@@ -142,13 +144,14 @@ def _stream_handle(stream):
 # ---------------------------------------------------------------- entry points
 def nm_mesh_create(n, h, gamma, Ms, A, alpha, Ku=None, easy=None, h_cell=None,
                    h_uniform=(0.0, 0.0, 0.0), drive_mask=None, drive_amp=(0.0, 0.0, 0.0),
-                   drive_freq=0.0, drive_phase=0.0, stream=None, basis=NM_BASIS_3D, D=None):
+                   drive_freq=0.0, drive_phase=0.0, stream=None, basis=NM_BASIS_3D, D=None,
+                   dmi_type=NM_DMI_INTERFACIAL, Kc=None, cubic=None):
     """Create a mesh from float32 device tensors (copied by the library)."""
     desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), _stream_handle(stream),
                         int(basis))
     mat = nm_material(_ptr(Ms), _ptr(A), _ptr(alpha), _ptr(Ku), _ptr(easy), _ptr(h_cell),
                       (c_float * 3)(*h_uniform), _ptr(drive_mask), (c_float * 3)(*drive_amp),
-                      float(drive_freq), float(drive_phase), _ptr(D))
+                      float(drive_freq), float(drive_phase), _ptr(D), int(dmi_type), _ptr(Kc), _ptr(cubic))
     out = c_void_p()
     _check(lib().nm_mesh_create(ctypes.byref(desc), ctypes.byref(mat), ctypes.byref(out)))
     return out
@@ -311,7 +314,8 @@ def mesh_from_problem(p, device="cuda", stream=None, tensor=True):
     def dev(a):
         return None if a is None else torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
 
-    arrays = {k: dev(p.get(k)) for k in ("Ms", "A", "alpha", "Ku", "easy", "h_cell", "drive_mask", "D")}
+    arrays = {k: dev(p.get(k)) for k in ("Ms", "A", "alpha", "Ku", "easy", "h_cell", "drive_mask", "D", "Kc",
+                                         "cubic")}
     mesh = nm_mesh_create(p["n"], p["h"], p["gamma"], arrays["Ms"], arrays["A"], arrays["alpha"],
                           Ku=arrays["Ku"], easy=arrays["easy"], h_cell=arrays["h_cell"],
                           h_uniform=tuple(float(v) for v in p["h_uniform"]),
@@ -319,7 +323,9 @@ def mesh_from_problem(p, device="cuda", stream=None, tensor=True):
                           drive_amp=tuple(float(v) for v in p["drive_amp"]),
                           drive_freq=p["drive_freq"], drive_phase=p["drive_phase"], stream=stream,
                           basis=NM_BASIS_FILM if p.get("basis", "3d") == "film" else NM_BASIS_3D,
-                          D=arrays["D"])
+                          D=arrays["D"],
+                          dmi_type=NM_DMI_BULK if p.get("dmi_type", "interfacial") == "bulk" else NM_DMI_INTERFACIAL,
+                          Kc=arrays["Kc"], cubic=arrays["cubic"])
     if tensor:
         nm_demag_tensor_init(mesh)
     return mesh

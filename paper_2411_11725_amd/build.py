@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnm.so")
 SOURCES = ["adjoint.hip", "api.hip", "demag.hip", "newell.hip", "pool.hip", "profile.hip", "serve.hip",
-           "stencil.hip"]
+           "stencil.hip", "terms.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -304,6 +304,9 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
                "nm_adjoint_step: NM_T_DEMAG needs nm_demag_tensor_init first");
     NM_REQUIRE(!grad_hcell || (terms & NM_T_ZEEMAN), NM_EINVAL,
                "nm_adjoint_step: a field-map gradient needs NM_T_ZEEMAN");
+    NM_REQUIRE(!((terms & NM_T_CUBIC) && m->has_cubic), NM_EUNSUPPORTED,
+               "nm_adjoint_step: the backward field reuses the forward one, which holds for the quadratic "
+               "terms only (not the quartic cubic anisotropy)");
     const long long nn = m->n_nodes, n3 = 3 * nn;
     float *S = work;                                   // states m_0 .. m_{nsteps-1}
     float *V = work + (long long)nsteps * n3;          // 15 scratch vectors
@@ -454,6 +457,9 @@ extern "C" nm_status nm_adjoint_continuous(nm_mesh *m, float *mag, double t_end,
                "nm_adjoint_continuous: NM_T_DEMAG needs nm_demag_tensor_init first");
     NM_REQUIRE(!grad_hcell || (terms & NM_T_ZEEMAN), NM_EINVAL,
                "nm_adjoint_continuous: a field-map gradient needs NM_T_ZEEMAN");
+    NM_REQUIRE(!((terms & NM_T_CUBIC) && m->has_cubic), NM_EUNSUPPORTED,
+               "nm_adjoint_continuous: the backward field reuses the forward one, which holds for the quadratic "
+               "terms only (not the quartic cubic anisotropy)");
     const long long nn = m->n_nodes, n3 = 3 * nn;
     const dim3 g3((unsigned)((n3 + 255) / 256)), gn((unsigned)((nn + 255) / 256));
     hipStream_t st = m->stream;

@@ -52,6 +52,15 @@ __global__ void k_cell_setup(const float *__restrict__ Ms, const float *__restri
 // Under the film basis the single node layer sits at z = 0: its 4 cells give
 // half the film mass, consistent with the node kernel's gradient there (the
 // field -g/M is the film's).
+// cubic anisotropy per cell, packed for the node kernel: {Kc, c1}, {c2, 0}
+__global__ void k_cubic_pack(const float *__restrict__ Kc, const float *__restrict__ ax,
+                             float4 *__restrict__ out, long long nc) {
+    const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (c >= nc) return;
+    out[2 * c] = make_float4(Kc[c], ax[c], ax[nc + c], ax[2 * nc + c]);
+    out[2 * c + 1] = make_float4(ax[3 * nc + c], ax[4 * nc + c], ax[5 * nc + c], 0.f);
+}
+
 __global__ void k_node_setup(const float *__restrict__ Ms, const float *__restrict__ alpha,
                              const float *__restrict__ wc, float *__restrict__ inv_mass,
                              float *__restrict__ alpha_n, float *__restrict__ gp_n, int N1, int N2,
@@ -136,7 +145,7 @@ static bool sizes_of(const nm_mesh_desc *d, Sizes *s) {
 static size_t footprint(const Sizes &s) {
     size_t b = 0;
     b += sizeof(float) * s.nc * (1 + 1 + 1 + 1 + 3 + 3 + 1 + 1);  // Ms, A2, wc, Ku, easy, h_cell, drive, D
-    b += sizeof(float) * s.nc * (4 + 4);                      // cellP, wstat
+    b += sizeof(float) * s.nc * (4 + 4 + 8);                  // cellP, wstat, cubic
     b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
     b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
     b += sizeof(float) * 4 * s.nc;                              // demag cell field / source
@@ -182,7 +191,7 @@ static void free_mesh(nm_mesh *m) {
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->Dc, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
-                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat};
+                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat, m->cubP};
     for (void *p : ptrs) dev_free(p, m->pool);
     for (int j = 0; j < 7; ++j) dev_free(m->k[j], m->pool);
     host_free(m->ctrl_host, m->pool);
@@ -217,6 +226,10 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     NM_REQUIRE(mat->Ms && mat->A && mat->alpha, NM_EINVAL, "nm_mesh_create: Ms, A and alpha are required");
     NM_REQUIRE((mat->Ku == nullptr) == (mat->easy == nullptr), NM_EINVAL,
                "nm_mesh_create: Ku and easy must be given together");
+    NM_REQUIRE((mat->Kc == nullptr) == (mat->cubic == nullptr), NM_EINVAL,
+               "nm_mesh_create: Kc and cubic must be given together");
+    NM_REQUIRE(mat->dmi_type == NM_DMI_INTERFACIAL || mat->dmi_type == NM_DMI_BULK, NM_EINVAL,
+               "nm_mesh_create: unknown dmi_type");
     NM_REQUIRE(std::isfinite(mat->drive_freq) && std::isfinite(mat->drive_phase), NM_EINVAL,
                "nm_mesh_create: non-finite drive parameters");
 
@@ -249,6 +262,8 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     m->has_hcell = mat->h_cell != nullptr;
     m->has_drive = mat->drive_mask != nullptr;
     m->has_dmi = mat->D != nullptr;
+    m->dmi_bulk = mat->dmi_type == NM_DMI_BULK;
+    m->has_cubic = mat->Kc != nullptr;
     for (int k = 0; k < 3; ++k) {
         m->h_uniform[k] = mat->h_uniform[k];
         m->drive_amp[k] = mat->drive_amp[k];
@@ -256,22 +271,27 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     m->drive_freq = mat->drive_freq;
     m->drive_phase = mat->drive_phase;
 
-    // element matrices by axis-difference pattern (bit k set: a_k != b_k)
-    for (int mask = 0; mask < 8; ++mask) {
-        double mm[3], ss[3];
-        for (int k = 0; k < 3; ++k) {
-            const bool diff = (mask >> k) & 1;
-            mm[k] = d->h[k] * (diff ? 1.0 : 2.0) / 6.0;
-            ss[k] = (diff ? -1.0 : 1.0) / d->h[k];
+    // neighbour weights of the node kernel from the element matrices (terms.hip)
+    {
+        ElementTables T;
+        std::string why;
+        if (!generate_element_tables(d->h, &T, &why)) {
+            delete m;
+            set_error("nm_mesh_create: term generator: " + why);
+            return NM_EINVAL;
         }
-        m->Kp[mask] = (float)(ss[0] * mm[1] * mm[2] + mm[0] * ss[1] * mm[2] + mm[0] * mm[1] * ss[2]);
-        m->Mp[mask] = (float)(mm[0] * mm[1] * mm[2]);
-    }
-    for (int i = 0; i < 4; ++i) {
-        const double my = d->h[1] * ((i & 1) ? 1.0 : 2.0) / 6.0, mx = d->h[0] * ((i & 1) ? 1.0 : 2.0) / 6.0;
-        const double mz = d->h[2] * ((i >> 1) ? 1.0 : 2.0) / 6.0;
-        m->gx[i] = (float)(my * mz);
-        m->gy[i] = (float)(mx * mz);
+        for (int i = 0; i < 8; ++i) {
+            m->Kp[i] = T.Kp[i];
+            m->Mp[i] = T.Mp[i];
+        }
+        for (int i = 0; i < 4; ++i) {
+            m->gx[i] = T.gx[i];
+            m->gy[i] = T.gy[i];
+            m->gz[i] = T.gz[i];
+        }
+        m->gq[0] = T.gq[0];
+        m->gq[1] = T.gq[1];
+        m->gw = T.gw;
     }
 
     m->pool = thread_pool();
@@ -289,6 +309,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess && m->has_anis) e = dalloc(m, &m->easy, 3 * nc);
     if (e == hipSuccess && m->has_drive) e = dalloc(m, &m->drive_mask, nc);
     if (e == hipSuccess && m->has_dmi) e = dalloc(m, &m->Dc, nc);
+    if (e == hipSuccess && m->has_cubic) e = dalloc(m, &m->cubP, 2 * nc);
     if (e == hipSuccess) e = dalloc(m, &m->inv_mass, nn);
     if (e == hipSuccess) e = dalloc(m, &m->alpha_n, nn);
     if (e == hipSuccess) e = dalloc(m, &m->gp_n, nn);
@@ -331,6 +352,9 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
         hipLaunchKernelGGL(k_node_setup, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, m->Ms,
                            m->acc, m->wc, m->inv_mass, m->alpha_n, m->gp_n, m->N1, m->N2, m->N3,
                            m->NZ, m->gamma);
+        if (m->has_cubic)
+            hipLaunchKernelGGL(k_cubic_pack, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, mat->Kc,
+                               mat->cubic, m->cubP, nc);
         e = hipGetLastError();
         if (e == hipSuccess) e = launch_cell_pack(m);
     }

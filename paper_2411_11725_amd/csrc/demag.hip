@@ -50,10 +50,10 @@ __device__ __forceinline__ float2 keep(float2 v, bool ok) {
 // node pairs (z, z + 1) of its RB + 1 node rows into LDS (each node value is
 // read once per block), then each cell adds four of those pair sums.
 template <int L>
-__global__ void __launch_bounds__(256)
-k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
-       const float2 *__restrict__ tw, int N1, int N2, int N3, int NZ, int P2, int KP,
-       const Ctrl *__restrict__ ctrl) {
+__device__ __forceinline__ void xfwd_body(const float *__restrict__ mag, const float *__restrict__ Ms,
+                                          float2 *__restrict__ spec, const float2 *__restrict__ tw, int N1,
+                                          int N2, int N3, int NZ, int P2, int KP, const Ctrl *__restrict__ ctrl,
+                                          int bx, int by) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     constexpr int NR = RB + 1, RL = L + 1;      // node rows; node slots per row (N1 + 1 <= L + 1)
@@ -63,7 +63,7 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     __shared__ float zs[NZI];
     __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
     const int tid = threadIdx.x;
-    const int y0 = blockIdx.x * RB, z = blockIdx.y;
+    const int y0 = bx * RB, z = by;
     const int nrows = min(RB, N2 - y0);
     const int NX = N1 + 1, NY = N2 + 1;
     const unsigned nn = (unsigned)NX * NY * NZ;
@@ -137,19 +137,27 @@ k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__re
     }
 }
 
-// ---------------------------------------------------------------- x inverse
 template <int L>
 __global__ void __launch_bounds__(256)
-k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__restrict__ tw,
-       int N1, int N2, int N3, int P2, int KP, const float *__restrict__ wc,
-       const float4 *__restrict__ wstat, int src_mode, const Ctrl *__restrict__ ctrl) {
+k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
+       const float2 *__restrict__ tw, int N1, int N2, int N3, int NZ, int P2, int KP,
+       const Ctrl *__restrict__ ctrl) {
+    xfwd_body<L>(mag, Ms, spec, tw, N1, N2, N3, NZ, P2, KP, ctrl, blockIdx.x, blockIdx.y);
+}
+
+// ---------------------------------------------------------------- x inverse
+template <int L>
+__device__ __forceinline__ void xinv_body(const float2 *__restrict__ spec, float *__restrict__ hd,
+                                          const float2 *__restrict__ tw, int N1, int N2, int N3, int P2, int KP,
+                                          const float *__restrict__ wc, const float4 *__restrict__ wstat,
+                                          int src_mode, const Ctrl *__restrict__ ctrl, int bx) {
     constexpr int RB = x_rows_per_block(L);
     constexpr int NP = 3 * RB;
     __shared__ float2 s[NP * L];
     __shared__ float2 tl[L + 1];   // exp(-2 pi i k / P1), k <= L
     const int tid = threadIdx.x;
     const int rows = N2 * N3;
-    const int row0 = blockIdx.x * RB;
+    const int row0 = bx * RB;
     const long long nc = (long long)N1 * N2 * N3;
     static_assert((RB * L) % 256 == 0, "whole iterations");
     constexpr int NI = RB * L / 256;
@@ -236,26 +244,34 @@ k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__
     }
 }
 
+template <int L>
+__global__ void __launch_bounds__(256)
+k_xinv(const float2 *__restrict__ spec, float *__restrict__ hd, const float2 *__restrict__ tw,
+       int N1, int N2, int N3, int P2, int KP, const float *__restrict__ wc,
+       const float4 *__restrict__ wstat, int src_mode, const Ctrl *__restrict__ ctrl) {
+    xinv_body<L>(spec, hd, tw, N1, N2, N3, P2, KP, wc, wstat, src_mode, ctrl, blockIdx.x);
+}
+
 // ----------------------------------------- y pass, register FFT form
 // NPB columns per block, T threads per column (fft2 split of L).  Forward:
 // the N2 <= L / 2 data rows in, all L rows out.  Inverse: all L rows in, the
 // N2 data rows out.
 template <int L, int DIR, int SH>
-__global__ void __launch_bounds__(256)
-k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int N2, int K1, int KP,
-          const Ctrl *__restrict__ ctrl) {
+__device__ __forceinline__ void ypass_body(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3,
+                                           int N2, int K1, int KP, const Ctrl *__restrict__ ctrl, int bx,
+                                           int comp) {
     constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
     constexpr int NPB = (256 / TT) >> SH, E = L / TT, NT = NPB * TT;   // 2^-SH of the widest block
     static_assert(NPB >= 1, "block width");
     __shared__ float2 sh[TT > 1 ? L * NPB : 1];
     __shared__ float2 tl[L];
     const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
-    const int col = blockIdx.x * NPB + b;
+    const int col = bx * NPB + b;
     const int zc = col / KP, kx = col - zc * KP;
     const bool valid = col < N3 * KP && kx < K1;
     // 32-bit byte offsets within one component (N3 P2 KP complex < 4 GiB);
     // pad / past-the-end lanes read column 0
-    float2 *cb = spec + (long long)blockIdx.y * N3 * L * KP;
+    float2 *cb = spec + (long long)comp * N3 * L * KP;
     const unsigned oc = valid ? 8u * ((unsigned)zc * (unsigned)(L * KP) + (unsigned)kx) : 0u;
     const unsigned rs = 8u * (unsigned)KP;   // row stride
     float2 v[1][E];
@@ -305,6 +321,13 @@ k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int 
                 if (y < N2) sto(cb, oc + (unsigned)y * rs, v[0][a * L2 + n2]);
             }
     }
+}
+
+template <int L, int DIR, int SH>
+__global__ void __launch_bounds__(256)
+k_ypass_r(float2 *__restrict__ spec, const float2 *__restrict__ tw, int N3, int N2, int K1, int KP,
+          const Ctrl *__restrict__ ctrl) {
+    ypass_body<L, DIR, SH>(spec, tw, N3, N2, K1, KP, ctrl, blockIdx.x, blockIdx.y);
 }
 
 // ------------------------------------------- k-space product of one element
@@ -446,9 +469,9 @@ k_zconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
 // z < L / 2 can hold data (P3 >= 2 N3), so half of the inputs are known zeros
 // and half of the outputs are never stored.
 template <int L, int SH>
-__global__ void __launch_bounds__(256)
-k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
-          int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
+__device__ __forceinline__ void zconv_r_body(float2 *__restrict__ spec, const float *__restrict__ T,
+                                             const float2 *__restrict__ tw, int N3, int P2, int K1, int KP,
+                                             int P2h, int P3h, const Ctrl *__restrict__ ctrl, int lblock) {
     constexpr int L1 = fft2_l1(L), L2 = L / L1, TT = fft2_threads(L);
     constexpr int NPB = (256 / TT) >> SH, E = L / TT, A = L1 / TT, NT = NPB * TT;
     static_assert(NPB >= 1, "block width");
@@ -459,7 +482,7 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
     // columns in mirror order: ky rows 0, 1, P2-1, 2, P2-2, ..., P2/2 (rows ky
     // and P2-ky read the same stored tensor entries), blocks in contiguous
     // ranges per XCD, so a row's mirror finds the tensor in the same L2
-    const int pos = (int)xcd_block(blockIdx.x, gridDim.x) * NPB + b;
+    const int pos = lblock * NPB + b;
     const int slot = pos / KP, kxp = pos - slot * KP;
     const int kyp = slot == 0 ? 0 : slot >= P2 - 1 ? P2 / 2 : (slot & 1) ? (slot + 1) / 2 : P2 - (slot + 1) / 2;
     const int col = kyp * KP + kxp;
@@ -543,11 +566,18 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
         }
 }
 
+template <int L, int SH>
+__global__ void __launch_bounds__(256)
+k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
+          int N3, int P2, int K1, int KP, int P2h, int P3h, const Ctrl *__restrict__ ctrl) {
+    zconv_r_body<L, SH>(spec, T, tw, N3, P2, K1, KP, P2h, P3h, ctrl, (int)xcd_block(blockIdx.x, gridDim.x));
+}
+
 // ------------------------------------ y forward + product + y inverse (N3 = 1)
 template <int L, int TB>
-__global__ void __launch_bounds__(256)
-k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
-        int N2, int K1, int KP, int P2h, const Ctrl *__restrict__ ctrl) {
+__device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const float *__restrict__ T,
+                                           const float2 *__restrict__ tw, int N2, int K1, int KP, int P2h,
+                                           const Ctrl *__restrict__ ctrl, int lblock) {
     constexpr int NP = 3 * TB;
     __shared__ float2 s[(L + 1) * NP];   // + one spare row for masked lanes
     __shared__ float2 tl[L / 2 + 1];
@@ -555,7 +585,7 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
     const long long cstride = (long long)L * KP;
     // neighbouring column tiles on one XCD: a tile is narrower than a cache
     // line, and the tiles next to it read the rest of each line from L2
-    const int col0 = (int)xcd_block(blockIdx.x, gridDim.x) * TB;
+    const int col0 = lblock * TB;
     static_assert((L * NP) % 256 == 0, "whole iterations");
     constexpr int NI = L * NP / 256;
     float2 v[NI];
@@ -615,6 +645,13 @@ k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__
         const int col = col0 + b;
         if (col < K1) spec[c * cstride + (long long)e * KP + col] = s[e * NP + p];
     }
+}
+
+template <int L, int TB>
+__global__ void __launch_bounds__(256)
+k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
+        int N2, int K1, int KP, int P2h, const Ctrl *__restrict__ ctrl) {
+    yconv_body<L, TB>(spec, T, tw, N2, K1, KP, P2h, ctrl, (int)xcd_block(blockIdx.x, gridDim.x));
 }
 
 // --------------------------------------------------------------- dispatch
@@ -833,6 +870,137 @@ hipError_t tune_passes(nm_mesh *m) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = {best_y, best_z};
     return hipSuccess;
+}
+
+// ------------------------------------------------------ batched launches
+// One launch per pass covers every slot of a batch group (grid z = slot);
+// grids cover the largest mesh of the class, and blocks past a slot's own
+// rows or columns return before any work.  Each block runs the single-mesh
+// kernel's code on its slot's buffers, so results do not depend on the group.
+template <int L>
+__global__ void __launch_bounds__(256) k_xfwd_b(const BatchSlot *__restrict__ slots, int stage,
+                                                const float2 *__restrict__ tw) {
+    const BatchSlot &d = slots[blockIdx.z];
+    constexpr int RB = x_rows_per_block(L);
+    if (!d.active || (int)blockIdx.x * RB >= d.N2 || (int)blockIdx.y >= d.N3) return;
+    xfwd_body<L>(d.stage_in[stage], d.Ms, d.spec, tw, d.N1, d.N2, d.N3, d.NZ, d.P2, d.KP, d.ctrl, blockIdx.x,
+                 blockIdx.y);
+}
+template <int L>
+__global__ void __launch_bounds__(256) k_xinv_b(const BatchSlot *__restrict__ slots, const float2 *__restrict__ tw) {
+    const BatchSlot &d = slots[blockIdx.z];
+    constexpr int RB = x_rows_per_block(L);
+    if (!d.active || (int)blockIdx.x * RB >= d.N2 * d.N3) return;
+    xinv_body<L>(d.spec, d.hd, tw, d.N1, d.N2, d.N3, d.P2, d.KP, d.wc, d.wstat, d.src_mode, d.ctrl, blockIdx.x);
+}
+template <int L, int DIR, int SH>
+__global__ void __launch_bounds__(256) k_ypass_b(const BatchSlot *__restrict__ slots, const float2 *__restrict__ tw) {
+    const BatchSlot &d = slots[blockIdx.z];
+    constexpr int NPB = (256 / fft2_threads(L)) >> SH;
+    if (!d.active || (int)blockIdx.x * NPB >= d.N3 * d.KP) return;
+    ypass_body<L, DIR, SH>(d.spec, tw, d.N3, d.N2, d.K1, d.KP, d.ctrl, blockIdx.x, blockIdx.y);
+}
+template <int L, int SH>
+__global__ void __launch_bounds__(256) k_zconv_b(const BatchSlot *__restrict__ slots, const float2 *__restrict__ tw) {
+    const BatchSlot &d = slots[blockIdx.z];
+    if (!d.active) return;
+    zconv_r_body<L, SH>(d.spec, d.tensor, tw, d.N3, d.P2, d.K1, d.KP, d.P2h, d.P3h, d.ctrl,
+                        (int)xcd_block(blockIdx.x, gridDim.x));
+}
+template <int L, int TB>
+__global__ void __launch_bounds__(256) k_yconv_b(const BatchSlot *__restrict__ slots, const float2 *__restrict__ tw) {
+    const BatchSlot &d = slots[blockIdx.z];
+    if (!d.active) return;
+    yconv_body<L, TB>(d.spec, d.tensor, tw, d.N2, d.K1, d.KP, d.P2h, d.ctrl, (int)xcd_block(blockIdx.x, gridDim.x));
+}
+namespace {
+struct BatchLaunch {
+    const BatchClass &bc;
+    const BatchSlot *slots;
+    int cap, stage;
+    hipStream_t st;
+    const float2 *tw;
+    int KP() const { return ((bc.P1 / 2 + 1) + 15) / 16 * 16; }
+};
+
+template <int L>
+void launch_xfwd_bt(const BatchLaunch &b) {
+    constexpr int RB = x_rows_per_block(L);
+    const int n2max = b.bc.P2 > 1 ? b.bc.P2 / 2 : 1;
+    hipLaunchKernelGGL((k_xfwd_b<L>), dim3((n2max + RB - 1) / RB, b.bc.maxN3, b.cap), dim3(256), 0, b.st, b.slots,
+                       b.stage, b.tw);
+}
+template <int L>
+void launch_xinv_bt(const BatchLaunch &b) {
+    constexpr int RB = x_rows_per_block(L);
+    const int rows = (b.bc.P2 > 1 ? b.bc.P2 / 2 : 1) * b.bc.maxN3;
+    hipLaunchKernelGGL((k_xinv_b<L>), dim3((rows + RB - 1) / RB, 1, b.cap), dim3(256), 0, b.st, b.slots, b.tw);
+}
+template <int L, int DIR, int SH>
+void launch_ypass_bsh(const BatchLaunch &b) {
+    constexpr int TT = fft2_threads(L), NPB = (256 / TT) >> SH;
+    const int ncols = b.bc.maxN3 * b.KP();
+    hipLaunchKernelGGL((k_ypass_b<L, DIR, SH>), dim3((ncols + NPB - 1) / NPB, 3, b.cap), dim3(NPB * TT), 0, b.st,
+                       b.slots, b.tw);
+}
+template <int L, int DIR>
+void launch_ypass_bt(const BatchLaunch &b) {
+    switch (b.bc.tune_y) {
+        case 1: if constexpr ((256 / fft2_threads(L)) >= 2) { launch_ypass_bsh<L, DIR, 1>(b); return; } break;
+        case 2: if constexpr ((256 / fft2_threads(L)) >= 4) { launch_ypass_bsh<L, DIR, 2>(b); return; } break;
+        default: break;
+    }
+    launch_ypass_bsh<L, DIR, 0>(b);
+}
+template <int L>
+void launch_yfwd_bt(const BatchLaunch &b) { launch_ypass_bt<L, -1>(b); }
+template <int L>
+void launch_yinv_bt(const BatchLaunch &b) { launch_ypass_bt<L, 1>(b); }
+template <int L, int SH>
+void launch_zconv_bsh(const BatchLaunch &b) {
+    constexpr int TT = fft2_threads(L), NPB = (256 / TT) >> SH;
+    const int ncols = b.bc.P2 * b.KP();
+    hipLaunchKernelGGL((k_zconv_b<L, SH>), dim3((ncols + NPB - 1) / NPB, 1, b.cap), dim3(NPB * TT), 0, b.st,
+                       b.slots, b.tw);
+}
+template <int L>
+void launch_zconv_bt(const BatchLaunch &b) {
+    if constexpr (L <= 256) {
+        switch (b.bc.tune_z) {
+            case 1: if constexpr ((256 / fft2_threads(L)) >= 2) { launch_zconv_bsh<L, 1>(b); return; } break;
+            case 2: if constexpr ((256 / fft2_threads(L)) >= 4) { launch_zconv_bsh<L, 2>(b); return; } break;
+            default: break;
+        }
+        launch_zconv_bsh<L, 0>(b);
+    }
+}
+template <int L>
+void launch_yconv_bt(const BatchLaunch &b) {
+    constexpr int TB = tb_triple(L);
+    const int K1 = b.bc.P1 / 2 + 1;
+    hipLaunchKernelGGL((k_yconv_b<L, TB>), dim3((K1 + TB - 1) / TB, 1, b.cap), dim3(256), 0, b.st, b.slots, b.tw);
+}
+}  // namespace
+
+hipError_t launch_batch_demag(const BatchClass &bc, const BatchSlot *slots, int cap, int stage, hipStream_t st) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const float2 *tw = twiddles(dev);
+    if (!tw) return hipErrorOutOfMemory;
+    if (bc.P3 > 256) return hipErrorInvalidValue;   // the register z convolution only
+    const BatchLaunch b{bc, slots, cap, stage, st, tw};
+    const int L1 = bc.P1 / 2;
+    NM_DISPATCH_ROW(L1, launch_xfwd_bt, b);
+    if (bc.P3 > 1) {
+        NM_DISPATCH_COL(bc.P2, launch_yfwd_bt, b);
+        NM_DISPATCH_COL(bc.P3, launch_zconv_bt, b);
+        NM_DISPATCH_COL(bc.P2, launch_yinv_bt, b);
+    } else {
+        NM_DISPATCH_COL(bc.P2, launch_yconv_bt, b);
+    }
+    NM_DISPATCH_ROW(L1, launch_xinv_bt, b);
+    return hipGetLastError();
 }
 
 hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode) {

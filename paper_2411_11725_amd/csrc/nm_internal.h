@@ -36,7 +36,89 @@ struct ErrPartial {
     int nonfinite;
 };
 
+// Arguments of the fused node kernel (mesh constants) and of one of its
+// stages (buffers, clock).
+struct StencilParams {
+    int N1, N2, N3, NX, NY, NZ;
+    long long nn, nc;
+    float Kp[8], Mp[8];
+    // node kernel: packed cell data and the pre-weighted cell-field source
+    const float4 *cellP;           // {2A with the sign bit of Ku, sqrt|Ku| e}
+    // {mu0 Ms V/8 (H_d [+ static H_ext]), mu0 Ms V/8 drive mask} per cell, or NULL
+    const float4 *src;
+    int drive;                     // add the drive (the w component times sin and its amplitude)
+    int W;                         // LDS window length per z offset: 256 + 2 NX + 2
+    int faces;                     // K^e couples face neighbours (cells are not cubes)
+    unsigned zcols;                // node kernel: 256-node ranges per node layer
+    const float *Dc;               // DMI constant per cell, or NULL
+    int dmi_bulk;                  // bulk (m . curl m) rather than interfacial DMI
+    float gx[4], gy[4], gz[4];     // DMI weights (see the node kernel)
+    const float4 *cubP;            // cubic anisotropy per cell {Kc, c1}, {c2, 0}, or NULL
+    float gq[2], gw;               // Gauss-point basis values and weight
+    float rNX, rNY;                // 1 / NX, 1 / NY
+    // energy kernel: raw cell data
+    const float *wc, *A2, *Ku, *easy, *hcell, *dmask, *hd;
+    float hu[3], damp[3];
+    double dfreq, dphase;
+    const float *inv_mass, *alpha_n, *gp_n;
+    unsigned terms;
+};
+
+struct StageArgs {
+    const float *in;
+    float *out, *y_next, *mstate, *acc;
+    float *k[7];
+    const Ctrl *ctrl;
+    ErrPartial *partials;
+    double t0, dt0;
+};
+
+// One solve of a batched launch: everything the batched kernels read about
+// it, in device memory (one descriptor per slot of a batch group).  Slots
+// with active = 0 are empty: every batched kernel returns at once there.
+struct BatchSlot {
+    int active;
+    // demag passes
+    int N1, N2, N3, NZ, P2, K1, KP, P2h, P3h, src_mode;
+    const float *Ms;
+    float2 *spec;
+    const float *tensor;
+    float *hd;
+    const float *wc;
+    const float4 *wstat;
+    const float *stage_in[8];    // input of DP45 stage s (2..7)
+    // controller and stage epilogue
+    Ctrl *ctrl;
+    ErrPartial *partials;
+    int np;                      // node-kernel blocks = error partials
+    float *mstate, *y0, *y1, *k1, *k7;
+    long long n3;                // 3 n_nodes
+    // node kernel
+    StencilParams P;
+    StageArgs S[8];              // DP45 stages 2..7
+};
+
+// Shape class of a batch group: solves with equal padded lengths, node
+// window, basis and terms run the same kernel instantiations; grids cover the
+// largest mesh of the class, blocks beyond a solve's own range return.
+struct BatchClass {
+    int P1, P2, P3, nit;
+    unsigned terms;
+    int tune_y, tune_z;          // column-tile widths of the register FFT passes
+    int maxN3;                   // N3 <= P3 / 2 (1 for single-layer grids)
+    unsigned node_blocks;        // node-kernel blocks of the largest mesh
+};
+
 struct ProfState;  // per-kernel event timing (measurement only)
+
+// Neighbour-weight tables of the node kernel, generated from the element
+// matrices of the quadratic terms (terms.hip).
+struct ElementTables {
+    float Kp[8], Mp[8];      // stiffness and mass by axis-difference pattern
+    float gx[4], gy[4], gz[4];   // antisymmetric first-derivative parts per axis
+    float gq[2], gw;         // psi_1 at the two Gauss points; weight of a point
+};
+bool generate_element_tables(const double h[3], ElementTables *out, std::string *why);
 
 // Element access by 32-bit byte offset from a uniform base pointer: the loads
 // and stores then take the scalar-base form with one 32-bit offset register.
@@ -100,7 +182,11 @@ struct nm_mesh {
     // DMI: the antisymmetric part of int phi_a d_k phi_b between nodes that
     // differ by d is d_k gx[(d_y != 0) + 2 (d_z != 0)] (k = x) and
     // d_y gy[(d_x != 0) + 2 (d_z != 0)] (k = y): products of 1D mass factors
-    float gx[4], gy[4];
+    float gx[4], gy[4], gz[4];
+    bool dmi_bulk;           // bulk DMI (m . curl m) instead of interfacial
+    bool has_cubic;
+    float4 *cubP;            // per cell: {Kc, c1}, {c2, 0} (cubic anisotropy)
+    float gq[2], gw;         // 1D basis value psi_1 at the two Gauss points; point weight V / 8
 
     // nodal coefficients
     float *inv_mass, *alpha_n, *gp_n;
@@ -187,6 +273,7 @@ hipError_t launch_newell_octant(int n1, int n2, int n3, const double h[3], doubl
                                 hipStream_t s);
 hipError_t build_kspace_tensor(nm_mesh *m);
 size_t kspace_scratch_bytes(const nm_mesh *m);          // float64 temporaries of the set-up
+size_t kspace_scratch_bytes(int N1, int N2, int N3, int P1, int P2, int P3);
 hipError_t build_kspace_tensor_with(nm_mesh *m, void *work);   // temporaries in work; no allocation
 
 // stencil / LLG / stage kernels
@@ -206,6 +293,14 @@ struct StageSpec {
 };
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp);
+
+// batched launches over the cap slots of a group (grid z = slot)
+int window_items(int NX, int NZ);          // node-kernel LDS window items (0: direct loads)
+void batch_slot_fill(const nm_mesh *m, unsigned terms, Ctrl *ctrl, float *mstate, BatchSlot *out);
+hipError_t launch_batch_demag(const BatchClass &bc, const BatchSlot *slots, int cap, int stage, hipStream_t st);
+hipError_t launch_batch_node(const BatchClass &bc, const BatchSlot *slots, int cap, int stage, hipStream_t st);
+hipError_t launch_batch_control(const BatchSlot *slots, int cap, hipStream_t st);
+hipError_t launch_batch_finish(const BatchClass &bc, const BatchSlot *slots, int cap, hipStream_t st);
 dim3 stencil_grid(const nm_mesh *m);   // blocks of the fused node kernel
 hipError_t launch_energy(nm_mesh *m, const float *mag, unsigned terms, double t, double e[6]);
 hipError_t launch_dp45_control(nm_mesh *m);

@@ -2,17 +2,25 @@
 //
 // Requests (host memory, copied at submission) wait in a FIFO queue.  A
 // scheduler thread admits them while the device memory of the admitted
-// solves stays within the budget and fewer than max_active run; every
-// admitted solve keeps its state resident on the device and advances by
-// replays of its own captured Dormand-Prince graph (attempts_per_launch
-// attempts each) on one stream of a pool, so the work of many solves is in
-// flight on the GPU at once.  Solves progress independently: a replay is
-// re-issued as soon as the previous one has finished, finished solves leave
-// and waiting requests join between replays.  Device memory of the solves
-// comes from a pool (pool.hip): a finished solve gives its buffers back
-// without hipFree, which would wait for the whole device.  Every solve runs
-// the same kernels on its own buffers, so its result does not depend on what
-// else is in the mix.
+// solves (plus the transient tensor set-up of the one being admitted) stays
+// within the budget and fewer than max_active run.  Every admitted solve keeps
+// its state resident on the device and joins a batch group: solves of one
+// shape class (equal padded FFT lengths, node-kernel window and terms) share
+// the kernel instantiations, and a group's captured graph advances all of its
+// members together, one launch per pass and stage for the whole group.  The
+// members' descriptors (buffers, sizes, controller) live in device memory and
+// each member keeps its own controller (t, dt, accept), so members finish
+// independently; finished solves leave and waiting requests join between
+// replays, and the graph is captured once per group, not per member.  Groups
+// of different classes replay concurrently on a pool of streams.
+//
+// A group's slot count is its batch shape, chosen per class by timing the
+// batched stage kernels on the class's first member with 1, 2, 4, 8 and 16
+// slots (cached per class and device); the FFT column tiles come from the
+// per-mesh tuner.  Every member runs the single-mesh kernels' code on its own
+// buffers, so its result does not depend on what else is in the group.
+// Device memory of the solves comes from a pool (pool.hip): a finished solve
+// gives its buffers back without hipFree, which would wait for the device.
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -22,6 +30,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "nm_internal.h"
@@ -36,23 +45,60 @@ double now_s() {
     return std::chrono::duration<double>(clk::now() - t0).count();
 }
 
+int pad_len(int n) {
+    if (n <= 1) return 1;
+    int p = 1;
+    while (p < 2 * n - 1) p <<= 1;
+    return p;
+}
+
+struct Group;
+
 struct Solve {
     uint64_t ticket = 0;
     nm_solve_request req{};
     std::vector<float> Ms, A, alpha, m0;
-    size_t footprint = 0;
+    size_t footprint = 0, setup = 0;
     long long nn = 0, nc = 0;
     nm_mesh *mesh = nullptr;
     float *m_dev = nullptr;
     float *par_dev = nullptr;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    int batch = 16;
-    int next = 16;           // attempts in the next replay (fewer near the end)
-    bool inflight = false;
-    nm_clock clk{};
+    Group *group = nullptr;
+    int slot = -1;
     nm_solve_result res{};
     std::vector<float> m_out;
+};
+
+// class key: padded lengths and terms.  The node kernel's LDS window is sized
+// for the longest rows of the class; a longer window holds the same values
+// at the same places, so a member's result does not depend on it.
+using ClassKey = std::tuple<int, int, int, unsigned>;
+
+ClassKey class_of(const nm_solve_request &r) {
+    return ClassKey{pad_len(r.n[0]), pad_len(r.n[1]), pad_len(r.n[2]), r.terms};
+}
+
+enum SlotState { kFree = 0, kJoining = 1, kRunning = 2 };
+
+struct Group {
+    ClassKey key;
+    BatchClass bc{};
+    int cap = 0;
+    hipStream_t stream = nullptr;
+    BatchSlot *slots_dev = nullptr;   // cap descriptors read by the graph
+    BatchSlot *slots_pin = nullptr;   // pinned staging of the descriptors
+    std::vector<BatchSlot> next;      // descriptors for the next replay
+    Ctrl *ctrl_dev = nullptr;         // cap controllers
+    Ctrl *ctrl_pin = nullptr;         // pinned read-back of the controllers
+    std::vector<Solve *> member;
+    std::vector<int> state;
+    // graphs over the first 1, 2, 4, ... slots: a replay covers the lowest
+    // power of two of slots that holds every member (new members take the
+    // lowest free slot), so a group that is far from full does not dispatch
+    // the blocks of its empty slots
+    hipGraphExec_t gexec[5] = {};
+    hipEvent_t ev = nullptr;          // end of the last replay and read-back
+    bool inflight = false, dirty = false, wait_admit = false;
 };
 
 }  // namespace
@@ -62,12 +108,15 @@ struct nm_server {
     size_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;
     int next_stream = 0;
+    hipStream_t admit_stream = nullptr;
+    hipEvent_t admit_ev = nullptr;    // end of the last admission set-up
     int device = 0;
     DevPool *pool = nullptr;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Solve *> pending;
-    std::vector<Solve *> active;
+    int n_active = 0;
+    std::vector<Group *> groups;
     std::map<uint64_t, Solve *> done;
     std::map<uint64_t, int> known;  // ticket -> 0 pending / 1 active / 2 done
     uint64_t next_ticket = 1;
@@ -76,6 +125,11 @@ struct nm_server {
 };
 
 namespace {
+
+// batch shape per class and device, chosen by timing (see tune_cap)
+std::mutex g_cap_mu;
+std::map<std::tuple<ClassKey, int>, int> g_cap;
+constexpr int kMaxCap = 16;
 
 size_t solve_footprint(const nm_solve_request &r) {
     nm_mesh_desc d{};
@@ -91,44 +145,170 @@ size_t solve_footprint(const nm_solve_request &r) {
     return base + sizeof(float) * (3 * nn + 3 * nc);   // state + staged parameters
 }
 
+// device bytes the tensor set-up of a request takes while it runs (float64
+// temporaries, given back to the pool at its end)
+size_t solve_setup(const nm_solve_request &r) {
+    return kspace_scratch_bytes(r.n[0], r.n[1], r.n[2], pad_len(r.n[0]), pad_len(r.n[1]), pad_len(r.n[2]));
+}
+
 // give back the resources of a solve whose stream work has completed
 void release(Solve *s, DevPool *pool) {
     if (s->mesh) mesh_release(s->mesh);
     dev_free(s->m_dev, pool);
     dev_free(s->par_dev, pool);
-    if (s->ev) (void)hipEventDestroy(s->ev);
     s->mesh = nullptr;
     s->m_dev = s->par_dev = nullptr;
-    s->ev = nullptr;
 }
 
-void fail(nm_server *S, Solve *s, int status) {
-    if (s->stream) (void)hipStreamSynchronize(s->stream);   // rare path: drain before reuse
+void finish(nm_server *S, Solve *s, int status, bool counted) {
     release(s, S->pool);
     s->res.status = status;
     s->res.t_done = now_s();
     std::lock_guard<std::mutex> lk(S->mu);
+    if (counted) {
+        S->used -= s->footprint;
+        S->n_active -= 1;
+    }
     S->done[s->ticket] = s;
     S->known[s->ticket] = 2;
     S->cv_done.notify_all();
 }
 
-// upload, create the mesh and its tensor, start the integrator; on the solve's stream
+void group_destroy(Group *g, DevPool *pool) {
+    for (hipGraphExec_t x : g->gexec)
+        if (x) (void)hipGraphExecDestroy(x);
+    if (g->ev) (void)hipEventDestroy(g->ev);
+    dev_free(g->slots_dev, pool);
+    dev_free(g->ctrl_dev, pool);
+    if (g->slots_pin) (void)hipHostFree(g->slots_pin);
+    if (g->ctrl_pin) (void)hipHostFree(g->ctrl_pin);
+    delete g;
+}
+
+// one replay's kernels: attempts DP45 attempts of the first `slots` slots
+hipError_t enqueue_attempts(const Group *g, int slots, int attempts, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < attempts && e == hipSuccess; ++a) {
+        for (int s = 2; s <= 7 && e == hipSuccess; ++s) {
+            if (g->bc.terms & NM_T_DEMAG) e = launch_batch_demag(g->bc, g->slots_dev, slots, s, st);
+            if (e == hipSuccess) e = launch_batch_node(g->bc, g->slots_dev, slots, s, st);
+        }
+        if (e == hipSuccess) e = launch_batch_control(g->slots_dev, slots, st);
+        if (e == hipSuccess) e = launch_batch_finish(g->bc, g->slots_dev, slots, st);
+    }
+    return e;
+}
+
+// Batch shape of a class: the stage-2 kernels (demag passes and the node
+// kernel) on 1, 2, 4, 8 and 16 slots that all describe the class's first
+// member, timed on the group's stream; the slot count with the least time
+// per slot wins unless a smaller count is within 10% of it (fewer slots:
+// members wait less for each other).  Stage 2 writes only the first
+// member's stage buffers and FFT workspace, which its first real attempt
+// rewrites before reading.
+int tune_cap(nm_server *S, Group *g, const BatchSlot &first) {
+    const auto ck = std::make_tuple(g->key, S->device);
+    {
+        std::lock_guard<std::mutex> lk(g_cap_mu);
+        auto it = g_cap.find(ck);
+        if (it != g_cap.end()) return it->second;
+    }
+    for (int i = 0; i < kMaxCap; ++i) g->slots_pin[i] = first;
+    hipError_t e = hipMemcpyAsync(g->slots_dev, g->slots_pin, sizeof(BatchSlot) * kMaxCap, hipMemcpyHostToDevice,
+                                  g->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    float per[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    auto stage2 = [&](int c) -> hipError_t {
+        hipError_t r = hipSuccess;
+        if (g->bc.terms & NM_T_DEMAG) r = launch_batch_demag(g->bc, g->slots_dev, c, 2, g->stream);
+        if (r == hipSuccess) r = launch_batch_node(g->bc, g->slots_dev, c, 2, g->stream);
+        return r;
+    };
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        const int c = 1 << k;
+        float best = 1e30f;
+        e = stage2(c);   // warm-up
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, g->stream);
+            for (int q = 0; q < 4 && e == hipSuccess; ++q) e = stage2(c);
+            if (e == hipSuccess) e = hipEventRecord(e1, g->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            best = std::fmin(best, ms);
+        }
+        per[k] = best / (float)c;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    int cap = 1;
+    if (e == hipSuccess) {
+        int bk = 0;
+        for (int k = 1; k < 5; ++k)
+            if (per[k] < per[bk]) bk = k;
+        int k = 0;
+        while (k < bk && per[k] > 1.1f * per[bk]) ++k;
+        cap = 1 << k;
+    }
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(g_cap_mu);
+    g_cap[ck] = cap;
+    return cap;
+}
+
+// create the group of a class on the first admitted member (its descriptor
+// is used to time the batch shapes)
+Group *group_create(nm_server *S, const ClassKey &key, const Solve *first, const BatchSlot &desc) {
+    Group *g = new Group();
+    g->key = key;
+    g->bc.P1 = std::get<0>(key);
+    g->bc.P2 = std::get<1>(key);
+    g->bc.P3 = std::get<2>(key);
+    g->bc.terms = std::get<3>(key);
+    g->bc.tune_y = first->mesh->tune_y;
+    g->bc.tune_z = first->mesh->tune_z;
+    g->bc.maxN3 = g->bc.P3 > 1 ? g->bc.P3 / 2 : 1;
+    // the window of the class's longest rows (N1 <= P1 / 2, N3 <= P3 / 2)
+    g->bc.nit = window_items(g->bc.P1 / 2 + 1, g->bc.maxN3 + 1);
+    const long long nmax = (long long)(g->bc.P1 / 2 + 1) * (g->bc.P2 / 2 + 1) * (g->bc.maxN3 + 1);
+    g->bc.node_blocks = (unsigned)((nmax + 255) / 256);
+    g->stream = S->streams[S->next_stream++ % S->streams.size()];
+    bool ok = dev_alloc((void **)&g->slots_dev, sizeof(BatchSlot) * kMaxCap, S->pool) == hipSuccess &&
+              dev_alloc((void **)&g->ctrl_dev, sizeof(Ctrl) * kMaxCap, S->pool) == hipSuccess &&
+              hipHostMalloc((void **)&g->slots_pin, sizeof(BatchSlot) * kMaxCap, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc((void **)&g->ctrl_pin, sizeof(Ctrl) * kMaxCap, hipHostMallocDefault) == hipSuccess &&
+              hipEventCreateWithFlags(&g->ev, hipEventDisableTiming) == hipSuccess;
+    // the timing runs after the member's set-up
+    ok = ok && hipStreamWaitEvent(g->stream, S->admit_ev, 0) == hipSuccess;
+    if (!ok) {
+        group_destroy(g, S->pool);
+        return nullptr;
+    }
+    g->cap = tune_cap(S, g, desc);
+    BatchSlot empty{};
+    g->next.assign(g->cap, empty);
+    g->member.assign(g->cap, nullptr);
+    g->state.assign(g->cap, kFree);
+    return g;
+}
+
+// upload, create the mesh and its tensor, start the integrator (first
+// stage, on the admission stream) and place the solve in a group slot
 bool admit(nm_server *S, Solve *s) {
-    s->stream = S->streams[S->next_stream++ % S->streams.size()];
     const nm_solve_request &r = s->req;
     s->nc = (long long)r.n[0] * r.n[1] * r.n[2];
     s->nn = (long long)(r.n[0] + 1) * (r.n[1] + 1) * (r.n[2] + 1);
+    hipStream_t st = S->admit_stream;
     if (dev_alloc((void **)&s->par_dev, sizeof(float) * 3 * s->nc, S->pool) != hipSuccess) return false;
     if (dev_alloc((void **)&s->m_dev, sizeof(float) * 3 * s->nn, S->pool) != hipSuccess) return false;
-    if (hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess) return false;
     float *Ms = s->par_dev, *A = s->par_dev + s->nc, *al = s->par_dev + 2 * s->nc;
     const size_t cb = sizeof(float) * s->nc;
-    if (hipMemcpyAsync(Ms, s->Ms.data(), cb, hipMemcpyHostToDevice, s->stream) != hipSuccess) return false;
-    if (hipMemcpyAsync(A, s->A.data(), cb, hipMemcpyHostToDevice, s->stream) != hipSuccess) return false;
-    if (hipMemcpyAsync(al, s->alpha.data(), cb, hipMemcpyHostToDevice, s->stream) != hipSuccess) return false;
-    if (hipMemcpyAsync(s->m_dev, s->m0.data(), sizeof(float) * 3 * s->nn, hipMemcpyHostToDevice, s->stream) !=
-        hipSuccess)
+    if (hipMemcpyAsync(Ms, s->Ms.data(), cb, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+    if (hipMemcpyAsync(A, s->A.data(), cb, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+    if (hipMemcpyAsync(al, s->alpha.data(), cb, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+    if (hipMemcpyAsync(s->m_dev, s->m0.data(), sizeof(float) * 3 * s->nn, hipMemcpyHostToDevice, st) != hipSuccess)
         return false;
     nm_mesh_desc d{};
     for (int k = 0; k < 3; ++k) {
@@ -136,7 +316,7 @@ bool admit(nm_server *S, Solve *s) {
         d.h[k] = r.h[k];
     }
     d.gamma = r.gamma;
-    d.stream = s->stream;
+    d.stream = st;
     nm_material mat{};
     mat.Ms = Ms;
     mat.A = A;
@@ -150,34 +330,122 @@ bool admit(nm_server *S, Solve *s) {
     in.rtol = r.rtol;
     in.atol = r.atol;
     in.dt_min = 1e-20;
-    s->clk = nm_clock{0.0, r.dt0, 0, 0, 0, 0.0};
-    if (step_begin(s->mesh, s->m_dev, &s->clk, &in, r.t_end, 1L << 40, &s->batch) != NM_OK) return false;
-    s->batch = S->desc.attempts_per_launch;
-    s->next = batch_for(std::ceil(r.t_end / r.dt0 * (1.0 + 1e-9)), s->batch);
+    nm_clock clk{0.0, r.dt0, 0, 0, 0, 0.0};
+    int batch = 0;
+    if (step_begin(s->mesh, s->m_dev, &clk, &in, r.t_end, 1L << 40, &batch) != NM_OK) return false;
+    // its group: one of the class with a free slot, else a new one
+    const ClassKey key = class_of(r);
+    Group *g = nullptr;
+    int slot = -1;
+    for (Group *x : S->groups) {
+        if (x->key != key) continue;
+        for (int i = 0; i < x->cap; ++i)
+            if (x->state[i] == kFree) {
+                g = x;
+                slot = i;
+                break;
+            }
+        if (g) break;
+    }
+    BatchSlot desc{};
+    if (hipEventRecord(S->admit_ev, st) != hipSuccess) return false;
+    if (!g) {
+        // the controller the timing's stage-2 kernels read: the mesh's own
+        batch_slot_fill(s->mesh, r.terms, s->mesh->ctrl, s->m_dev, &desc);
+        g = group_create(S, key, s, desc);
+        if (!g) return false;
+        S->groups.push_back(g);
+        slot = 0;
+    }
+    // the group's controller of the slot starts as the mesh's (after the first stage)
+    if (hipMemcpyAsync(g->ctrl_dev + slot, s->mesh->ctrl, sizeof(Ctrl), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return false;
+    if (hipEventRecord(S->admit_ev, st) != hipSuccess) return false;
+    batch_slot_fill(s->mesh, r.terms, g->ctrl_dev + slot, s->m_dev, &desc);
+    g->next[slot] = desc;
+    g->member[slot] = s;
+    g->state[slot] = kJoining;
+    g->dirty = true;
+    g->wait_admit = true;
+    s->group = g;
+    s->slot = slot;
     s->res.t_admit = now_s();
     return true;
 }
 
-void complete(nm_server *S, Solve *s) {
-    nm_status st = step_finish(s->mesh, NM_DP45, &s->clk);
+// a finished member: result, state read back, resources released, slot freed
+void complete(nm_server *S, Group *g, int slot) {
+    Solve *s = g->member[slot];
+    const Ctrl &C = g->ctrl_pin[slot];
+    s->res.t = C.t;
+    s->res.accepted = C.accepted;
+    s->res.rejected = C.rejected;
+    s->res.rhs_evals = C.rhs_evals + 1;   // + the first stage
+    int status = C.status == NM_ENONFINITE ? NM_ENONFINITE : C.status == NM_ESTEPSIZE ? NM_ESTEPSIZE : NM_OK;
     s->m_out.resize(3 * s->nn);
-    hipError_t e = hipMemcpyAsync(s->m_out.data(), s->m_dev, sizeof(float) * 3 * s->nn,
-                                  hipMemcpyDeviceToHost, s->stream);
-    // wait for this solve's work only (the stream is shared with other solves)
-    if (e == hipSuccess) e = hipEventRecord(s->ev, s->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(s->ev);
-    s->res.status = e != hipSuccess ? NM_EHIP : st;
-    s->res.t = s->clk.t;
-    s->res.accepted = s->clk.accepted;
-    s->res.rejected = s->clk.rejected;
-    s->res.rhs_evals = s->clk.rhs_evals;
-    release(s, S->pool);
-    s->res.t_done = now_s();
-    std::lock_guard<std::mutex> lk(S->mu);
-    S->used -= s->footprint;
-    S->done[s->ticket] = s;
-    S->known[s->ticket] = 2;
-    S->cv_done.notify_all();
+    hipError_t e = hipMemcpyAsync(s->m_out.data(), s->m_dev, sizeof(float) * 3 * s->nn, hipMemcpyDeviceToHost,
+                                  g->stream);
+    if (e == hipSuccess) e = hipEventRecord(g->ev, g->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(g->ev);
+    if (e != hipSuccess) status = NM_EHIP;
+    g->member[slot] = nullptr;
+    g->state[slot] = kFree;
+    g->next[slot].active = 0;
+    g->dirty = true;
+    finish(S, s, status, true);
+}
+
+// issue one replay of an idle group: new descriptors, the graph, the
+// controllers' read-back
+hipError_t issue(nm_server *S, Group *g) {
+    hipError_t e = hipSuccess;
+    if (g->dirty) {
+        std::memcpy(g->slots_pin, g->next.data(), sizeof(BatchSlot) * g->cap);
+        e = hipMemcpyAsync(g->slots_dev, g->slots_pin, sizeof(BatchSlot) * g->cap, hipMemcpyHostToDevice, g->stream);
+        for (int i = 0; i < g->cap; ++i)
+            if (g->state[i] == kJoining) g->state[i] = kRunning;
+        g->dirty = false;
+    }
+    if (e == hipSuccess && g->wait_admit) {
+        e = hipStreamWaitEvent(g->stream, S->admit_ev, 0);
+        g->wait_admit = false;
+    }
+    // the smallest power of two of slots that covers every occupied slot
+    int hi = 0;
+    for (int i = 0; i < g->cap; ++i)
+        if (g->state[i] != kFree) hi = i + 1;
+    int k = 0;
+    while ((1 << k) < hi) ++k;
+    const int slots = std::min(1 << k, g->cap);
+    if (e == hipSuccess && !g->gexec[k]) {
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeRelaxed);
+        hipError_t e2 = e == hipSuccess ? enqueue_attempts(g, slots, S->desc.attempts_per_launch, g->stream) : e;
+        if (e == hipSuccess) e = hipStreamEndCapture(g->stream, &graph);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&g->gexec[k], graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e == hipSuccess) e = hipGraphUpload(g->gexec[k], g->stream);
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(g->gexec[k], g->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->ctrl_pin, g->ctrl_dev, sizeof(Ctrl) * g->cap, hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipEventRecord(g->ev, g->stream);
+    if (e == hipSuccess) g->inflight = true;
+    return e;
+}
+
+void fail_group(nm_server *S, Group *g) {
+    (void)hipStreamSynchronize(g->stream);
+    for (int i = 0; i < g->cap; ++i)
+        if (g->member[i]) {
+            finish(S, g->member[i], NM_EHIP, true);
+            g->member[i] = nullptr;
+            g->state[i] = kFree;
+            g->next[i].active = 0;
+        }
+    g->dirty = true;
+    g->inflight = false;
 }
 
 void run(nm_server *S) {
@@ -190,72 +458,65 @@ void run(nm_server *S) {
             {
                 std::unique_lock<std::mutex> lk(S->mu);
                 if (S->stop) return;
-                if (S->active.empty() && S->pending.empty()) {
+                if (S->n_active == 0 && S->pending.empty()) {
                     S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty(); });
                     if (S->stop) return;
                 }
-                if (S->pending.empty() || (int)S->active.size() >= S->desc.max_active) break;
+                if (S->pending.empty() || S->n_active >= S->desc.max_active) break;
                 Solve *f = S->pending.front();
-                if (S->used + f->footprint > S->budget) {
-                    if (!S->active.empty()) break;   // wait for memory to free up
-                    S->pending.pop_front();          // can never fit
+                if (S->used + f->footprint + f->setup > S->budget) {
+                    if (S->n_active > 0) break;   // wait for memory to free up
+                    S->pending.pop_front();        // can never fit
                     lk.unlock();
-                    fail(S, f, NM_EBUDGET);
+                    finish(S, f, NM_EBUDGET, false);
                     continue;
                 }
                 S->pending.pop_front();
                 S->used += f->footprint;
+                S->n_active += 1;
                 S->known[f->ticket] = 1;
                 s = f;
             }
             if (!admit(S, s)) {
-                {
-                    std::lock_guard<std::mutex> lk(S->mu);
-                    S->used -= s->footprint;
+                (void)hipStreamSynchronize(S->admit_stream);
+                if (s->group) {
+                    Group *g = s->group;
+                    g->member[s->slot] = nullptr;
+                    g->state[s->slot] = kFree;
+                    g->next[s->slot].active = 0;
+                    g->dirty = true;
                 }
-                fail(S, s, NM_EHIP);
-                continue;
+                finish(S, s, NM_EHIP, true);
             }
-            S->active.push_back(s);
         }
-        // issue a replay for every idle solve, retire finished ones
+        // retire finished members of groups whose replay has ended, then
+        // issue a replay for every idle group with running members
         bool progressed = false;
-        for (Solve *s : S->active) {
-            if (s->inflight) continue;
-            hipError_t e = step_batch(s->mesh, s->m_dev, NM_DP45, s->req.terms, s->batch, s->next);
-            if (e == hipSuccess) e = ctrl_readback(s->mesh);
-            if (e == hipSuccess) e = hipEventRecord(s->ev, s->stream);
-            if (e != hipSuccess) {
-                s->res.status = NM_EHIP;
-                s->inflight = false;
-                continue;
-            }
-            s->inflight = true;
-            progressed = true;
-        }
-        std::vector<Solve *> still;
-        for (Solve *s : S->active) {
-            if (s->res.status == NM_EHIP) {
-                {
-                    std::lock_guard<std::mutex> lk(S->mu);
-                    S->used -= s->footprint;
-                }
-                fail(S, s, NM_EHIP);
-                progressed = true;
-                continue;
-            }
-            if (s->inflight && hipEventQuery(s->ev) == hipSuccess) {
-                s->inflight = false;
-                progressed = true;
-                if (s->mesh->ctrl_host->done) {
-                    complete(S, s);
+        for (Group *g : S->groups) {
+            if (g->inflight) {
+                const hipError_t q = hipEventQuery(g->ev);
+                if (q == hipErrorNotReady) {
+                    (void)hipGetLastError();   // not an error: keep it out of later checks
                     continue;
                 }
-                s->next = next_batch(s->mesh, s->batch);
+                g->inflight = false;
+                progressed = true;
+                if (q != hipSuccess) {
+                    fail_group(S, g);
+                    continue;
+                }
+                for (int i = 0; i < g->cap; ++i)
+                    if (g->state[i] == kRunning && g->ctrl_pin[i].done) complete(S, g, i);
             }
-            still.push_back(s);
+            bool any = false;
+            for (int i = 0; i < g->cap; ++i) any = any || g->state[i] != kFree;
+            if (!any) continue;
+            if (issue(S, g) != hipSuccess) {
+                fail_group(S, g);
+                continue;
+            }
+            progressed = true;
         }
-        S->active.swap(still);
         if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
@@ -287,15 +548,22 @@ extern "C" nm_status nm_server_create(const nm_server_desc *desc, nm_server **ou
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) freeb = 0;
     S->budget = desc->hbm_budget ? desc->hbm_budget : (size_t)(0.8 * (double)freeb);
-    for (int i = 0; i < desc->n_streams; ++i) {
+    bool ok = true;
+    for (int i = 0; i < desc->n_streams + 1 && ok; ++i) {
         hipStream_t st = nullptr;
-        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
-            delete S;
-            set_error("nm_server_create: stream creation failed");
-            return NM_EHIP;
-        }
-        S->streams.push_back(st);
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (!ok) break;
+        if (i < desc->n_streams) S->streams.push_back(st);
+        else S->admit_stream = st;
+    }
+    ok = ok && hipEventCreateWithFlags(&S->admit_ev, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+        if (S->admit_stream) (void)hipStreamDestroy(S->admit_stream);
+        if (S->admit_ev) (void)hipEventDestroy(S->admit_ev);
+        delete S;
+        set_error("nm_server_create: stream creation failed");
+        return NM_EHIP;
     }
     S->pool = pool_create();
     S->worker = std::thread(run, S);
@@ -311,14 +579,21 @@ extern "C" nm_status nm_server_destroy(nm_server *S) {
     }
     S->cv_work.notify_all();
     S->worker.join();
-    for (Solve *s : S->active) {
-        (void)hipStreamSynchronize(s->stream);
-        release(s, S->pool);
-        delete s;
+    for (hipStream_t x : S->streams) (void)hipStreamSynchronize(x);
+    (void)hipStreamSynchronize(S->admit_stream);
+    for (Group *g : S->groups) {
+        for (Solve *s : g->member)
+            if (s) {
+                release(s, S->pool);
+                delete s;
+            }
+        group_destroy(g, S->pool);
     }
     for (Solve *s : S->pending) delete s;
     for (auto &kv : S->done) delete kv.second;
     for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
+    (void)hipStreamDestroy(S->admit_stream);
+    (void)hipEventDestroy(S->admit_ev);
     pool_destroy(S->pool);
     delete S;
     return NM_OK;
@@ -330,11 +605,13 @@ extern "C" nm_status nm_serve_submit(nm_server *S, const nm_solve_request *r, ui
     NM_REQUIRE(r->t_end > 0.0 && r->dt0 > 0.0 && r->rtol > 0.0 && r->atol > 0.0, NM_EINVAL,
                "nm_serve_submit: need t_end, dt0, rtol, atol > 0");
     NM_REQUIRE(!(r->terms & ~(unsigned)NM_T_ALL), NM_EINVAL, "nm_serve_submit: unknown term bits");
+    NM_REQUIRE(r->n[2] <= 128, NM_EINVAL, "nm_serve_submit: the server takes at most 128 cells along z");
     const size_t fp = solve_footprint(*r);
     NM_REQUIRE(fp > 0, NM_EINVAL, "nm_serve_submit: unsupported mesh size");
     Solve *s = new Solve();
     s->req = *r;
     s->footprint = fp;
+    s->setup = (r->terms & NM_T_DEMAG) ? solve_setup(*r) : 0;
     const size_t nc = (size_t)r->n[0] * r->n[1] * r->n[2];
     const size_t nn = (size_t)(r->n[0] + 1) * (r->n[1] + 1) * (r->n[2] + 1);
     s->Ms.assign(r->Ms, r->Ms + nc);

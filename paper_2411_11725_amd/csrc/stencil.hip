@@ -20,38 +20,6 @@
 
 namespace nm {
 
-struct StencilParams {
-    int N1, N2, N3, NX, NY, NZ;
-    long long nn, nc;
-    float Kp[8], Mp[8];
-    // node kernel: packed cell data and the pre-weighted cell-field source
-    const float4 *cellP;           // {2A with the sign bit of Ku, sqrt|Ku| e}
-    // {mu0 Ms V/8 (H_d [+ static H_ext]), mu0 Ms V/8 drive mask} per cell, or NULL
-    const float4 *src;
-    int drive;                     // add the drive (the w component times sin and its amplitude)
-    int W;                         // LDS window length per z offset: 256 + 2 NX + 2
-    int faces;                     // K^e couples face neighbours (cells are not cubes)
-    unsigned zcols;                // node kernel: 256-node ranges per node layer
-    const float *Dc;               // DMI constant per cell, or NULL
-    float gx[4], gy[4];            // DMI weights (see the node kernel)
-    float rNX, rNY;                // 1 / NX, 1 / NY
-    // energy kernel: raw cell data
-    const float *wc, *A2, *Ku, *easy, *hcell, *dmask, *hd;
-    float hu[3], damp[3];
-    double dfreq, dphase;
-    const float *inv_mass, *alpha_n, *gp_n;
-    unsigned terms;
-};
-
-struct StageArgs {
-    const float *in;
-    float *out, *y_next, *mstate, *acc;
-    float *k[7];
-    const Ctrl *ctrl;
-    ErrPartial *partials;
-    double t0, dt0;
-};
-
 // Dormand & Prince (1980) RK5(4)7FM: y_{s+1} = m + dt sum_{j<=s} a_{s+1,j} k_j
 __host__ __device__ constexpr double dp_c(int s) {  // stage s (1-based) time fraction
     return s == 1 ? 0.0 : s == 2 ? 1.0 / 5 : s == 3 ? 3.0 / 10 : s == 4 ? 4.0 / 5 : s == 5 ? 8.0 / 9 : 1.0;
@@ -164,22 +132,13 @@ __device__ __forceinline__ int small_div(int a, int d, float rd) {
 #define NM_NODE_WAVES 3
 #endif
 constexpr unsigned kNodeZGroup = 32;
-template <int MODE, int STAGE, int NIT, bool DMI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
-k_node(StencilParams P, StageArgs S) {
-    // consecutive block numbers on one XCD walk groups of kNodeZGroup
-    // 256-node ranges (a few rows of one node layer) layer by layer: the next
-    // layer's blocks find two of their three window layers and one of their
-    // two cell layers in that XCD's L2, while each block still reads
-    // contiguous rows.  zcols: ranges per layer; ranges past zcols NZ keep
-    // their place.
-    unsigned lb = xcd_block(blockIdx.x, gridDim.x);
-    if (kNodeZGroup > 0 && lb < P.zcols * (unsigned)P.NZ) {
-        const unsigned gi = lb / (kNodeZGroup * (unsigned)P.NZ);
-        const unsigned w = min(kNodeZGroup, P.zcols - gi * kNodeZGroup);
-        const unsigned rem = lb - gi * kNodeZGroup * (unsigned)P.NZ;
-        lb = (rem / w) * P.zcols + gi * kNodeZGroup + rem % w;
-    }
+// The node kernel's work for the 256-node range lb (the body shared by the
+// single-mesh and the batched kernels).
+// XT: the optional terms of this instantiation, a bit mask: 1 interfacial
+// DMI, 2 bulk DMI, 4 cubic anisotropy
+constexpr int kXtDmiI = 1, kXtDmiB = 2, kXtCubic = 4;
+template <int MODE, int STAGE, int NIT, int XT>
+__device__ __forceinline__ void node_body(const StencilParams &P, const StageArgs &S, unsigned lb) {
     const int tid = (int)threadIdx.x;
     const int n0 = (int)lb * 256;
     const int n = n0 + tid;
@@ -276,7 +235,7 @@ k_node(StencilParams P, StageArgs S) {
     }
     // DMI constants weighted like the cells (0 outside the mesh)
     float dq[8];
-    if constexpr (DMI) {
+    if constexpr ((XT & (kXtDmiI | kXtDmiB)) != 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) dq[q] = cw[q] * ldo(P.Dc, co[q] >> 2);
     }
@@ -426,16 +385,18 @@ k_node(StencilParams P, StageArgs S) {
                     }
                 }
         }
-        if constexpr (DMI) {
+        if constexpr ((XT & (kXtDmiI | kXtDmiB)) != 0) {
             // A_k(a, b) = G_k(a, b) - G_k(b, a) = d_k times the 1D mass factors
-            // of the other two axes (gx, gy indexed by which of them differ):
-            // the same in every cell holding both nodes, so per neighbour d it
-            // is weighted by the sum of D over those cells
+            // of the other two axes (gx, gy, gz indexed by which of them
+            // differ): the same in every cell holding both nodes, so per
+            // neighbour d it is weighted by the sum of D over those cells.
+            // Interfacial: g += (-A_x m_z, -A_y m_z, A_x m_x + A_y m_y);
+            // bulk: g_j += eps_jkl A_k m_l
 #pragma unroll
             for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
                 for (int dx = -1; dx <= 1; ++dx) {
-                    if (dx == 0 && dy == 0) continue;
+                    if (dx == 0 && dy == 0 && ((XT & kXtDmiI) || dz == 0)) continue;
                     float ds = 0.f;
 #pragma unroll
                     for (int q = 0; q < 8; ++q)
@@ -443,10 +404,73 @@ k_node(StencilParams P, StageArgs S) {
                     const float wx = dx == 0 ? 0.f : ds * (float)dx * P.gx[(dy != 0) + 2 * (dz != 0)];
                     const float wy = dy == 0 ? 0.f : ds * (float)dy * P.gy[(dx != 0) + 2 * (dz != 0)];
                     const float4 b = vb[(dy + 1) * 3 + dx + 1];
-                    g0 -= wx * b.z;
-                    g1 -= wy * b.z;
-                    g2 += wx * b.x + wy * b.y;
+                    if constexpr (XT & kXtDmiI) {
+                        g0 -= wx * b.z;
+                        g1 -= wy * b.z;
+                        g2 += wx * b.x + wy * b.y;
+                    } else {
+                        const float wz = dz == 0 ? 0.f : ds * (float)dz * P.gz[(dx != 0) + 2 * (dy != 0)];
+                        g0 += wy * b.z - wz * b.y;
+                        g1 += wz * b.x - wx * b.z;
+                        g2 += wx * b.y - wy * b.x;
+                    }
                 }
+        }
+    }
+    if constexpr ((XT & kXtCubic) != 0) {
+        // cubic anisotropy, quartic in m: Kc sum_g w phi_a(x_g) df/dm(m^h(x_g))
+        // over the 2-point Gauss points x_g of each cell q holding the node,
+        // a = (i1, i2, i3) the node's corner of q, m^h(x_g) interpolated from
+        // the cell's 8 corners (node offsets b - a) axis by axis
+        const float xi[2] = {P.gq[0], P.gq[1]};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int i1 = q & 1, i2 = (q >> 1) & 1, i3 = q >> 2;
+            const float4 k0 = ldo(P.cubP, 2u * co[q]), k1 = ldo(P.cubP, 2u * co[q] + 16u);
+            const float kc = k0.x * cw[q] * P.gw;
+            const float c1[3] = {k0.y, k0.z, k0.w}, c2[3] = {k1.x, k1.y, k1.z};
+            const float c3[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
+                                 c1[0] * c2[1] - c1[1] * c2[0]};
+            // corner values, then interpolation along x, y, z to the Gauss points
+            float cv[8][3];
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const float4 t = nb(((b >> 2) - i3 + 1) * 9 + (((b >> 1) & 1) - i2 + 1) * 3 + ((b & 1) - i1 + 1));
+                cv[b][0] = t.x;
+                cv[b][1] = t.y;
+                cv[b][2] = t.z;
+            }
+            float gv[8][3];
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const float wgt[3] = {xi[g & 1], xi[(g >> 1) & 1], xi[g >> 2]};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float yz[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) yz[r] = cv[2 * r][c] + wgt[0] * (cv[2 * r + 1][c] - cv[2 * r][c]);
+                    const float z0 = yz[0] + wgt[1] * (yz[1] - yz[0]), z1 = yz[2] + wgt[1] * (yz[3] - yz[2]);
+                    gv[g][c] = z0 + wgt[2] * (z1 - z0);
+                }
+            }
+            float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const float a1 = gv[g][0] * c1[0] + gv[g][1] * c1[1] + gv[g][2] * c1[2];
+                const float a2 = gv[g][0] * c2[0] + gv[g][1] * c2[1] + gv[g][2] * c2[2];
+                const float a3 = gv[g][0] * c3[0] + gv[g][1] * c3[1] + gv[g][2] * c3[2];
+                const float s1 = a1 * a1, s2 = a2 * a2, s3 = a3 * a3;
+                // phi_a at x_g: psi_{a_k}(x_g,k) = x or 1 - x
+                const float ph = (i1 ? xi[g & 1] : 1.f - xi[g & 1]) * (i2 ? xi[(g >> 1) & 1] : 1.f - xi[(g >> 1) & 1]) *
+                                 (i3 ? xi[g >> 2] : 1.f - xi[g >> 2]);
+                const float f1 = 2.f * a1 * (s2 + s3) * ph, f2 = 2.f * a2 * (s3 + s1) * ph, f3 = 2.f * a3 * (s1 + s2) * ph;
+                acc0 += f1 * c1[0] + f2 * c2[0] + f3 * c3[0];
+                acc1 += f1 * c1[1] + f2 * c2[1] + f3 * c3[1];
+                acc2 += f1 * c1[2] + f2 * c2[2] + f3 * c3[2];
+            }
+            g0 += kc * acc0;
+            g1 += kc * acc1;
+            g2 += kc * acc2;
         }
     }
     if (an) {
@@ -521,6 +545,25 @@ k_node(StencilParams P, StageArgs S) {
     if (MODE == kModeDP45 && STAGE == 7) reduce_partial(sq, mf, nf, S.partials + lb);
 }
 
+template <int MODE, int STAGE, int NIT, int XT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
+k_node(StencilParams P, StageArgs S) {
+    // consecutive block numbers on one XCD walk groups of kNodeZGroup
+    // 256-node ranges (a few rows of one node layer) layer by layer: the next
+    // layer's blocks find two of their three window layers and one of their
+    // two cell layers in that XCD's L2, while each block still reads
+    // contiguous rows.  zcols: ranges per layer; ranges past zcols NZ keep
+    // their place.
+    unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+    if (kNodeZGroup > 0 && lb < P.zcols * (unsigned)P.NZ) {
+        const unsigned gi = lb / (kNodeZGroup * (unsigned)P.NZ);
+        const unsigned w = min(kNodeZGroup, P.zcols - gi * kNodeZGroup);
+        const unsigned rem = lb - gi * kNodeZGroup * (unsigned)P.NZ;
+        lb = (rem / w) * P.zcols + gi * kNodeZGroup + rem % w;
+    }
+    node_body<MODE, STAGE, NIT, XT>(P, S, lb);
+}
+
 dim3 stencil_grid(const nm_mesh *m) { return dim3((unsigned)((m->n_nodes + 255) / 256)); }
 
 // ---------------------------------------------------------------- energies
@@ -584,17 +627,51 @@ __global__ void __launch_bounds__(256) k_energy_cells(StencilParams P, const flo
         if ((P.terms & NM_T_DEMAG) && P.hd)
             ed = -0.5f * w * (ms0 * P.hd[c] + ms1 * P.hd[P.nc + c] + ms2 * P.hd[2 * P.nc + c]);
         if ((P.terms & NM_T_DMI) && P.Dc) {
-            // D sum_ab [G_x(a,b) (m_az m_bx - m_ax m_bz) + G_y(a,b) (m_az m_by - m_ay m_bz)],
-            // G_k(a,b) = (b_k - 1/2) gk[...] (1D mass factors of the other axes)
+            // G_k(a,b) = (b_k - 1/2) gk[...] (1D mass factors of the other axes);
+            // interfacial: D sum_ab [G_x(a,b) (m_az m_bx - m_ax m_bz) + G_y(a,b) (m_az m_by - m_ay m_bz)],
+            // bulk: D sum_ab eps_jkl m_aj G_k(a,b) m_bl
             float s = 0.f;
             for (int a = 0; a < 8; ++a)
                 for (int b = 0; b < 8; ++b) {
                     const int d = a ^ b;
                     const float gxv = ((b & 1) ? 0.5f : -0.5f) * P.gx[((d >> 1) & 1) + 2 * ((d >> 2) & 1)];
                     const float gyv = (((b >> 1) & 1) ? 0.5f : -0.5f) * P.gy[(d & 1) + 2 * ((d >> 2) & 1)];
-                    s += gxv * (v[a][2] * v[b][0] - v[a][0] * v[b][2]) + gyv * (v[a][2] * v[b][1] - v[a][1] * v[b][2]);
+                    if (!P.dmi_bulk) {
+                        s += gxv * (v[a][2] * v[b][0] - v[a][0] * v[b][2]) +
+                             gyv * (v[a][2] * v[b][1] - v[a][1] * v[b][2]);
+                    } else {
+                        const float gzv = ((b >> 2) ? 0.5f : -0.5f) * P.gz[(d & 1) + 2 * ((d >> 1) & 1)];
+                        s += gyv * (v[a][0] * v[b][2] - v[a][2] * v[b][0]) +
+                             gzv * (v[a][1] * v[b][0] - v[a][0] * v[b][1]) +
+                             gxv * (v[a][2] * v[b][1] - v[a][1] * v[b][2]);
+                    }
                 }
             edm = P.Dc[c] * s;
+        }
+        if ((P.terms & NM_T_CUBIC) && P.cubP) {
+            // Kc sum_g w f(m^h(x_g)) over the 2-point Gauss points, added to
+            // the anisotropy energy
+            const float4 k0 = P.cubP[2 * c], k1 = P.cubP[2 * c + 1];
+            const float c1[3] = {k0.y, k0.z, k0.w}, c2[3] = {k1.x, k1.y, k1.z};
+            const float c3[3] = {c1[1] * c2[2] - c1[2] * c2[1], c1[2] * c2[0] - c1[0] * c2[2],
+                                 c1[0] * c2[1] - c1[1] * c2[0]};
+            float s = 0.f;
+            for (int g = 0; g < 8; ++g) {
+                float mg[3] = {0.f, 0.f, 0.f};
+                for (int b = 0; b < 8; ++b) {
+                    float ph = 1.f;
+                    for (int k = 0; k < 3; ++k) {
+                        const float x = P.gq[(g >> k) & 1];
+                        ph *= ((b >> k) & 1) ? x : 1.f - x;
+                    }
+                    for (int q = 0; q < 3; ++q) mg[q] += ph * v[b][q];
+                }
+                const float a1 = mg[0] * c1[0] + mg[1] * c1[1] + mg[2] * c1[2];
+                const float a2 = mg[0] * c2[0] + mg[1] * c2[1] + mg[2] * c2[2];
+                const float a3 = mg[0] * c3[0] + mg[1] * c3[1] + mg[2] * c3[2];
+                s += a1 * a1 * a2 * a2 + a2 * a2 * a3 * a3 + a3 * a3 * a1 * a1;
+            }
+            ean += k0.x * P.gw * s;
         }
     }
     __shared__ double s[5][256];
@@ -633,7 +710,7 @@ __global__ void k_energy_final(const double *__restrict__ part, int nb, double *
 // One block of 1024 threads: each thread sums a fixed strided subset of the
 // block partials (8 loads in flight per round), then lane exchanges and LDS
 // combine the 16 waves; the order is fixed, so the result is reproducible.
-__global__ void __launch_bounds__(1024) k_dp45_control(Ctrl *C, const ErrPartial *__restrict__ part, int np) {
+__device__ __forceinline__ void dp45_control_body(Ctrl *C, const ErrPartial *__restrict__ part, int np) {
     __shared__ double s_sq[16];
     __shared__ float s_mf[16];
     __shared__ int s_nf[16];
@@ -725,11 +802,14 @@ __global__ void __launch_bounds__(1024) k_dp45_control(Ctrl *C, const ErrPartial
     C->dt = fmin(dtn, C->t_end - C->t);
 }
 
-__global__ void k_dp45_finish(const Ctrl *__restrict__ C, float *__restrict__ mstate,
-                              const float *__restrict__ y7, float *__restrict__ k1,
-                              const float *__restrict__ k7, float *__restrict__ y2, long long n3,
-                              double a21) {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+__global__ void __launch_bounds__(1024) k_dp45_control(Ctrl *C, const ErrPartial *__restrict__ part, int np) {
+    dp45_control_body(C, part, np);
+}
+
+__device__ __forceinline__ void dp45_finish_body(const Ctrl *__restrict__ C, float *__restrict__ mstate,
+                                                 const float *__restrict__ y7, float *__restrict__ k1,
+                                                 const float *__restrict__ k7, float *__restrict__ y2,
+                                                 long long n3, double a21, long long i) {
     if (i >= n3) return;
     const bool acc = C->accept;
     const bool done = C->done;
@@ -747,6 +827,13 @@ __global__ void k_dp45_finish(const Ctrl *__restrict__ C, float *__restrict__ ms
         kv = k1[i];
     }
     if (!done) y2[i] = mv + (float)(C->dt * a21) * kv;
+}
+
+__global__ void k_dp45_finish(const Ctrl *__restrict__ C, float *__restrict__ mstate,
+                              const float *__restrict__ y7, float *__restrict__ k1,
+                              const float *__restrict__ k7, float *__restrict__ y2, long long n3,
+                              double a21) {
+    dp45_finish_body(C, mstate, y7, k1, k7, y2, n3, a21, (long long)blockIdx.x * 256 + threadIdx.x);
 }
 
 __global__ void k_rk4_advance(Ctrl *C) {
@@ -785,10 +872,17 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
     P.faces = (m->Kp[1] != 0.f || m->Kp[2] != 0.f || m->Kp[4] != 0.f) ? 1 : 0;
     P.zcols = m->NZ > 1 ? stencil_grid(m).x / (unsigned)m->NZ : 0u;
     P.Dc = ((terms & NM_T_DMI) && m->has_dmi) ? m->Dc : nullptr;
+    P.dmi_bulk = m->dmi_bulk ? 1 : 0;
     for (int i = 0; i < 4; ++i) {
         P.gx[i] = m->gx[i];
         P.gy[i] = m->gy[i];
+        // a single node layer (the film basis) has no derivative along z
+        P.gz[i] = m->NZ > 1 ? m->gz[i] : 0.f;
     }
+    P.cubP = ((terms & NM_T_CUBIC) && m->has_cubic) ? m->cubP : nullptr;
+    P.gq[0] = m->gq[0];
+    P.gq[1] = m->gq[1];
+    P.gw = m->gw;
     P.rNX = 1.f / (float)m->NX;
     P.rNY = 1.f / (float)m->NY;
     P.wc = m->wc;
@@ -814,36 +908,58 @@ static StencilParams make_params(const nm_mesh *m, unsigned terms) {
 // window items per thread: the smallest of 5, 7, 10, 13 covering the 3 W of
 // the dz windows (one W with a single node layer); longer rows (NX > 425,
 // or NX > 1535 with one layer) read their neighbours directly
-static int window_items(int NX, int NZ) {
+int window_items(int NX, int NZ) {
     const int need = ((NZ > 1 ? 3 : 1) * (256 + 2 * NX + 2) + 255) / 256;
     return need <= 5 ? 5 : need <= 7 ? 7 : need <= 10 ? 10 : need <= 13 ? 13 : 0;
 }
 
-// the DMI term is a separate instantiation, so meshes without it keep the
-// register budget of the other terms; with it the 13-item window would spill
-// at 3 waves per SIMD, and those rows read their neighbours directly
-template <int MODE, int STAGE, bool DMI>
+// The optional terms are separate instantiations, so meshes without them
+// keep the register budget of the others.  Interfacial DMI takes the LDS
+// window up to 10 items (the 13-item window would spill at 3 waves per
+// SIMD); bulk DMI and cubic anisotropy read their neighbours directly.
+template <int MODE, int STAGE, int XT>
 static void launch_node_t(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
-    switch (window_items(m->NX, m->NZ)) {
-        case 5: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 5, DMI>), grid, dim3(256), 0, P, S); break;
-        case 7: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 7, DMI>), grid, dim3(256), 0, P, S); break;
-        case 10: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 10, DMI>), grid, dim3(256), 0, P, S); break;
-        case 13:
-            if constexpr (!DMI) {
-                NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 13, false>), grid, dim3(256), 0, P, S);
+    const int nit = (XT & ~kXtDmiI) ? 0 : window_items(m->NX, m->NZ);
+    switch (nit) {
+        case 5:
+            if constexpr ((XT & ~kXtDmiI) == 0) {
+                NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 5, XT>), grid, dim3(256), 0, P, S);
                 break;
             }
             [[fallthrough]];
-        default: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 0, DMI>), grid, dim3(256), 0, P, S); break;
+        case 7:
+            if constexpr ((XT & ~kXtDmiI) == 0) {
+                NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 7, XT>), grid, dim3(256), 0, P, S);
+                break;
+            }
+            [[fallthrough]];
+        case 10:
+            if constexpr ((XT & ~kXtDmiI) == 0) {
+                NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 10, XT>), grid, dim3(256), 0, P, S);
+                break;
+            }
+            [[fallthrough]];
+        case 13:
+            if constexpr (XT == 0) {
+                NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 13, 0>), grid, dim3(256), 0, P, S);
+                break;
+            }
+            [[fallthrough]];
+        default: NM_LAUNCH(m, NM_PROF_STENCIL, (k_node<MODE, STAGE, 0, XT>), grid, dim3(256), 0, P, S); break;
     }
 }
 
 template <int MODE, int STAGE>
 static void launch_node(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
-    if (P.Dc)
-        launch_node_t<MODE, STAGE, true>(m, grid, P, S);
-    else
-        launch_node_t<MODE, STAGE, false>(m, grid, P, S);
+    const int xt = (P.Dc ? (P.dmi_bulk ? kXtDmiB : kXtDmiI) : 0) | (P.cubP ? kXtCubic : 0);
+    switch (xt) {
+        case 0: launch_node_t<MODE, STAGE, 0>(m, grid, P, S); break;
+        case kXtDmiI: launch_node_t<MODE, STAGE, kXtDmiI>(m, grid, P, S); break;
+        case kXtDmiB: launch_node_t<MODE, STAGE, kXtDmiB>(m, grid, P, S); break;
+        case kXtCubic: launch_node_t<MODE, STAGE, kXtCubic>(m, grid, P, S); break;
+        case kXtCubic | kXtDmiI: launch_node_t<MODE, STAGE, kXtCubic | kXtDmiI>(m, grid, P, S); break;
+        default: launch_node_t<MODE, STAGE, kXtCubic | kXtDmiB>(m, grid, P, S); break;
+    }
 }
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
@@ -969,6 +1085,117 @@ hipError_t launch_cell_pack(nm_mesh *m) {
 
 hipError_t launch_rk4_advance(nm_mesh *m) {
     NM_LAUNCH(m, NM_PROF_CONTROL, k_rk4_advance, dim3(1), dim3(1), 0, m->ctrl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ batched launches
+// One launch covers every slot of a batch group (grid z = slot).  Each block
+// runs exactly the code of the single-mesh kernel on its slot's buffers (the
+// node kernel without the XCD renumbering, which changes only which block
+// takes which node range), so a solve's result does not depend on the other
+// solves of its group.
+template <int STAGE, int NIT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
+k_node_b(const BatchSlot *__restrict__ slots) {
+    const BatchSlot &d = slots[blockIdx.z];
+    if (!d.active || blockIdx.x >= (unsigned)d.np) return;
+    node_body<kModeDP45, STAGE, NIT, 0>(d.P, d.S[STAGE], blockIdx.x);
+}
+
+__global__ void __launch_bounds__(1024) k_dp45_control_b(const BatchSlot *__restrict__ slots) {
+    const BatchSlot &d = slots[blockIdx.x];
+    if (!d.active) return;
+    dp45_control_body(d.ctrl, d.partials, d.np);
+}
+
+__global__ void k_dp45_finish_b(const BatchSlot *__restrict__ slots, double a21) {
+    const BatchSlot &d = slots[blockIdx.z];
+    if (!d.active) return;
+    dp45_finish_body(d.ctrl, d.mstate, d.y1, d.k1, d.k7, d.y0, d.n3, a21,
+                     (long long)blockIdx.x * 256 + threadIdx.x);
+}
+
+// descriptor of one solve: mesh m with its state mstate, the buffers as the
+// DP45 stepping of nm_llg_step uses them; ctrl: the controller the batched
+// kernels update
+void batch_slot_fill(const nm_mesh *m, unsigned terms, Ctrl *ctrl, float *mstate, BatchSlot *out) {
+    BatchSlot d{};
+    d.active = 1;
+    d.N1 = m->N1;
+    d.N2 = m->N2;
+    d.N3 = m->N3;
+    d.NZ = m->NZ;
+    d.P2 = m->P2;
+    d.K1 = m->K1;
+    d.KP = m->KP;
+    d.P2h = m->P2h;
+    d.P3h = m->P3h;
+    d.src_mode = (terms & NM_T_ZEEMAN) ? 2 : 1;
+    d.Ms = m->Ms;
+    d.spec = m->spec;
+    d.tensor = m->tensor;
+    d.hd = m->hd;
+    d.wc = m->wc;
+    d.wstat = m->wstat;
+    d.ctrl = ctrl;
+    d.partials = m->partials;
+    d.np = (int)stencil_grid(m).x;
+    d.y0 = m->y[0];
+    d.y1 = m->y[1];
+    d.k1 = m->k[0];
+    d.k7 = m->k[6];
+    d.n3 = 3 * m->n_nodes;
+    d.P = make_params(m, terms);
+    d.mstate = mstate;
+    for (int st = 2; st <= 7; ++st) {
+        d.stage_in[st] = m->y[st % 2];
+        StageArgs &S = d.S[st];
+        S.in = m->y[st % 2];
+        S.out = nullptr;
+        S.y_next = st < 7 ? m->y[(st + 1) % 2] : nullptr;
+        S.mstate = mstate;
+        S.acc = m->acc;
+        S.ctrl = ctrl;
+        S.partials = m->partials;
+        for (int j = 0; j < 7; ++j) S.k[j] = m->k[j];
+        S.t0 = S.dt0 = 0.0;
+    }
+    *out = d;
+}
+
+template <int STAGE>
+static void launch_node_b(const BatchClass &bc, const BatchSlot *slots, int cap, hipStream_t st) {
+    const dim3 g(bc.node_blocks, 1, (unsigned)cap);
+    switch (bc.nit) {
+        case 5: hipLaunchKernelGGL((k_node_b<STAGE, 5>), g, dim3(256), 0, st, slots); break;
+        case 7: hipLaunchKernelGGL((k_node_b<STAGE, 7>), g, dim3(256), 0, st, slots); break;
+        case 10: hipLaunchKernelGGL((k_node_b<STAGE, 10>), g, dim3(256), 0, st, slots); break;
+        case 13: hipLaunchKernelGGL((k_node_b<STAGE, 13>), g, dim3(256), 0, st, slots); break;
+        default: hipLaunchKernelGGL((k_node_b<STAGE, 0>), g, dim3(256), 0, st, slots); break;
+    }
+}
+
+hipError_t launch_batch_node(const BatchClass &bc, const BatchSlot *slots, int cap, int stage, hipStream_t st) {
+    switch (stage) {
+        case 2: launch_node_b<2>(bc, slots, cap, st); break;
+        case 3: launch_node_b<3>(bc, slots, cap, st); break;
+        case 4: launch_node_b<4>(bc, slots, cap, st); break;
+        case 5: launch_node_b<5>(bc, slots, cap, st); break;
+        case 6: launch_node_b<6>(bc, slots, cap, st); break;
+        case 7: launch_node_b<7>(bc, slots, cap, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_control(const BatchSlot *slots, int cap, hipStream_t st) {
+    hipLaunchKernelGGL(k_dp45_control_b, dim3((unsigned)cap), dim3(1024), 0, st, slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BatchClass &bc, const BatchSlot *slots, int cap, hipStream_t st) {
+    const unsigned blocks = (unsigned)((3ull * bc.node_blocks * 256 + 255) / 256);
+    hipLaunchKernelGGL(k_dp45_finish_b, dim3(blocks, 1, (unsigned)cap), dim3(256), 0, st, slots, dp_a(2, 1));
     return hipGetLastError();
 }
 

@@ -140,11 +140,13 @@ def as_film(p):
 
 
 def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
-                 hetero=True, ku_range=(0.0, 5e5), dmi=False):
+                 hetero=True, ku_range=(0.0, 5e5), dmi=False, dmi_type="interfacial", cubic=False):
     """Small heterogeneous problem used by the parity tests: every term on,
     per-cell Ms, A, alpha, Ku ~ U[ku_range] (a negative Ku makes the cell
-    easy-plane), easy axes and applied field; with dmi, an interfacial DMI
-    constant D ~ U[-3e-3, 3e-3] J/m^2 per cell."""
+    easy-plane), easy axes and applied field; with dmi, a DMI constant
+    D ~ U[-3e-3, 3e-3] J/m^2 per cell of the given kind ("interfacial" or
+    "bulk"); with cubic, a cubic anisotropy Kc ~ U[-4e5, 4e5] J/m^3 and
+    random orthonormal cubic axes (c1, c2) per cell."""
     rng = np.random.default_rng(seed)
     n1, n2, n3 = n
     cells = (n3, n2, n1)
@@ -153,10 +155,20 @@ def small_random(n, h=(2e-9, 2e-9, 2e-9), seed=7, anis=True, field=True,
     alpha = rng.uniform(0.01, 0.5, size=cells) if hetero else 0.1
     hc = rng.uniform(-5e4, 5e4, size=(3,) + cells) if field else None
     D = rng.uniform(-3e-3, 3e-3, size=cells) if dmi else None
-    return make_problem(n, h, Ms, A, alpha, seed=seed + 1,
-                        Ku=("uniform",) + tuple(ku_range) if anis else None,
-                        easy="random", h_uniform=(1e4, -2e4, 3e4) if field else (0, 0, 0),
-                        h_cell=hc, D=D)
+    p = make_problem(n, h, Ms, A, alpha, seed=seed + 1,
+                     Ku=("uniform",) + tuple(ku_range) if anis else None,
+                     easy="random", h_uniform=(1e4, -2e4, 3e4) if field else (0, 0, 0),
+                     h_cell=hc, D=D)
+    p["dmi_type"] = dmi_type
+    if cubic:
+        nc = n1 * n2 * n3
+        c1 = random_unit_vectors(nc, rng)
+        r = random_unit_vectors(nc, rng)
+        c2 = np.cross(c1, r, axis=0)
+        c2 /= np.linalg.norm(c2, axis=0, keepdims=True)
+        p["Kc"] = _f32(rng.uniform(-4e5, 4e5, size=cells))
+        p["cubic"] = _f32(np.concatenate([c1, c2]).reshape((6,) + cells))
+    return p
 
 
 def serving_requests(count, seed=104, rate=200.0, nmin=32, nmax=512, nzmax=8, h=3e-9):

@@ -13,7 +13,9 @@ def to_oracle(p):
         Ku=f(p["Ku"]), easy=f(p["easy"]), h_cell=f(p["h_cell"]),
         h_uniform=f(p["h_uniform"]), drive_mask=f(p["drive_mask"]),
         drive_amp=f(p["drive_amp"]), drive_freq=p["drive_freq"],
-        drive_phase=p["drive_phase"], D=f(p.get("D")))
+        drive_phase=p["drive_phase"], D=f(p.get("D")), dmi_type=p.get("dmi_type", "interfacial"),
+        Kc=f(p.get("Kc")),
+        cubic=None if p.get("cubic") is None else f(p["cubic"]).reshape((2, 3) + tuple(p["cubic"].shape[1:])))
     return mesh, mat, np.asarray(p["m0"], dtype=np.float64)
 
 
