@@ -7,7 +7,11 @@
 
 Controller (the paper names the method only): accept when the scaled RMS
 error is <= 1; the next step is dt * clip(0.9 err^(-1/5), 0.2, 5), without
-growth right after a rejection; the last step is shortened to land on t_end.
+growth right after a rejection; the last step is shortened to land on t_end,
+and a step that covers the remaining span to within a relative 1e-9 ends
+the integration at t_end exactly (rounding in the sum of the steps leaves no
+sliver step); the floor dt_min applies to the proposals of an integration
+that goes on.
 """
 import numpy as np
 
@@ -104,6 +108,7 @@ def dp45_solve(mesh, mat, m0, t0, t_end, dt0, rtol=1e-5, atol=1e-5,
         if t >= t_end or (max_accepted is not None and n_acc >= max_accepted):
             break
         dt = min(dt, t_end - t, dt_max)
+        last = dt >= (t_end - t) * (1.0 - 1e-9)
         y, err, k7 = dp45_attempt(mesh, mat, m, t, dt, k1, terms, a)
         if k1 is None:
             k1 = llg_rhs(mesh, mat, m, t, terms, a)
@@ -113,7 +118,7 @@ def dp45_solve(mesh, mat, m0, t0, t_end, dt0, rtol=1e-5, atol=1e-5,
         fac = 5.0 if e == 0.0 else min(5.0, max(0.2, 0.9 * e ** -0.2))
         if e <= 1.0:
             log.append((t, dt, True))
-            t = t + dt
+            t = t_end if last else t + dt
             m = y
             k1 = k7
             if rejected_last:
@@ -124,7 +129,7 @@ def dp45_solve(mesh, mat, m0, t0, t_end, dt0, rtol=1e-5, atol=1e-5,
             log.append((t, dt, False))
             rejected_last = True
         dt = dt * fac
-        if dt < dt_min:
+        if dt < dt_min and t < t_end:
             raise FloatingPointError("step size below dt_min")
     if return_dt:
         return m, log, dt

@@ -2,10 +2,18 @@
 adaptive Dormand-Prince run of the full 128 x 128 x 32 block (2 nm cells,
 alpha = 1, per-cell Ku ~ U[0, 5e5] J/m^3 with random easy axes, Ms = 1e6
 A/m, A = 1.5e-11 J/m, random m0; rtol = atol = 1e-5, dt0 = 1e-14 s; exchange,
-demag and anisotropy).  Stores every attempt (t, dt, accepted), and after
+demag and anisotropy), with steps capped at 1.5e-13 s.  Stores every
+attempt (t, dt, accepted), and after
 accepted steps 8, 16 and 24 the block average <m>, the total energy and m at
 64 sampled nodes (seed 7), so that the GPU can take the oracle's accepted
-steps on the full mesh and be compared node by node (Sec. 5.3).  Calls only
+steps on the full mesh and be compared node by node (Sec. 5.3).  The cap
+keeps every step inside the stability region of the exchange modes of 2 nm
+cells (|lambda| ~ gamma' 2A/(mu0 Ms) 12/h^2 sqrt(2) ~ 1e13 1/s at alpha = 1):
+an uncapped controller takes steps outside it while the smooth error still
+allows them, and rounding noise in those modes then grows by several times
+per step until the error estimate sees it -- in float32 about 1e9 times
+sooner than in float64, so replaying such steps compares two amplified
+noises, not the method.  Calls only
 the oracle and the input generator (~3 s per oracle right-hand side):
 
     python tests/golden/make_block_prefix.py
@@ -30,6 +38,7 @@ from paper_2411_11725_amd import synth  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "block_prefix.txt")
 TERMS = EXCHANGE | DEMAG | ANISOTROPY
+DT_MAX = 1.5e-13
 CHECK = (8, 16, 24)
 
 
@@ -49,7 +58,7 @@ def main():
     t0 = time.perf_counter()
     for target in CHECK:
         m, seg, dt = oracle.dp45_solve(mesh, mat, m, t, 1e-9, dt, rtol=1e-5, atol=1e-5, terms=TERMS,
-                                       max_accepted=target - done, return_dt=True)
+                                       dt_max=DT_MAX, max_accepted=target - done, return_dt=True)
         log += seg
         done = target
         t = seg[-1][0] + seg[-1][1]
@@ -57,8 +66,8 @@ def main():
         rows.append((target, t, m.mean(axis=(1, 2, 3)), e["total"], m.reshape(3, -1)[:, idx]))
         print("accepted %d: t = %.4e s, E = %.10e J (%.0f s)" % (target, t, e["total"], time.perf_counter() - t0),
               flush=True)
-    lines = ["# block 128x128x32 (synth.block), DP45 rtol = atol = 1e-5, dt0 = 1e-14 s, exchange + demag + "
-             "anisotropy, float64 oracle;",
+    lines = ["# block 128x128x32 (synth.block), DP45 rtol = atol = 1e-5, dt0 = 1e-14 s, dt_max = %.3g s, "
+             "exchange + demag + anisotropy, float64 oracle;" % DT_MAX,
              "# the run continues after each check from the step the controller proposed (a split forgets only a",
              "# rejection right before it); written by tests/golden/make_block_prefix.py",
              "nodes " + " ".join(str(int(i)) for i in idx),

@@ -3,7 +3,7 @@
 recorded with the oracle: RMS over the components of magnetic nodes of
 e / (atol + rtol max(|y_old|, |y_new|)), accept when <= 1, next step
 dt clip(0.9 err^(-1/5), 0.2, 5), no growth right after a rejection, the last
-step shortened to land on t_end).
+step shortened to land on t_end exactly).
 
 The pins do not go through the oracle's stage arithmetic.  An undamped
 macrospin in a static field along z is a linear system: the in-plane part
@@ -152,11 +152,12 @@ def _controller_log(dt0, t_end, atol, rtol):
     log, capped = [], 0
     while t < t_end:
         dt = min(dt, t_end - t)
+        last = dt >= (t_end - t) * (1.0 - 1e-9)
         err, wn = _closed_norm(w, mz, dt, atol, rtol)
         grow = min(5.0, max(0.2, 0.9 * err ** (-1.0 / 5.0)))
         if err <= 1.0:
             log.append((t, dt, True))
-            t, w = t + dt, wn
+            t, w = (t_end if last else t + dt), wn
             if rejected_last and grow > 1.0:
                 capped += 1
                 grow = 1.0
@@ -223,3 +224,20 @@ def test_max_accepted_and_continuation():
     # the continuation forgets a rejection just before the split only; here
     # the third accepted step is not preceded by one
     assert [x[1] for x in a + b] == pytest.approx([x[1] for x in full], rel=1e-12)
+
+
+def test_last_step_lands_on_t_end_under_a_step_cap():
+    """With a step cap that does not divide the span, the steps add up to
+    t_end without a rounding sliver: the last one ends exactly there and no
+    step-size floor is hit on the way out (a sliver step of ~1e-26 s would
+    propose a step below dt_min)."""
+    mesh, mat, m = _macrospin()
+    span = 1e-9
+    _, log = oracle.dp45_solve(mesh, mat, m, 0.0, span, 1e-13, dt_max=3e-13, dt_min=1e-20, terms=TERMS)
+    acc = [(t, dt) for t, dt, ok in log if ok]
+    assert all(dt > 1e-14 for _, dt in acc)
+    assert acc[-1][0] + acc[-1][1] == pytest.approx(span, rel=1e-12)
+    assert max(dt for _, dt in acc) <= 3e-13
+    _, log2, dt_next = oracle.dp45_solve(mesh, mat, m, 0.0, span, 1e-13, dt_max=3e-13, terms=TERMS,
+                                         return_dt=True)
+    assert dt_next > 0 and log2 == log
