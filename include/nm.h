@@ -300,6 +300,13 @@ typedef struct {
     float h_uniform[3];            /* uniform applied field (A/m) */
     unsigned terms;                /* NM_T_* */
     double rtol, atol, dt0, t_end;
+    /* optional cell arrays as in nm_material (NULL: absent; zero-initialise
+     * the request so that callers unaware of them leave them absent) */
+    const float *Ku, *easy;        /* N and 3*N floats, given together */
+    const float *h_cell;           /* 3*N per-cell applied field (A/m) */
+    const float *D;                /* N floats, DMI constant (J/m^2) */
+    int dmi_type;                  /* NM_DMI_INTERFACIAL (0) or NM_DMI_BULK */
+    const float *Kc, *cubic;       /* N and 6*N floats, given together */
 } nm_solve_request;
 
 typedef struct {

@@ -64,7 +64,8 @@ class nm_solve_request(ctypes.Structure):
     _fields_ = [("n", c_int * 3), ("h", c_double * 3), ("gamma", c_double), ("Ms", c_void_p),
                 ("A", c_void_p), ("alpha", c_void_p), ("m0", c_void_p), ("h_uniform", c_float * 3),
                 ("terms", c_uint), ("rtol", c_double), ("atol", c_double), ("dt0", c_double),
-                ("t_end", c_double)]
+                ("t_end", c_double), ("Ku", c_void_p), ("easy", c_void_p), ("h_cell", c_void_p),
+                ("D", c_void_p), ("dmi_type", c_int), ("Kc", c_void_p), ("cubic", c_void_p)]
 
 
 class nm_solve_result(ctypes.Structure):
@@ -262,14 +263,23 @@ def nm_server_destroy(server):
 
 
 def nm_serve_submit(server, p, terms=NM_T_ALL, rtol=1e-5, atol=1e-5, dt0=1e-14, t_end=0.2e-9):
-    """Submit a problem dict (see synth.make_problem; host float32 arrays)."""
+    """Submit a problem dict (see synth.make_problem; host float32 arrays).
+    The optional cell arrays Ku/easy, h_cell, D (with dmi_type) and
+    Kc/cubic go with the request when the dict has them; a drive does not
+    (the server runs no time-dependent field)."""
     import numpy as np
-    keep = [np.ascontiguousarray(p[k], dtype=np.float32) for k in ("Ms", "A", "alpha", "m0")]
-    ptr = [c_void_p(a.ctypes.data) for a in keep]
+    if p.get("drive_mask") is not None and any(float(v) != 0.0 for v in p.get("drive_amp", (0.0,) * 3)):
+        raise ValueError("nm_serve_submit: the server runs no time-dependent drive")
+    keys = ("Ms", "A", "alpha", "m0", "Ku", "easy", "h_cell", "D", "Kc", "cubic")
+    keep = {k: np.ascontiguousarray(p[k], dtype=np.float32) for k in keys if p.get(k) is not None}
+    ptr = {k: c_void_p(a.ctypes.data) for k, a in keep.items()}
     req = nm_solve_request((c_int * 3)(*p["n"]), (c_double * 3)(*p["h"]), float(p["gamma"]),
-                           ptr[0], ptr[1], ptr[2], ptr[3],
+                           ptr["Ms"], ptr["A"], ptr["alpha"], ptr["m0"],
                            (c_float * 3)(*[float(v) for v in p["h_uniform"]]), int(terms),
-                           float(rtol), float(atol), float(dt0), float(t_end))
+                           float(rtol), float(atol), float(dt0), float(t_end),
+                           ptr.get("Ku"), ptr.get("easy"), ptr.get("h_cell"), ptr.get("D"),
+                           NM_DMI_BULK if p.get("dmi_type", "interfacial") == "bulk" else NM_DMI_INTERFACIAL,
+                           ptr.get("Kc"), ptr.get("cubic"))
     t = ctypes.c_uint64()
     _check(lib().nm_serve_submit(server, ctypes.byref(req), ctypes.byref(t)))
     return t.value

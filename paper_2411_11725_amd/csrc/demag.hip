@@ -137,12 +137,32 @@ __device__ __forceinline__ void xfwd_body(const float *__restrict__ mag, const f
     }
 }
 
+// Block (row group, plane) of the x forward pass.  A block's last node row
+// is the next block's first; with one cell row per block (L >= 512) that is
+// half of what it reads, so the blocks go to the XCDs in contiguous ranges
+// and the shared row comes from the XCD's L2 (the dispatcher hands
+// consecutive blocks to different XCDs).  With several rows per block the
+// dispatch order stays: plane-ordered ranges measured no faster there.
+template <int L>
+__device__ __forceinline__ void xfwd_block(int &bx, int &by) {
+    if constexpr (x_rows_per_block(L) == 1) {
+        const unsigned nx = gridDim.x, l = xcd_block(blockIdx.x + nx * blockIdx.y, nx * gridDim.y);
+        bx = (int)(l % nx);
+        by = (int)(l / nx);
+    } else {
+        bx = (int)blockIdx.x;
+        by = (int)blockIdx.y;
+    }
+}
+
 template <int L>
 __global__ void __launch_bounds__(256)
 k_xfwd(const float *__restrict__ mag, const float *__restrict__ Ms, float2 *__restrict__ spec,
        const float2 *__restrict__ tw, int N1, int N2, int N3, int NZ, int P2, int KP,
        const Ctrl *__restrict__ ctrl) {
-    xfwd_body<L>(mag, Ms, spec, tw, N1, N2, N3, NZ, P2, KP, ctrl, blockIdx.x, blockIdx.y);
+    int bx, by;
+    xfwd_block<L>(bx, by);
+    xfwd_body<L>(mag, Ms, spec, tw, N1, N2, N3, NZ, P2, KP, ctrl, bx, by);
 }
 
 // ---------------------------------------------------------------- x inverse
@@ -524,12 +544,9 @@ __device__ __forceinline__ void zconv_r_body(float2 *__restrict__ spec, const fl
         const int kz = j + TT * (i / L1) + L2 * (i % L1);
         tensor_apply(N, kz <= L / 2 ? 1.f : -1.f, v[0][i], v[1][i], v[2][i]);
     };
-    constexpr bool PREFETCH = E <= 8;   // registers allow holding all E entries
-    Tensor6 Nt[PREFETCH ? E : 1];
-    if constexpr (PREFETCH) {
-#pragma unroll
-        for (int i = 0; i < E; ++i) Nt[i] = tensor_at(i);
-    }
+    // The tensor entries are loaded where they are applied, after the forward
+    // transform: fetching all E of them up front (to hide their latency
+    // behind the transform) costs 24 VGPRs and measured 7% slower at L = 64.
     // a finished controller turns the kernel into a no-op; the flag is read
     // after the data loads are issued, so its round trip overlaps theirs
     if (ctrl && ctrl->done) return;
@@ -542,10 +559,7 @@ __device__ __forceinline__ void zconv_r_body(float2 *__restrict__ spec, const fl
             fft2<L1, L2, -1, 1, NPB, E, true, false>(*reinterpret_cast<float2(*)[1][E]>(&v[c]), sh, tl, j, b);
     }
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-        if constexpr (PREFETCH) apply(i, Nt[i]);
-        else apply(i, tensor_at(i));
-    }
+    for (int i = 0; i < E; ++i) apply(i, tensor_at(i));
     if constexpr (NCX == 3) {
         fft2<L2, L1, 1, 3, NPB, E, false, true>(v, sh, tl, j, b);
     } else {
@@ -574,7 +588,10 @@ k_zconv_r(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *
 }
 
 // ------------------------------------ y forward + product + y inverse (N3 = 1)
-template <int L, int TB>
+// NTH threads per block (yconv_threads): the long columns of large films
+// are few (K1 = P1/2 + 1 of them, one per block), so each gets more threads
+// (512 at L = 1024: 9% faster than 256; 1024 gained nothing)
+template <int L, int TB, int NTH>
 __device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const float *__restrict__ T,
                                            const float2 *__restrict__ tw, int N2, int K1, int KP, int P2h,
                                            const Ctrl *__restrict__ ctrl, int lblock) {
@@ -586,12 +603,12 @@ __device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const floa
     // neighbouring column tiles on one XCD: a tile is narrower than a cache
     // line, and the tiles next to it read the rest of each line from L2
     const int col0 = lblock * TB;
-    static_assert((L * NP) % 256 == 0, "whole iterations");
-    constexpr int NI = L * NP / 256;
+    static_assert((L * NP) % NTH == 0, "whole iterations");
+    constexpr int NI = L * NP / NTH;
     float2 v[NI];
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-        const int it = tid + i * 256;
+        const int it = tid + i * NTH;
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
@@ -599,11 +616,11 @@ __device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const floa
         v[i] = keep(t, col < K1 && e < N2);
     }
     const long long tstride = (long long)P2h * KP;
-    constexpr int NT = ((L / 2 + 1) * TB + 255) / 256;
+    constexpr int NT = ((L / 2 + 1) * TB + NTH - 1) / NTH;
     Tensor6 Nt[NT];   // fetched now, applied after the forward transform
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
-        const int it = tid + i * 256;
+        const int it = tid + i * NTH;
         const int b = it % TB, kyr = it / TB;
         const bool ok = col0 + b < K1 && kyr <= L / 2;
         Nt[i] = tensor_load(T, tstride, (long long)(ok ? kyr : 0) * KP + min(col0 + b, K1 - 1), 1.f, false);
@@ -611,15 +628,15 @@ __device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const floa
     // a finished controller turns the kernel into a no-op; the flag is read
     // after the data loads are issued, so its round trip overlaps theirs
     if (ctrl && ctrl->done) return;
-    load_twiddles<L, 256>(tl, tw, tid);
+    load_twiddles<L, NTH>(tl, tw, tid);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) s[tid + i * 256] = v[i];
+    for (int i = 0; i < NI; ++i) s[tid + i * NTH] = v[i];
     __syncthreads();
-    lds_fft<L, -1, NP, 256, true, L>(s, tl, tid);
+    lds_fft<L, -1, NP, NTH, true, L>(s, tl, tid);
     // ky and L - ky share the stored tensor entry (xy flips sign)
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
-        const int it = tid + i * 256;
+        const int it = tid + i * NTH;
         const int b = it % TB, kyr = it / TB;
         const bool ok = col0 + b < K1 && kyr <= L / 2;
         const int kyc = ok ? kyr : 0;
@@ -638,8 +655,8 @@ __device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const floa
         }
     }
     __syncthreads();
-    lds_fft<L, 1, NP, 256, true, L>(s, tl, tid);
-    for (int it = tid; it < N2 * NP; it += 256) {
+    lds_fft<L, 1, NP, NTH, true, L>(s, tl, tid);
+    for (int it = tid; it < N2 * NP; it += NTH) {
         const int p = it % NP, e = it / NP;
         const int c = p / TB, b = p - (p / TB) * TB;
         const int col = col0 + b;
@@ -647,11 +664,13 @@ __device__ __forceinline__ void yconv_body(float2 *__restrict__ spec, const floa
     }
 }
 
+__host__ __device__ constexpr int yconv_threads(int L) { return L >= 1024 ? 512 : 256; }
+
 template <int L, int TB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(yconv_threads(L))
 k_yconv(float2 *__restrict__ spec, const float *__restrict__ T, const float2 *__restrict__ tw,
         int N2, int K1, int KP, int P2h, const Ctrl *__restrict__ ctrl) {
-    yconv_body<L, TB>(spec, T, tw, N2, K1, KP, P2h, ctrl, (int)xcd_block(blockIdx.x, gridDim.x));
+    yconv_body<L, TB, yconv_threads(L)>(spec, T, tw, N2, K1, KP, P2h, ctrl, (int)xcd_block(blockIdx.x, gridDim.x));
 }
 
 // --------------------------------------------------------------- dispatch
@@ -716,7 +735,7 @@ static void launch_zconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
 template <int L>
 static void launch_yconv(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     constexpr int TB = tb_triple(L);
-    NM_LAUNCH(m, NM_PROF_CONV, (k_yconv<L, TB>), dim3((m->K1 + TB - 1) / TB), dim3(256), 0, m->spec,
+    NM_LAUNCH(m, NM_PROF_CONV, (k_yconv<L, TB>), dim3((m->K1 + TB - 1) / TB), dim3(yconv_threads(L)), 0, m->spec,
               m->tensor, tw, m->N2, m->K1, m->KP, m->P2h, ctrl);
 }
 
@@ -797,11 +816,12 @@ void launch_y_pair(nm_mesh *m, const float2 *tw, const Ctrl *ctrl) {
     launch_y<L, 1>(m, tw, ctrl);
 }
 
-int widths(int L) {   // how many of the shifts 0, 1, 2 exist for length L
+}  // namespace
+
+int tile_widths(int L) {   // how many of the shifts 0, 1, 2 exist for length L
     const int npb = 256 / fft2_threads_host(L);
     return npb >= 4 ? 3 : npb >= 2 ? 2 : 1;
 }
-}  // namespace
 
 hipError_t tune_passes(nm_mesh *m) {
     m->tune_y = m->tune_z = 0;
@@ -851,13 +871,13 @@ hipError_t tune_passes(nm_mesh *m) {
     };
     int best_y = 0, best_z = 0;
     if (e == hipSuccess)
-        e = pick(widths(m->P2), [&](int v) -> hipError_t {
+        e = pick(tile_widths(m->P2), [&](int v) -> hipError_t {
             m->tune_y = v;
             NM_DISPATCH_COL(m->P2, launch_y_pair, m, tw, nullptr);
             return hipGetLastError();
         }, &best_y);
     if (e == hipSuccess && m->P3 <= 256)
-        e = pick(widths(m->P3), [&](int v) -> hipError_t {
+        e = pick(tile_widths(m->P3), [&](int v) -> hipError_t {
             m->tune_z = v;
             NM_DISPATCH_COL(m->P3, launch_zconv, m, tw, nullptr);
             return hipGetLastError();
@@ -882,9 +902,10 @@ __global__ void __launch_bounds__(256) k_xfwd_b(const BatchSlot *__restrict__ sl
                                                 const float2 *__restrict__ tw) {
     const BatchSlot &d = slots[blockIdx.z];
     constexpr int RB = x_rows_per_block(L);
-    if (!d.active || (int)blockIdx.x * RB >= d.N2 || (int)blockIdx.y >= d.N3) return;
-    xfwd_body<L>(d.stage_in[stage], d.Ms, d.spec, tw, d.N1, d.N2, d.N3, d.NZ, d.P2, d.KP, d.ctrl, blockIdx.x,
-                 blockIdx.y);
+    int bx, by;
+    xfwd_block<L>(bx, by);
+    if (!d.active || bx * RB >= d.N2 || by >= d.N3) return;
+    xfwd_body<L>(d.stage_in[stage], d.Ms, d.spec, tw, d.N1, d.N2, d.N3, d.NZ, d.P2, d.KP, d.ctrl, bx, by);
 }
 template <int L>
 __global__ void __launch_bounds__(256) k_xinv_b(const BatchSlot *__restrict__ slots, const float2 *__restrict__ tw) {
@@ -908,10 +929,12 @@ __global__ void __launch_bounds__(256) k_zconv_b(const BatchSlot *__restrict__ s
                         (int)xcd_block(blockIdx.x, gridDim.x));
 }
 template <int L, int TB>
-__global__ void __launch_bounds__(256) k_yconv_b(const BatchSlot *__restrict__ slots, const float2 *__restrict__ tw) {
+__global__ void __launch_bounds__(yconv_threads(L)) k_yconv_b(const BatchSlot *__restrict__ slots,
+                                                              const float2 *__restrict__ tw) {
     const BatchSlot &d = slots[blockIdx.z];
     if (!d.active) return;
-    yconv_body<L, TB>(d.spec, d.tensor, tw, d.N2, d.K1, d.KP, d.P2h, d.ctrl, (int)xcd_block(blockIdx.x, gridDim.x));
+    yconv_body<L, TB, yconv_threads(L)>(d.spec, d.tensor, tw, d.N2, d.K1, d.KP, d.P2h, d.ctrl,
+                                        (int)xcd_block(blockIdx.x, gridDim.x));
 }
 namespace {
 struct BatchLaunch {
@@ -978,7 +1001,8 @@ template <int L>
 void launch_yconv_bt(const BatchLaunch &b) {
     constexpr int TB = tb_triple(L);
     const int K1 = b.bc.P1 / 2 + 1;
-    hipLaunchKernelGGL((k_yconv_b<L, TB>), dim3((K1 + TB - 1) / TB, 1, b.cap), dim3(256), 0, b.st, b.slots, b.tw);
+    hipLaunchKernelGGL((k_yconv_b<L, TB>), dim3((K1 + TB - 1) / TB, 1, b.cap), dim3(yconv_threads(L)), 0, b.st,
+                       b.slots, b.tw);
 }
 }  // namespace
 

@@ -104,6 +104,7 @@ struct BatchSlot {
 struct BatchClass {
     int P1, P2, P3, nit;
     unsigned terms;
+    int xt;                      // node-kernel term instantiation (node_xt)
     int tune_y, tune_z;          // column-tile widths of the register FFT passes
     int maxN3;                   // N3 <= P3 / 2 (1 for single-layer grids)
     unsigned node_blocks;        // node-kernel blocks of the largest mesh
@@ -265,6 +266,7 @@ const float2 *twiddles(int device);   // per-device table (built at mesh creatio
 // {mu0 Ms V/8 (H_d + h_uniform + h_cell), mu0 Ms V/8 drive mask} (2)
 hipError_t demag_forward_conv_inverse(nm_mesh *m, const float *mag, int src_mode);
 hipError_t tune_passes(nm_mesh *m);   // block widths of the register-FFT passes
+int tile_widths(int L);               // how many column-tile widths (0, 1, 2) length L has
 hipError_t demag_forward_conv_inverse_ctrl(nm_mesh *m, const float *mag, const Ctrl *ctrl,
                                            int src_mode);
 
@@ -296,6 +298,7 @@ hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp);
 
 // batched launches over the cap slots of a group (grid z = slot)
 int window_items(int NX, int NZ);          // node-kernel LDS window items (0: direct loads)
+int node_xt(const nm_mesh *m, unsigned terms);   // node-kernel term instantiation of a mesh
 void batch_slot_fill(const nm_mesh *m, unsigned terms, Ctrl *ctrl, float *mstate, BatchSlot *out);
 hipError_t launch_batch_demag(const BatchClass &bc, const BatchSlot *slots, int cap, int stage, hipStream_t st);
 hipError_t launch_batch_node(const BatchClass &bc, const BatchSlot *slots, int cap, int stage, hipStream_t st);

@@ -14,11 +14,12 @@
 // replays, and the graph is captured once per group, not per member.  Groups
 // of different classes replay concurrently on a pool of streams.
 //
-// A group's slot count is its batch shape, chosen per class by timing the
-// batched stage kernels on the class's first member with 1, 2, 4, 8 and 16
-// slots (cached per class and device); the FFT column tiles come from the
-// per-mesh tuner.  Every member runs the single-mesh kernels' code on its own
-// buffers, so its result does not depend on what else is in the group.
+// A group's batch shape (the column-tile widths of its register-FFT passes
+// and its slot count) is chosen per class by timing the batched stage
+// kernels on the class's first member, cached per class and device.  Every
+// member runs the single-mesh kernels' code on its own buffers, so its
+// result does not depend on what else is in the group (nor on the widths,
+// which change only how columns are grouped into blocks).
 // Device memory of the solves comes from a pool (pool.hip): a finished solve
 // gives its buffers back without hipFree, which would wait for the device.
 #include <chrono>
@@ -58,6 +59,8 @@ struct Solve {
     uint64_t ticket = 0;
     nm_solve_request req{};
     std::vector<float> Ms, A, alpha, m0;
+    // optional cell arrays (empty: absent), in the order staged on the device
+    std::vector<float> opt[6];   // Ku, easy, h_cell, D, Kc, cubic
     size_t footprint = 0, setup = 0;
     long long nn = 0, nc = 0;
     nm_mesh *mesh = nullptr;
@@ -69,13 +72,23 @@ struct Solve {
     std::vector<float> m_out;
 };
 
-// class key: padded lengths and terms.  The node kernel's LDS window is sized
+// optional cell arrays of a request: pointer and floats per cell
+struct OptArray {
+    const float *nm_solve_request::*ptr;
+    int per_cell;
+};
+constexpr OptArray kOpt[6] = {{&nm_solve_request::Ku, 1},     {&nm_solve_request::easy, 3},
+                              {&nm_solve_request::h_cell, 3}, {&nm_solve_request::D, 1},
+                              {&nm_solve_request::Kc, 1},     {&nm_solve_request::cubic, 6}};
+
+// class key: padded lengths, terms and the node kernel's term instantiation
+// (which extra terms the mesh carries).  The node kernel's LDS window is sized
 // for the longest rows of the class; a longer window holds the same values
 // at the same places, so a member's result does not depend on it.
-using ClassKey = std::tuple<int, int, int, unsigned>;
+using ClassKey = std::tuple<int, int, int, unsigned, int>;
 
-ClassKey class_of(const nm_solve_request &r) {
-    return ClassKey{pad_len(r.n[0]), pad_len(r.n[1]), pad_len(r.n[2]), r.terms};
+ClassKey class_of(const nm_solve_request &r, const nm_mesh *m) {
+    return ClassKey{pad_len(r.n[0]), pad_len(r.n[1]), pad_len(r.n[2]), r.terms, node_xt(m, r.terms)};
 }
 
 enum SlotState { kFree = 0, kJoining = 1, kRunning = 2 };
@@ -126,9 +139,12 @@ struct nm_server {
 
 namespace {
 
-// batch shape per class and device, chosen by timing (see tune_cap)
+// batch shape per class and device, chosen by timing (see tune_shape)
+struct Shape {
+    int cap, tune_y, tune_z;
+};
 std::mutex g_cap_mu;
-std::map<std::tuple<ClassKey, int>, int> g_cap;
+std::map<std::tuple<ClassKey, int>, Shape> g_cap;
 constexpr int kMaxCap = 16;
 
 size_t solve_footprint(const nm_solve_request &r) {
@@ -142,7 +158,10 @@ size_t solve_footprint(const nm_solve_request &r) {
     if (base == 0) return 0;
     const size_t nn = (size_t)(r.n[0] + 1) * (r.n[1] + 1) * (r.n[2] + 1);
     const size_t nc = (size_t)r.n[0] * r.n[1] * r.n[2];
-    return base + sizeof(float) * (3 * nn + 3 * nc);   // state + staged parameters
+    size_t staged = 3;   // Ms, A, alpha
+    for (const OptArray &o : kOpt)
+        if (r.*(o.ptr)) staged += (size_t)o.per_cell;
+    return base + sizeof(float) * (3 * nn + staged * nc);   // state + staged parameters
 }
 
 // device bytes the tensor set-up of a request takes while it runs (float64
@@ -199,14 +218,17 @@ hipError_t enqueue_attempts(const Group *g, int slots, int attempts, hipStream_t
     return e;
 }
 
-// Batch shape of a class: the stage-2 kernels (demag passes and the node
-// kernel) on 1, 2, 4, 8 and 16 slots that all describe the class's first
-// member, timed on the group's stream; the slot count with the least time
-// per slot wins unless a smaller count is within 10% of it (fewer slots:
-// members wait less for each other).  Stage 2 writes only the first
-// member's stage buffers and FFT workspace, which its first real attempt
-// rewrites before reading.
-int tune_cap(nm_server *S, Group *g, const BatchSlot &first) {
+// Batch shape of a class, from the stage-2 kernels (demag passes and the
+// node kernel) on slots that all describe the class's first member, timed
+// on the group's stream (a warm-up and three interleaved timings of 4
+// launches, the fastest kept): first the column-tile widths of the y passes
+// and the z convolution on one slot (the widest unless another is 5%
+// faster), then the slot count among 1, 2, 4, 8, 16: the least time per slot
+// wins unless a smaller count is within 10% of it (members of a fuller group
+// wait longer for each other).  Stage 2 writes only the first member's
+// stage buffers and FFT workspace, which its first real attempt rewrites
+// before reading.
+Shape tune_shape(nm_server *S, Group *g, const BatchSlot &first) {
     const auto ck = std::make_tuple(g->key, S->device);
     {
         std::lock_guard<std::mutex> lk(g_cap_mu);
@@ -219,43 +241,64 @@ int tune_cap(nm_server *S, Group *g, const BatchSlot &first) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    float per[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
     auto stage2 = [&](int c) -> hipError_t {
         hipError_t r = hipSuccess;
         if (g->bc.terms & NM_T_DEMAG) r = launch_batch_demag(g->bc, g->slots_dev, c, 2, g->stream);
         if (r == hipSuccess) r = launch_batch_node(g->bc, g->slots_dev, c, 2, g->stream);
         return r;
     };
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-        const int c = 1 << k;
+    auto time_c = [&](int c, float *ms_out) -> hipError_t {
         float best = 1e30f;
-        e = stage2(c);   // warm-up
-        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-            e = hipEventRecord(e0, g->stream);
-            for (int q = 0; q < 4 && e == hipSuccess; ++q) e = stage2(c);
-            if (e == hipSuccess) e = hipEventRecord(e1, g->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
+        hipError_t r = stage2(c);   // warm-up
+        for (int rep = 0; rep < 3 && r == hipSuccess; ++rep) {
+            r = hipEventRecord(e0, g->stream);
+            for (int q = 0; q < 4 && r == hipSuccess; ++q) r = stage2(c);
+            if (r == hipSuccess) r = hipEventRecord(e1, g->stream);
+            if (r == hipSuccess) r = hipEventSynchronize(e1);
             float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
             best = std::fmin(best, ms);
         }
-        per[k] = best / (float)c;
+        *ms_out = best;
+        return r;
+    };
+    auto pick_width = [&](int *w, int nw) {
+        float t[3] = {1e30f, 1e30f, 1e30f};
+        for (int v = 0; v < nw && e == hipSuccess; ++v) {
+            *w = v;
+            e = time_c(1, &t[v]);
+        }
+        int b = 0;
+        for (int v = 1; v < nw; ++v)
+            if (t[v] < 0.95f * t[b]) b = v;
+        *w = b;
+    };
+    Shape sh{1, 0, 0};
+    if ((g->bc.terms & NM_T_DEMAG) && g->bc.P3 > 1) {
+        pick_width(&g->bc.tune_y, tile_widths(g->bc.P2));
+        pick_width(&g->bc.tune_z, tile_widths(g->bc.P3));
+    }
+    sh.tune_y = g->bc.tune_y;
+    sh.tune_z = g->bc.tune_z;
+    float per[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        e = time_c(1 << k, &per[k]);
+        per[k] /= (float)(1 << k);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    int cap = 1;
     if (e == hipSuccess) {
         int bk = 0;
         for (int k = 1; k < 5; ++k)
             if (per[k] < per[bk]) bk = k;
         int k = 0;
         while (k < bk && per[k] > 1.1f * per[bk]) ++k;
-        cap = 1 << k;
+        sh.cap = 1 << k;
     }
     (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(g_cap_mu);
-    g_cap[ck] = cap;
-    return cap;
+    g_cap[ck] = sh;
+    return sh;
 }
 
 // create the group of a class on the first admitted member (its descriptor
@@ -267,8 +310,8 @@ Group *group_create(nm_server *S, const ClassKey &key, const Solve *first, const
     g->bc.P2 = std::get<1>(key);
     g->bc.P3 = std::get<2>(key);
     g->bc.terms = std::get<3>(key);
-    g->bc.tune_y = first->mesh->tune_y;
-    g->bc.tune_z = first->mesh->tune_z;
+    g->bc.xt = std::get<4>(key);
+    g->bc.tune_y = g->bc.tune_z = 0;
     g->bc.maxN3 = g->bc.P3 > 1 ? g->bc.P3 / 2 : 1;
     // the window of the class's longest rows (N1 <= P1 / 2, N3 <= P3 / 2)
     g->bc.nit = window_items(g->bc.P1 / 2 + 1, g->bc.maxN3 + 1);
@@ -286,7 +329,10 @@ Group *group_create(nm_server *S, const ClassKey &key, const Solve *first, const
         group_destroy(g, S->pool);
         return nullptr;
     }
-    g->cap = tune_cap(S, g, desc);
+    const Shape sh = tune_shape(S, g, desc);
+    g->cap = sh.cap;
+    g->bc.tune_y = sh.tune_y;
+    g->bc.tune_z = sh.tune_z;
     BatchSlot empty{};
     g->next.assign(g->cap, empty);
     g->member.assign(g->cap, nullptr);
@@ -301,13 +347,25 @@ bool admit(nm_server *S, Solve *s) {
     s->nc = (long long)r.n[0] * r.n[1] * r.n[2];
     s->nn = (long long)(r.n[0] + 1) * (r.n[1] + 1) * (r.n[2] + 1);
     hipStream_t st = S->admit_stream;
-    if (dev_alloc((void **)&s->par_dev, sizeof(float) * 3 * s->nc, S->pool) != hipSuccess) return false;
+    size_t staged = 3 * (size_t)s->nc;
+    for (const std::vector<float> &v : s->opt) staged += v.size();
+    if (dev_alloc((void **)&s->par_dev, sizeof(float) * staged, S->pool) != hipSuccess) return false;
     if (dev_alloc((void **)&s->m_dev, sizeof(float) * 3 * s->nn, S->pool) != hipSuccess) return false;
     float *Ms = s->par_dev, *A = s->par_dev + s->nc, *al = s->par_dev + 2 * s->nc;
     const size_t cb = sizeof(float) * s->nc;
     if (hipMemcpyAsync(Ms, s->Ms.data(), cb, hipMemcpyHostToDevice, st) != hipSuccess) return false;
     if (hipMemcpyAsync(A, s->A.data(), cb, hipMemcpyHostToDevice, st) != hipSuccess) return false;
     if (hipMemcpyAsync(al, s->alpha.data(), cb, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+    const float *opt_dev[6] = {};
+    float *next = s->par_dev + 3 * s->nc;
+    for (int i = 0; i < 6; ++i) {
+        if (s->opt[i].empty()) continue;
+        if (hipMemcpyAsync(next, s->opt[i].data(), sizeof(float) * s->opt[i].size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+            return false;
+        opt_dev[i] = next;
+        next += s->opt[i].size();
+    }
     if (hipMemcpyAsync(s->m_dev, s->m0.data(), sizeof(float) * 3 * s->nn, hipMemcpyHostToDevice, st) != hipSuccess)
         return false;
     nm_mesh_desc d{};
@@ -322,8 +380,20 @@ bool admit(nm_server *S, Solve *s) {
     mat.A = A;
     mat.alpha = al;
     for (int k = 0; k < 3; ++k) mat.h_uniform[k] = r.h_uniform[k];
+    mat.Ku = opt_dev[0];
+    mat.easy = opt_dev[1];
+    mat.h_cell = opt_dev[2];
+    mat.D = opt_dev[3];
+    mat.dmi_type = r.dmi_type;
+    mat.Kc = opt_dev[4];
+    mat.cubic = opt_dev[5];
     if (nm_mesh_create(&d, &mat, &s->mesh) != NM_OK) return false;
-    if ((r.terms & NM_T_DEMAG) && nm_demag_tensor_init(s->mesh) != NM_OK) return false;
+    // the tensor without the per-mesh tile tuner: the group's kernels take
+    // the widths tuned for the whole class
+    if (r.terms & NM_T_DEMAG) {
+        if (build_kspace_tensor(s->mesh) != hipSuccess) return false;
+        s->mesh->tensor_ready = true;
+    }
     nm_integrator in{};
     in.method = NM_DP45;
     in.terms = r.terms;
@@ -334,7 +404,7 @@ bool admit(nm_server *S, Solve *s) {
     int batch = 0;
     if (step_begin(s->mesh, s->m_dev, &clk, &in, r.t_end, 1L << 40, &batch) != NM_OK) return false;
     // its group: one of the class with a free slot, else a new one
-    const ClassKey key = class_of(r);
+    const ClassKey key = class_of(r, s->mesh);
     Group *g = nullptr;
     int slot = -1;
     for (Group *x : S->groups) {
@@ -606,6 +676,12 @@ extern "C" nm_status nm_serve_submit(nm_server *S, const nm_solve_request *r, ui
                "nm_serve_submit: need t_end, dt0, rtol, atol > 0");
     NM_REQUIRE(!(r->terms & ~(unsigned)NM_T_ALL), NM_EINVAL, "nm_serve_submit: unknown term bits");
     NM_REQUIRE(r->n[2] <= 128, NM_EINVAL, "nm_serve_submit: the server takes at most 128 cells along z");
+    NM_REQUIRE((r->Ku == nullptr) == (r->easy == nullptr), NM_EINVAL,
+               "nm_serve_submit: Ku and easy must be given together");
+    NM_REQUIRE((r->Kc == nullptr) == (r->cubic == nullptr), NM_EINVAL,
+               "nm_serve_submit: Kc and cubic must be given together");
+    NM_REQUIRE(r->dmi_type == NM_DMI_INTERFACIAL || r->dmi_type == NM_DMI_BULK, NM_EINVAL,
+               "nm_serve_submit: unknown dmi_type");
     const size_t fp = solve_footprint(*r);
     NM_REQUIRE(fp > 0, NM_EINVAL, "nm_serve_submit: unsupported mesh size");
     Solve *s = new Solve();
@@ -619,6 +695,11 @@ extern "C" nm_status nm_serve_submit(nm_server *S, const nm_solve_request *r, ui
     s->alpha.assign(r->alpha, r->alpha + nc);
     s->m0.assign(r->m0, r->m0 + 3 * nn);
     s->req.Ms = s->req.A = s->req.alpha = s->req.m0 = nullptr;
+    for (int i = 0; i < 6; ++i) {
+        const float *src = r->*(kOpt[i].ptr);
+        if (src) s->opt[i].assign(src, src + kOpt[i].per_cell * nc);
+        s->req.*(kOpt[i].ptr) = nullptr;
+    }
     s->res.status = NM_ENOTREADY;
     s->res.t_submit = now_s();
     {

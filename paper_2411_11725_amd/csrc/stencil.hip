@@ -949,10 +949,16 @@ static void launch_node_t(nm_mesh *m, dim3 grid, const StencilParams &P, const S
     }
 }
 
+// the node kernel's term instantiation for parameters P (kXt* bits)
+static int params_xt(const StencilParams &P) {
+    return (P.Dc ? (P.dmi_bulk ? kXtDmiB : kXtDmiI) : 0) | (P.cubP ? kXtCubic : 0);
+}
+
+int node_xt(const nm_mesh *m, unsigned terms) { return params_xt(make_params(m, terms)); }
+
 template <int MODE, int STAGE>
 static void launch_node(nm_mesh *m, dim3 grid, const StencilParams &P, const StageArgs &S) {
-    const int xt = (P.Dc ? (P.dmi_bulk ? kXtDmiB : kXtDmiI) : 0) | (P.cubP ? kXtCubic : 0);
-    switch (xt) {
+    switch (params_xt(P)) {
         case 0: launch_node_t<MODE, STAGE, 0>(m, grid, P, S); break;
         case kXtDmiI: launch_node_t<MODE, STAGE, kXtDmiI>(m, grid, P, S); break;
         case kXtDmiB: launch_node_t<MODE, STAGE, kXtDmiB>(m, grid, P, S); break;
@@ -1094,12 +1100,12 @@ hipError_t launch_rk4_advance(nm_mesh *m) {
 // node kernel without the XCD renumbering, which changes only which block
 // takes which node range), so a solve's result does not depend on the other
 // solves of its group.
-template <int STAGE, int NIT>
+template <int STAGE, int NIT, int XT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
 k_node_b(const BatchSlot *__restrict__ slots) {
     const BatchSlot &d = slots[blockIdx.z];
     if (!d.active || blockIdx.x >= (unsigned)d.np) return;
-    node_body<kModeDP45, STAGE, NIT, 0>(d.P, d.S[STAGE], blockIdx.x);
+    node_body<kModeDP45, STAGE, NIT, XT>(d.P, d.S[STAGE], blockIdx.x);
 }
 
 __global__ void __launch_bounds__(1024) k_dp45_control_b(const BatchSlot *__restrict__ slots) {
@@ -1163,15 +1169,50 @@ void batch_slot_fill(const nm_mesh *m, unsigned terms, Ctrl *ctrl, float *mstate
     *out = d;
 }
 
+// the window sizes each term instantiation takes, as for a single mesh
+// (launch_node_t): interfacial DMI up to 10 items, the other extra terms none
+template <int STAGE, int XT>
+static void launch_node_bx(const BatchClass &bc, const BatchSlot *slots, int cap, hipStream_t st) {
+    const dim3 g(bc.node_blocks, 1, (unsigned)cap);
+    const int nit = (XT & ~kXtDmiI) ? 0 : bc.nit;
+    switch (nit) {
+        case 5:
+            if constexpr ((XT & ~kXtDmiI) == 0) {
+                hipLaunchKernelGGL((k_node_b<STAGE, 5, XT>), g, dim3(256), 0, st, slots);
+                break;
+            }
+            [[fallthrough]];
+        case 7:
+            if constexpr ((XT & ~kXtDmiI) == 0) {
+                hipLaunchKernelGGL((k_node_b<STAGE, 7, XT>), g, dim3(256), 0, st, slots);
+                break;
+            }
+            [[fallthrough]];
+        case 10:
+            if constexpr ((XT & ~kXtDmiI) == 0) {
+                hipLaunchKernelGGL((k_node_b<STAGE, 10, XT>), g, dim3(256), 0, st, slots);
+                break;
+            }
+            [[fallthrough]];
+        case 13:
+            if constexpr (XT == 0) {
+                hipLaunchKernelGGL((k_node_b<STAGE, 13, 0>), g, dim3(256), 0, st, slots);
+                break;
+            }
+            [[fallthrough]];
+        default: hipLaunchKernelGGL((k_node_b<STAGE, 0, XT>), g, dim3(256), 0, st, slots); break;
+    }
+}
+
 template <int STAGE>
 static void launch_node_b(const BatchClass &bc, const BatchSlot *slots, int cap, hipStream_t st) {
-    const dim3 g(bc.node_blocks, 1, (unsigned)cap);
-    switch (bc.nit) {
-        case 5: hipLaunchKernelGGL((k_node_b<STAGE, 5>), g, dim3(256), 0, st, slots); break;
-        case 7: hipLaunchKernelGGL((k_node_b<STAGE, 7>), g, dim3(256), 0, st, slots); break;
-        case 10: hipLaunchKernelGGL((k_node_b<STAGE, 10>), g, dim3(256), 0, st, slots); break;
-        case 13: hipLaunchKernelGGL((k_node_b<STAGE, 13>), g, dim3(256), 0, st, slots); break;
-        default: hipLaunchKernelGGL((k_node_b<STAGE, 0>), g, dim3(256), 0, st, slots); break;
+    switch (bc.xt) {
+        case 0: launch_node_bx<STAGE, 0>(bc, slots, cap, st); break;
+        case kXtDmiI: launch_node_bx<STAGE, kXtDmiI>(bc, slots, cap, st); break;
+        case kXtDmiB: launch_node_bx<STAGE, kXtDmiB>(bc, slots, cap, st); break;
+        case kXtCubic: launch_node_bx<STAGE, kXtCubic>(bc, slots, cap, st); break;
+        case kXtCubic | kXtDmiI: launch_node_bx<STAGE, kXtCubic | kXtDmiI>(bc, slots, cap, st); break;
+        default: launch_node_bx<STAGE, kXtCubic | kXtDmiB>(bc, slots, cap, st); break;
     }
 }
 

@@ -4,7 +4,10 @@ objective with respect to the per-cell applied-field map, for the full
 must reproduce), and, with --adjoint, the oracle's own discrete-adjoint
 gradient at the same cells.  Calls only the oracle and the input generator:
 
-    python tests/golden/make_magnonic_fd.py [--workers 6] [--adjoint]
+    python tests/golden/make_magnonic_fd.py [--workers 6] [--adjoint] [--resume LOG]
+
+--resume takes the progress lines ("run k/33: L = ...") an interrupted run
+of this script printed and recomputes only the runs missing there.
 
 Objective: L = -(1/K) sum_{k=1..K} mean over the output region's nodes (both
 node layers) of m_z(t_k)^2, K = 4000, dt = 5e-14 s; the output region is the
@@ -86,16 +89,23 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workers", type=int, default=6)
     ap.add_argument("--adjoint", action="store_true")
+    ap.add_argument("--resume", help="progress lines of an interrupted run")
     args = ap.parse_args()
     from multiprocessing import Pool
 
     cells = fd_cells()
     jobs = [None] + [(j, z, y, x, s * H_FD) for (j, z, y, x) in cells for s in (1.0, -1.0)]
+    vals = [None] * len(jobs)
+    if args.resume:
+        for line in open(args.resume):
+            if line.startswith("run ") and "/%d: L = " % len(jobs) in line:
+                k = int(line.split()[1].split("/")[0])
+                vals[k - 1] = float(line.split("=")[1])
+    todo = [k for k in range(len(jobs)) if vals[k] is None]
     with Pool(args.workers) as pool:
         adj = pool.apply_async(adjoint_gradient) if args.adjoint else None
-        vals = []
-        for k, v in enumerate(pool.imap(objective, jobs)):
-            vals.append(v)
+        for k, v in zip(todo, pool.imap(objective, [jobs[k] for k in todo])):
+            vals[k] = v
             print("run %d/%d: L = %.17e" % (k + 1, len(jobs), v), flush=True)
         dth = adj.get() if adj is not None else None
     L0 = vals[0]

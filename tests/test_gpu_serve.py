@@ -96,6 +96,65 @@ def test_served_solve_matches_the_oracle(n):
         assert np.abs(g - want).max() <= 1e-4
 
 
+def _material_requests():
+    """Requests carrying every optional cell array the server takes:
+    uniaxial Ku and easy axes, a per-cell field, DMI of both kinds, cubic
+    anisotropy (two members of each class, so the classes batch)."""
+    out = []
+    for i, (dmi, kind, cubic) in enumerate([(True, "interfacial", False), (True, "interfacial", False),
+                                            (True, "bulk", True), (True, "bulk", True),
+                                            (False, "interfacial", True), (False, "interfacial", False)]):
+        p = synth.small_random((12, 9, 3), (2e-9, 2.5e-9, 3e-9), seed=80 + i, dmi=dmi, dmi_type=kind,
+                               cubic=cubic, ku_range=(-2e5, 5e5))
+        out.append(p)
+    return out
+
+
+def test_served_material_terms_are_the_single_mesh_ones():
+    """A request's Ku/easy, h_cell, D (interfacial or bulk) and Kc/cubic reach
+    the batched kernels: each served result is bitwise nm_llg_step's."""
+    reqs = _material_requests()
+    mix, res = _serve(reqs, max_active=len(reqs), t_end=2e-12)
+    for p, m, r in zip(reqs, mix, res):
+        mesh = B.mesh_from_problem(p)
+        try:
+            mt = torch.as_tensor(p["m0"], device="cuda").contiguous()
+            clk = B.nm_clock(0.0, 1e-14, 0, 0, 0, 0.0)
+            B.nm_llg_step(mesh, mt, clk, B.NM_DP45, B.NM_T_ALL, t_end=2e-12)
+            single = mt.cpu().numpy().ravel()
+        finally:
+            B.nm_mesh_destroy(mesh)
+        assert np.array_equal(m, single)
+        assert (r.accepted, r.rejected) == (clk.accepted, clk.rejected)
+
+
+def test_served_material_solve_matches_the_oracle():
+    """Every term at once (bulk DMI, cubic and uniaxial anisotropy, per-cell
+    field): each node of the served result against the oracle's own run, to
+    1 ps (6 accepted steps, the last three at the stiff modes' stability
+    limit, before rounding noise there could change the step sequence)."""
+    p = _material_requests()[2]
+    (m,), (r,) = _serve([p], max_active=1, t_end=1e-12)
+    om, omat, m0 = to_oracle(p)
+    want, log = oracle.dp45_solve(om, omat, m0, 0.0, 1e-12, 1e-14, rtol=1e-5, atol=1e-5)
+    assert r.accepted == sum(1 for x in log if x[2])
+    assert np.abs(m.reshape(want.shape).astype(np.float64) - want).max() <= 1e-4
+
+
+def test_served_request_refuses_a_drive_and_half_given_arrays():
+    p = _material_requests()[0]
+    srv = B.nm_server_create(max_active=1)
+    try:
+        q = dict(p, drive_mask=np.ones_like(p["Ms"]), drive_amp=(1e3, 0.0, 0.0))
+        with pytest.raises(ValueError):
+            B.nm_serve_submit(srv, q)
+        with pytest.raises(B.NMError) as ei:
+            B.nm_serve_submit(srv, dict(p, easy=None))
+        assert ei.value.status == B.NM_EINVAL
+    finally:
+        B.nm_server_destroy(srv)
+
+
 def test_admission_respects_the_memory_budget():
     p = synth.make_problem((24, 24, 2), (3e-9,) * 3, 8e5, 1.3e-11, 0.1, seed=4)
     reqs = [dict(p, m0=synth.make_problem((24, 24, 2), (3e-9,) * 3, 8e5, 1.3e-11, 0.1, seed=10 + i)["m0"])
