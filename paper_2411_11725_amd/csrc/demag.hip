@@ -949,20 +949,19 @@ struct BatchLaunch {
 template <int L>
 void launch_xfwd_bt(const BatchLaunch &b) {
     constexpr int RB = x_rows_per_block(L);
-    const int n2max = b.bc.P2 > 1 ? b.bc.P2 / 2 : 1;
-    hipLaunchKernelGGL((k_xfwd_b<L>), dim3((n2max + RB - 1) / RB, b.bc.maxN3, b.cap), dim3(256), 0, b.st, b.slots,
+    hipLaunchKernelGGL((k_xfwd_b<L>), dim3((b.bc.gN2 + RB - 1) / RB, b.bc.gN3, b.cap), dim3(256), 0, b.st, b.slots,
                        b.stage, b.tw);
 }
 template <int L>
 void launch_xinv_bt(const BatchLaunch &b) {
     constexpr int RB = x_rows_per_block(L);
-    const int rows = (b.bc.P2 > 1 ? b.bc.P2 / 2 : 1) * b.bc.maxN3;
+    const int rows = b.bc.gN2 * b.bc.gN3;
     hipLaunchKernelGGL((k_xinv_b<L>), dim3((rows + RB - 1) / RB, 1, b.cap), dim3(256), 0, b.st, b.slots, b.tw);
 }
 template <int L, int DIR, int SH>
 void launch_ypass_bsh(const BatchLaunch &b) {
     constexpr int TT = fft2_threads(L), NPB = (256 / TT) >> SH;
-    const int ncols = b.bc.maxN3 * b.KP();
+    const int ncols = b.bc.gN3 * b.KP();
     hipLaunchKernelGGL((k_ypass_b<L, DIR, SH>), dim3((ncols + NPB - 1) / NPB, 3, b.cap), dim3(NPB * TT), 0, b.st,
                        b.slots, b.tw);
 }

@@ -106,8 +106,11 @@ struct BatchClass {
     unsigned terms;
     int xt;                      // node-kernel term instantiation (node_xt)
     int tune_y, tune_z;          // column-tile widths of the register FFT passes
-    int maxN3;                   // N3 <= P3 / 2 (1 for single-layer grids)
-    unsigned node_blocks;        // node-kernel blocks of the largest mesh
+    // grid extents, fitted to the members a group's graphs were captured
+    // for: the most rows (gN2) and cell layers (gN3) and node-kernel blocks
+    // of any of them; blocks past a member's own extent return at once
+    int gN2, gN3;
+    unsigned node_blocks;
 };
 
 struct ProfState;  // per-kernel event timing (measurement only)

@@ -22,6 +22,7 @@
 // which change only how columns are grouped into blocks).
 // Device memory of the solves comes from a pool (pool.hip): a finished solve
 // gives its buffers back without hipFree, which would wait for the device.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -68,8 +69,15 @@ struct Solve {
     float *par_dev = nullptr;
     Group *group = nullptr;
     int slot = -1;
+    Ctrl *own_ctrl = nullptr;   // the mesh's own controller while it uses the group's
     nm_solve_result res{};
     std::vector<float> m_out;
+    // retirement: the final state is copied into pinned staging on the
+    // retire stream; the solve is finished once ev has completed
+    float *pin = nullptr;
+    size_t pin_bytes = 0;
+    hipEvent_t ev = nullptr;
+    int status = NM_OK;
 };
 
 // optional cell arrays of a request: pointer and floats per cell
@@ -111,6 +119,7 @@ struct Group {
     // the blocks of its empty slots
     hipGraphExec_t gexec[5] = {};
     hipEvent_t ev = nullptr;          // end of the last replay and read-back
+    int sidx = 0;                     // stream of the replay in flight
     bool inflight = false, dirty = false, wait_admit = false;
 };
 
@@ -120,8 +129,11 @@ struct nm_server {
     nm_server_desc desc{};
     size_t budget = 0, used = 0;
     std::vector<hipStream_t> streams;
-    int next_stream = 0;
+    std::vector<int> load;            // replays in flight per stream
     hipStream_t admit_stream = nullptr;
+    hipStream_t retire_stream = nullptr;   // result read-back of finished solves
+    std::vector<Solve *> retiring;
+    std::multimap<size_t, float *> pinned;   // free pinned staging buffers by size
     hipEvent_t admit_ev = nullptr;    // end of the last admission set-up
     int device = 0;
     DevPool *pool = nullptr;
@@ -172,6 +184,7 @@ size_t solve_setup(const nm_solve_request &r) {
 
 // give back the resources of a solve whose stream work has completed
 void release(Solve *s, DevPool *pool) {
+    if (s->mesh && s->own_ctrl) s->mesh->ctrl = s->own_ctrl;
     if (s->mesh) mesh_release(s->mesh);
     dev_free(s->m_dev, pool);
     dev_free(s->par_dev, pool);
@@ -220,14 +233,17 @@ hipError_t enqueue_attempts(const Group *g, int slots, int attempts, hipStream_t
 
 // Batch shape of a class, from the stage-2 kernels (demag passes and the
 // node kernel) on slots that all describe the class's first member, timed
-// on the group's stream (a warm-up and three interleaved timings of 4
-// launches, the fastest kept): first the column-tile widths of the y passes
-// and the z convolution on one slot (the widest unless another is 5%
-// faster), then the slot count among 1, 2, 4, 8, 16: the least time per slot
-// wins unless a smaller count is within 10% of it (members of a fuller group
-// wait longer for each other).  Stage 2 writes only the first member's
-// stage buffers and FFT workspace, which its first real attempt rewrites
-// before reading.
+// on the group's stream (a warm-up and two timings of 2 launches, the faster
+// kept): first the column-tile widths of the y passes and the z convolution
+// on one slot (the widest unless another is 5% faster), then the slot count,
+// doubled from 1 while the time per slot falls by at least 10% (members of a
+// fuller group wait longer for each other; stopping at the first doubling
+// that does not pay keeps the timing of large classes, which fill the GPU
+// with one slot, to two launches' worth).  The timing runs inside the
+// stream of requests, so it is kept short: a class costs a few tens of
+// launches once per device.  Stage 2 writes only the first member's stage
+// buffers and FFT workspace, which its first real attempt rewrites before
+// reading.
 Shape tune_shape(nm_server *S, Group *g, const BatchSlot &first) {
     const auto ck = std::make_tuple(g->key, S->device);
     {
@@ -250,9 +266,9 @@ Shape tune_shape(nm_server *S, Group *g, const BatchSlot &first) {
     auto time_c = [&](int c, float *ms_out) -> hipError_t {
         float best = 1e30f;
         hipError_t r = stage2(c);   // warm-up
-        for (int rep = 0; rep < 3 && r == hipSuccess; ++rep) {
+        for (int rep = 0; rep < 2 && r == hipSuccess; ++rep) {
             r = hipEventRecord(e0, g->stream);
-            for (int q = 0; q < 4 && r == hipSuccess; ++q) r = stage2(c);
+            for (int q = 0; q < 2 && r == hipSuccess; ++q) r = stage2(c);
             if (r == hipSuccess) r = hipEventRecord(e1, g->stream);
             if (r == hipSuccess) r = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -280,25 +296,69 @@ Shape tune_shape(nm_server *S, Group *g, const BatchSlot &first) {
     }
     sh.tune_y = g->bc.tune_y;
     sh.tune_z = g->bc.tune_z;
-    float per[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < 5 && e == hipSuccess; ++k) {
-        e = time_c(1 << k, &per[k]);
-        per[k] /= (float)(1 << k);
+    float prev = 0.f;
+    for (int k = 0; (1 << k) <= kMaxCap && e == hipSuccess; ++k) {
+        float t = 0.f;
+        e = time_c(1 << k, &t);
+        t /= (float)(1 << k);
+        if (e != hipSuccess || (k > 0 && t > 0.9f * prev)) break;
+        sh.cap = 1 << k;
+        prev = t;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (e == hipSuccess) {
-        int bk = 0;
-        for (int k = 1; k < 5; ++k)
-            if (per[k] < per[bk]) bk = k;
-        int k = 0;
-        while (k < bk && per[k] > 1.1f * per[bk]) ++k;
-        sh.cap = 1 << k;
-    }
     (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(g_cap_mu);
     g_cap[ck] = sh;
     return sh;
+}
+
+// the stream with the fewest replays in flight (lowest index on ties)
+int least_loaded(const nm_server *S) {
+    int b = 0;
+    for (int i = 1; i < (int)S->load.size(); ++i)
+        if (S->load[i] < S->load[b]) b = i;
+    return b;
+}
+
+// pinned staging of at least `bytes`: a free buffer of the server, else a new
+// one rounded up to a power of two (kept until the server is destroyed)
+float *pinned_get(nm_server *S, size_t bytes, size_t *got) {
+    auto it = S->pinned.lower_bound(bytes);
+    if (it != S->pinned.end()) {
+        float *p = it->second;
+        *got = it->first;
+        S->pinned.erase(it);
+        return p;
+    }
+    size_t sz = 4096;
+    while (sz < bytes) sz <<= 1;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) return nullptr;
+    *got = sz;
+    return static_cast<float *>(p);
+}
+
+// Grid extents of a group: its launches cover the largest rows, layers and
+// node ranges of the members its graphs were captured for, and the LDS
+// window of their longest rows (a longer window holds the same values at the
+// same places, so a member's result depends on neither).
+struct Extents {
+    int N2 = 0, N3 = 0, NX = 0, NZ = 0;
+    int np = 0;
+};
+void grow(Extents *x, const BatchSlot &d) {
+    x->N2 = std::max(x->N2, d.N2);
+    x->N3 = std::max(x->N3, d.N3);
+    x->NX = std::max(x->NX, d.N1 + 1);
+    x->NZ = std::max(x->NZ, d.NZ);
+    x->np = std::max(x->np, d.np);
+}
+void set_extents(Group *g, const Extents &x) {
+    g->bc.gN2 = x.N2;
+    g->bc.gN3 = x.N3;
+    g->bc.node_blocks = (unsigned)x.np;
+    g->bc.nit = window_items(x.NX, x.NZ);
 }
 
 // create the group of a class on the first admitted member (its descriptor
@@ -312,12 +372,11 @@ Group *group_create(nm_server *S, const ClassKey &key, const Solve *first, const
     g->bc.terms = std::get<3>(key);
     g->bc.xt = std::get<4>(key);
     g->bc.tune_y = g->bc.tune_z = 0;
-    g->bc.maxN3 = g->bc.P3 > 1 ? g->bc.P3 / 2 : 1;
-    // the window of the class's longest rows (N1 <= P1 / 2, N3 <= P3 / 2)
-    g->bc.nit = window_items(g->bc.P1 / 2 + 1, g->bc.maxN3 + 1);
-    const long long nmax = (long long)(g->bc.P1 / 2 + 1) * (g->bc.P2 / 2 + 1) * (g->bc.maxN3 + 1);
-    g->bc.node_blocks = (unsigned)((nmax + 255) / 256);
-    g->stream = S->streams[S->next_stream++ % S->streams.size()];
+    Extents x{};
+    grow(&x, desc);
+    set_extents(g, x);
+    g->sidx = least_loaded(S);
+    g->stream = S->streams[g->sidx];
     bool ok = dev_alloc((void **)&g->slots_dev, sizeof(BatchSlot) * kMaxCap, S->pool) == hipSuccess &&
               dev_alloc((void **)&g->ctrl_dev, sizeof(Ctrl) * kMaxCap, S->pool) == hipSuccess &&
               hipHostMalloc((void **)&g->slots_pin, sizeof(BatchSlot) * kMaxCap, hipHostMallocDefault) == hipSuccess &&
@@ -432,6 +491,13 @@ bool admit(nm_server *S, Solve *s) {
         return false;
     if (hipEventRecord(S->admit_ev, st) != hipSuccess) return false;
     batch_slot_fill(s->mesh, r.terms, g->ctrl_dev + slot, s->m_dev, &desc);
+    // from here on the mesh's own kernels (a group with this member alone
+    // replays them) use the group's controller of the slot too, and the
+    // class's column-tile widths
+    s->own_ctrl = s->mesh->ctrl;
+    s->mesh->ctrl = g->ctrl_dev + slot;
+    s->mesh->tune_y = g->bc.tune_y;
+    s->mesh->tune_z = g->bc.tune_z;
     g->next[slot] = desc;
     g->member[slot] = s;
     g->state[slot] = kJoining;
@@ -443,7 +509,11 @@ bool admit(nm_server *S, Solve *s) {
     return true;
 }
 
-// a finished member: result, state read back, resources released, slot freed
+// a finished member leaves its slot at once; its final state is copied to
+// pinned staging on the retire stream (after the replay that finished it,
+// which has completed), and the solve is finished by retire() once that copy
+// has landed, so the scheduler never waits for a copy or for other groups'
+// work on a replay stream
 void complete(nm_server *S, Group *g, int slot) {
     Solve *s = g->member[slot];
     const Ctrl &C = g->ctrl_pin[slot];
@@ -451,24 +521,70 @@ void complete(nm_server *S, Group *g, int slot) {
     s->res.accepted = C.accepted;
     s->res.rejected = C.rejected;
     s->res.rhs_evals = C.rhs_evals + 1;   // + the first stage
-    int status = C.status == NM_ENONFINITE ? NM_ENONFINITE : C.status == NM_ESTEPSIZE ? NM_ESTEPSIZE : NM_OK;
-    s->m_out.resize(3 * s->nn);
-    hipError_t e = hipMemcpyAsync(s->m_out.data(), s->m_dev, sizeof(float) * 3 * s->nn, hipMemcpyDeviceToHost,
-                                  g->stream);
-    if (e == hipSuccess) e = hipEventRecord(g->ev, g->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(g->ev);
-    if (e != hipSuccess) status = NM_EHIP;
+    s->status = C.status == NM_ENONFINITE ? NM_ENONFINITE : C.status == NM_ESTEPSIZE ? NM_ESTEPSIZE : NM_OK;
+    const size_t bytes = sizeof(float) * 3 * s->nn;
+    hipError_t e = hipEventCreateWithFlags(&s->ev, hipEventDisableTiming);
+    if (e == hipSuccess) {
+        s->pin = pinned_get(S, bytes, &s->pin_bytes);
+        if (!s->pin) e = hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(s->pin, s->m_dev, bytes, hipMemcpyDeviceToHost, S->retire_stream);
+    if (e == hipSuccess) e = hipEventRecord(s->ev, S->retire_stream);
+    if (e != hipSuccess) {
+        // fall back to a blocking copy so the result is not lost
+        (void)hipGetLastError();
+        s->m_out.resize(3 * s->nn);
+        if (hipMemcpy(s->m_out.data(), s->m_dev, bytes, hipMemcpyDeviceToHost) != hipSuccess) s->status = NM_EHIP;
+        if (s->pin) S->pinned.emplace(s->pin_bytes, s->pin);
+        s->pin = nullptr;
+        if (s->ev) (void)hipEventDestroy(s->ev);
+        s->ev = nullptr;
+    }
     g->member[slot] = nullptr;
     g->state[slot] = kFree;
     g->next[slot].active = 0;
     g->dirty = true;
-    finish(S, s, status, true);
+    S->retiring.push_back(s);
+}
+
+// finish the retiring solves whose read-back has landed; true if any did
+bool retire(nm_server *S) {
+    bool any = false;
+    for (size_t i = 0; i < S->retiring.size();) {
+        Solve *s = S->retiring[i];
+        if (s->ev) {
+            const hipError_t q = hipEventQuery(s->ev);
+            if (q == hipErrorNotReady) {
+                (void)hipGetLastError();
+                ++i;
+                continue;
+            }
+            if (q == hipSuccess) {
+                s->m_out.assign(s->pin, s->pin + 3 * s->nn);
+            } else {
+                s->status = NM_EHIP;
+            }
+            (void)hipEventDestroy(s->ev);
+            s->ev = nullptr;
+            S->pinned.emplace(s->pin_bytes, s->pin);
+            s->pin = nullptr;
+        }
+        S->retiring[i] = S->retiring.back();
+        S->retiring.pop_back();
+        finish(S, s, s->status, true);
+        any = true;
+    }
+    return any;
 }
 
 // issue one replay of an idle group: new descriptors, the graph, the
 // controllers' read-back
 hipError_t issue(nm_server *S, Group *g) {
     hipError_t e = hipSuccess;
+    // the group's previous replay has completed, so its next one may go to
+    // any stream: the one with the fewest replays in flight
+    g->sidx = least_loaded(S);
+    g->stream = S->streams[g->sidx];
     if (g->dirty) {
         std::memcpy(g->slots_pin, g->next.data(), sizeof(BatchSlot) * g->cap);
         e = hipMemcpyAsync(g->slots_dev, g->slots_pin, sizeof(BatchSlot) * g->cap, hipMemcpyHostToDevice, g->stream);
@@ -479,6 +595,50 @@ hipError_t issue(nm_server *S, Group *g) {
     if (e == hipSuccess && g->wait_admit) {
         e = hipStreamWaitEvent(g->stream, S->admit_ev, 0);
         g->wait_admit = false;
+    }
+    // a group with one member replays that member's own single-mesh graph
+    // (the kernels nm_llg_step runs, with its exact grids and parameters in
+    // the kernel arguments) on the chosen stream; the batched kernels, which
+    // first read each slot's descriptor from device memory, only where they
+    // serve several members
+    int occupied = 0, only = -1;
+    for (int i = 0; i < g->cap; ++i)
+        if (g->state[i] != kFree) {
+            ++occupied;
+            only = i;
+        }
+    if (occupied == 1) {
+        Solve *s1 = g->member[only];
+        s1->mesh->stream = g->stream;
+        const int A = S->desc.attempts_per_launch;
+        if (e == hipSuccess) e = step_batch(s1->mesh, s1->m_dev, NM_DP45, g->bc.terms, A, A);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(g->ctrl_pin, g->ctrl_dev, sizeof(Ctrl) * g->cap, hipMemcpyDeviceToHost, g->stream);
+        if (e == hipSuccess) e = hipEventRecord(g->ev, g->stream);
+        if (e == hipSuccess) {
+            g->inflight = true;
+            S->load[g->sidx] += 1;
+        }
+        return e;
+    }
+    // refit the grids to the members: grow when a member exceeds them, shrink
+    // when they cover more than 5/4 of the node blocks needed; either way the
+    // captured graphs are dropped and recaptured on demand
+    {
+        Extents x{};
+        for (int i = 0; i < g->cap; ++i)
+            if (g->state[i] != kFree) grow(&x, g->next[i]);
+        const BatchClass &c = g->bc;
+        const bool over = x.N2 > c.gN2 || x.N3 > c.gN3 || x.np > (int)c.node_blocks ||
+                          window_items(x.NX, x.NZ) != c.nit;
+        const bool slack = 4 * (long long)c.node_blocks > 5LL * x.np;
+        if (x.np > 0 && (over || slack)) {
+            for (hipGraphExec_t &ge : g->gexec) {
+                if (ge) (void)hipGraphExecDestroy(ge);
+                ge = nullptr;
+            }
+            set_extents(g, x);
+        }
     }
     // the smallest power of two of slots that covers every occupied slot
     int hi = 0;
@@ -501,7 +661,10 @@ hipError_t issue(nm_server *S, Group *g) {
     if (e == hipSuccess)
         e = hipMemcpyAsync(g->ctrl_pin, g->ctrl_dev, sizeof(Ctrl) * g->cap, hipMemcpyDeviceToHost, g->stream);
     if (e == hipSuccess) e = hipEventRecord(g->ev, g->stream);
-    if (e == hipSuccess) g->inflight = true;
+    if (e == hipSuccess) {
+        g->inflight = true;
+        S->load[g->sidx] += 1;
+    }
     return e;
 }
 
@@ -570,6 +733,7 @@ void run(nm_server *S) {
                     continue;
                 }
                 g->inflight = false;
+                S->load[g->sidx] -= 1;
                 progressed = true;
                 if (q != hipSuccess) {
                     fail_group(S, g);
@@ -587,6 +751,7 @@ void run(nm_server *S) {
             }
             progressed = true;
         }
+        if (retire(S)) progressed = true;
         if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
 }
@@ -619,17 +784,20 @@ extern "C" nm_status nm_server_create(const nm_server_desc *desc, nm_server **ou
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) freeb = 0;
     S->budget = desc->hbm_budget ? desc->hbm_budget : (size_t)(0.8 * (double)freeb);
     bool ok = true;
-    for (int i = 0; i < desc->n_streams + 1 && ok; ++i) {
+    for (int i = 0; i < desc->n_streams + 2 && ok; ++i) {
         hipStream_t st = nullptr;
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
         if (!ok) break;
         if (i < desc->n_streams) S->streams.push_back(st);
-        else S->admit_stream = st;
+        else if (i == desc->n_streams) S->admit_stream = st;
+        else S->retire_stream = st;
     }
+    S->load.assign(S->streams.size(), 0);
     ok = ok && hipEventCreateWithFlags(&S->admit_ev, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
         if (S->admit_stream) (void)hipStreamDestroy(S->admit_stream);
+        if (S->retire_stream) (void)hipStreamDestroy(S->retire_stream);
         if (S->admit_ev) (void)hipEventDestroy(S->admit_ev);
         delete S;
         set_error("nm_server_create: stream creation failed");
@@ -651,6 +819,13 @@ extern "C" nm_status nm_server_destroy(nm_server *S) {
     S->worker.join();
     for (hipStream_t x : S->streams) (void)hipStreamSynchronize(x);
     (void)hipStreamSynchronize(S->admit_stream);
+    (void)hipStreamSynchronize(S->retire_stream);
+    for (Solve *s : S->retiring) {
+        release(s, S->pool);
+        if (s->ev) (void)hipEventDestroy(s->ev);
+        delete s;
+    }
+    for (auto &kv : S->pinned) (void)hipHostFree(kv.second);
     for (Group *g : S->groups) {
         for (Solve *s : g->member)
             if (s) {
@@ -663,6 +838,7 @@ extern "C" nm_status nm_server_destroy(nm_server *S) {
     for (auto &kv : S->done) delete kv.second;
     for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
     (void)hipStreamDestroy(S->admit_stream);
+    (void)hipStreamDestroy(S->retire_stream);
     (void)hipEventDestroy(S->admit_ev);
     pool_destroy(S->pool);
     delete S;

@@ -545,23 +545,27 @@ __device__ __forceinline__ void node_body(const StencilParams &P, const StageArg
     if (MODE == kModeDP45 && STAGE == 7) reduce_partial(sq, mf, nf, S.partials + lb);
 }
 
-template <int MODE, int STAGE, int NIT, int XT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
-k_node(StencilParams P, StageArgs S) {
-    // consecutive block numbers on one XCD walk groups of kNodeZGroup
-    // 256-node ranges (a few rows of one node layer) layer by layer: the next
-    // layer's blocks find two of their three window layers and one of their
-    // two cell layers in that XCD's L2, while each block still reads
-    // contiguous rows.  zcols: ranges per layer; ranges past zcols NZ keep
-    // their place.
-    unsigned lb = xcd_block(blockIdx.x, gridDim.x);
+// The node range of block b of nb (the mesh's node blocks): consecutive
+// block numbers on one XCD walk groups of kNodeZGroup 256-node ranges (a few
+// rows of one node layer) layer by layer: the next layer's blocks find two of
+// their three window layers and one of their two cell layers in that XCD's
+// L2, while each block still reads contiguous rows.  zcols: ranges per
+// layer; ranges past zcols NZ keep their place.
+__device__ __forceinline__ unsigned node_range(unsigned b, unsigned nb, const StencilParams &P) {
+    unsigned lb = xcd_block(b, nb);
     if (kNodeZGroup > 0 && lb < P.zcols * (unsigned)P.NZ) {
         const unsigned gi = lb / (kNodeZGroup * (unsigned)P.NZ);
         const unsigned w = min(kNodeZGroup, P.zcols - gi * kNodeZGroup);
         const unsigned rem = lb - gi * kNodeZGroup * (unsigned)P.NZ;
         lb = (rem / w) * P.zcols + gi * kNodeZGroup + rem % w;
     }
-    node_body<MODE, STAGE, NIT, XT>(P, S, lb);
+    return lb;
+}
+
+template <int MODE, int STAGE, int NIT, int XT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
+k_node(StencilParams P, StageArgs S) {
+    node_body<MODE, STAGE, NIT, XT>(P, S, node_range(blockIdx.x, gridDim.x, P));
 }
 
 dim3 stencil_grid(const nm_mesh *m) { return dim3((unsigned)((m->n_nodes + 255) / 256)); }
@@ -1096,16 +1100,18 @@ hipError_t launch_rk4_advance(nm_mesh *m) {
 
 // ------------------------------------------------------ batched launches
 // One launch covers every slot of a batch group (grid z = slot).  Each block
-// runs exactly the code of the single-mesh kernel on its slot's buffers (the
-// node kernel without the XCD renumbering, which changes only which block
-// takes which node range), so a solve's result does not depend on the other
-// solves of its group.
+// runs exactly the code of the single-mesh kernel on its slot's buffers, so a
+// solve's result does not depend on the other solves of its group.  The
+// first np blocks of a slot (its own node blocks) take node ranges as the
+// single-mesh launch does; the dispatcher deals them over the XCDs in the
+// same rotation, shifted by the slot's place in the grid, which keeps each
+// XCD on one contiguous range.
 template <int STAGE, int NIT, int XT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NIT > 0 ? NM_NODE_WAVES : 2, NIT > 0 ? NM_NODE_WAVES : 2)))
 k_node_b(const BatchSlot *__restrict__ slots) {
     const BatchSlot &d = slots[blockIdx.z];
     if (!d.active || blockIdx.x >= (unsigned)d.np) return;
-    node_body<kModeDP45, STAGE, NIT, XT>(d.P, d.S[STAGE], blockIdx.x);
+    node_body<kModeDP45, STAGE, NIT, XT>(d.P, d.S[STAGE], node_range(blockIdx.x, (unsigned)d.np, d.P));
 }
 
 __global__ void __launch_bounds__(1024) k_dp45_control_b(const BatchSlot *__restrict__ slots) {
