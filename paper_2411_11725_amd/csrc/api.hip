@@ -332,7 +332,11 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     }
     hipStream_t st = m->stream;
     float *Atmp = m->A2;  // A is staged in A2 and doubled in place
-    e = hipMemcpyAsync(m->Ms, mat->Ms, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
+    // the spectrum workspace starts zeroed: no pass writes the pitch's pad
+    // columns (K1 <= kx < KP), and the column passes' pad lanes read them in
+    // place, finite and in the same cache lines as their rows' last columns
+    e = hipMemsetAsync(m->spec, 0, sizeof(float2) * (size_t)s.spec, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->Ms, mat->Ms, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess) e = hipMemcpyAsync(Atmp, mat->A, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);
     if (e == hipSuccess && m->has_anis)
         e = hipMemcpyAsync(m->Ku, mat->Ku, sizeof(float) * nc, hipMemcpyDeviceToDevice, st);

@@ -288,11 +288,12 @@ __device__ __forceinline__ void ypass_body(float2 *__restrict__ spec, const floa
     const int tid = threadIdx.x, b = tid % NPB, j = tid / NPB;
     const int col = bx * NPB + b;
     const int zc = col / KP, kx = col - zc * KP;
-    const bool valid = col < N3 * KP && kx < K1;
+    const bool inrow = col < N3 * KP, valid = inrow && kx < K1;
     // 32-bit byte offsets within one component (N3 P2 KP complex < 4 GiB);
-    // pad / past-the-end lanes read column 0
+    // pad lanes (K1 <= kx < KP) read their own zeroed column, past-the-end
+    // lanes column 0
     float2 *cb = spec + (long long)comp * N3 * L * KP;
-    const unsigned oc = valid ? 8u * ((unsigned)zc * (unsigned)(L * KP) + (unsigned)kx) : 0u;
+    const unsigned oc = inrow ? 8u * ((unsigned)zc * (unsigned)(L * KP) + (unsigned)kx) : 0u;
     const unsigned rs = 8u * (unsigned)KP;   // row stride
     float2 v[1][E];
     if constexpr (DIR < 0) {
@@ -506,8 +507,10 @@ __device__ __forceinline__ void zconv_r_body(float2 *__restrict__ spec, const fl
     const int slot = pos / KP, kxp = pos - slot * KP;
     const int kyp = slot == 0 ? 0 : slot >= P2 - 1 ? P2 / 2 : (slot & 1) ? (slot + 1) / 2 : P2 - (slot + 1) / 2;
     const int col = kyp * KP + kxp;
-    const bool valid = pos < P2 * KP && kxp < K1;
-    const int colc = valid ? col : 0;   // pad / past-the-end lanes read column 0
+    const bool inrange = pos < P2 * KP, valid = inrange && kxp < K1;
+    // pad lanes (K1 <= kx < KP) read their own zeroed column, past-the-end
+    // lanes column 0
+    const int colc = inrange ? col : 0;
     const long long plane = (long long)P2 * KP;
     // inputs z = (j + T a) + L1 n2, nonzero only for n2 < L2 / 2; 32-bit byte
     // offsets within one component (N3 P2 KP complex < 4 GiB)
