@@ -149,7 +149,7 @@ static size_t footprint(const Sizes &s) {
     b += sizeof(float) * s.nn * 3;                              // inv_mass, alpha_n, gp_n
     b += sizeof(float2) * s.spec + sizeof(float) * s.tensor;
     b += sizeof(float) * 4 * s.nc;                              // demag cell field / source
-    b += sizeof(float) * 3 * s.nn * 10;                         // y[2], acc, k[7]
+    b += sizeof(float) * 3 * s.nn * 11;                         // y[2], acc, k[7], RK4 compensation
     b += sizeof(Ctrl) + sizeof(ErrPartial) * s.partials + sizeof(double) * (5 * s.eblocks + 5);
     return b;
 }
@@ -191,7 +191,7 @@ static void free_mesh(nm_mesh *m) {
     if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
     void *ptrs[] = {m->Ms, m->A2, m->Ku, m->easy, m->h_cell, m->drive_mask, m->Dc, m->wc, m->inv_mass,
                     m->alpha_n, m->gp_n, m->spec, m->tensor, m->hd, m->y[0], m->y[1], m->acc,
-                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat, m->cubP};
+                    m->ctrl, m->partials, m->ered, m->cellP, m->wstat, m->cubP, m->mlo};
     for (void *p : ptrs) dev_free(p, m->pool);
     for (int j = 0; j < 7; ++j) dev_free(m->k[j], m->pool);
     host_free(m->ctrl_host, m->pool);
@@ -320,6 +320,7 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
     if (e == hipSuccess) e = dalloc(m, &m->y[1], 3 * nn);
     if (e == hipSuccess) e = dalloc(m, &m->acc, 3 * nn);
     for (int j = 0; j < 7 && e == hipSuccess; ++j) e = dalloc(m, &m->k[j], 3 * nn);
+    if (e == hipSuccess) e = dalloc(m, &m->mlo, 3 * nn);
     if (e == hipSuccess) e = dalloc(m, &m->ctrl, 1);
     if (e == hipSuccess) e = dalloc(m, &m->partials, s.partials);
     if (e == hipSuccess) e = dalloc(m, &m->ered, 5 * s.eblocks + 5);
@@ -507,7 +508,7 @@ extern "C" nm_status nm_energy(nm_mesh *m, const float *mag, unsigned terms, dou
 namespace {
 
 hipError_t stage(nm_mesh *m, unsigned terms, int mode, int s, const float *in, float *y_next,
-                 float *mstate) {
+                 float *mstate, float *lo = nullptr) {
     if (terms & NM_T_DEMAG) {
         hipError_t e = demag_forward_conv_inverse_ctrl(m, in, m->ctrl, (terms & NM_T_ZEEMAN) ? 2 : 1);
         if (e != hipSuccess) return e;
@@ -519,6 +520,7 @@ hipError_t stage(nm_mesh *m, unsigned terms, int mode, int s, const float *in, f
     sp.y_next = y_next;
     sp.mstate = mstate;
     sp.use_ctrl = true;
+    sp.lo = lo;
     return launch_stencil(m, terms, sp);
 }
 
@@ -528,8 +530,9 @@ hipError_t dp45_stage(nm_mesh *m, unsigned terms, int s, const float *in, float 
     return stage(m, terms, kModeDP45, s, in, s < 7 ? m->y[(s + 1) % 2] : nullptr, mstate);
 }
 
+// the state update (stage 4) carries its rounding error in m->mlo
 hipError_t rk4_stage(nm_mesh *m, unsigned terms, int s, const float *in, float *y_next, float *mstate) {
-    return stage(m, terms, kModeRK4, s, in, y_next, mstate);
+    return stage(m, terms, kModeRK4, s, in, y_next, mstate, s == 4 ? m->mlo : nullptr);
 }
 
 }  // namespace
@@ -539,6 +542,11 @@ namespace nm {
 // Controller initialisation from a kernel argument: the values travel with
 // the launch, so a call may return while it is still queued (an asynchronous
 // copy from host memory would race with the next call filling that memory).
+__global__ void k_zero(float *__restrict__ p, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
 __global__ void k_ctrl_set(Ctrl *C, Ctrl v) {
     const unsigned *src = reinterpret_cast<const unsigned *>(&v);
     unsigned *dst = reinterpret_cast<unsigned *>(C);
@@ -585,6 +593,13 @@ nm_status step_begin(nm_mesh *m, float *mag, const nm_clock *clk, const nm_integ
     // RK4 knows its step count: never capture more steps than the call needs
     int b = 16;
     if (in->method == NM_RK4) {
+        // the compensation carries on only where the last RK4 call on this
+        // mesh ended: the same state buffer at the clock it left behind
+        if (!(m->lo_valid && m->lo_mag == mag && m->lo_t == clk->t)) {
+            const long long n3 = 3 * m->n_nodes;
+            hipLaunchKernelGGL(k_zero, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, m->stream, m->mlo, n3);
+            NM_HIP(hipGetLastError(), "nm_llg_step");
+        }
         const double span = (t_end - clk->t) / clk->dt;
         long need = (long)std::ceil(span * (1.0 - 1e-12));
         if (need > max_steps) need = max_steps;
@@ -733,8 +748,12 @@ extern "C" nm_status nm_llg_step(nm_mesh *m, float *mag, nm_clock *clk, const nm
         clk->t = t;
         clk->accepted += acc;
         clk->rhs_evals += 4 * acc;
+        m->lo_valid = true;
+        m->lo_mag = mag;
+        m->lo_t = t;
         return NM_OK;
     } else {
+        m->lo_valid = false;   // DP45 moves the state without the compensation
         long long seen = -1;
         int b = batch_for(std::fmin((double)max_steps, std::ceil((t_end - clk->t) / clk->dt * (1.0 + 1e-9))), batch);
         for (;;) {

@@ -67,6 +67,7 @@ struct StencilParams {
 struct StageArgs {
     const float *in;
     float *out, *y_next, *mstate, *acc;
+    float *lo;               // RK4: the state's compensation (low part), or null
     float *k[7];
     const Ctrl *ctrl;
     ErrPartial *partials;
@@ -204,6 +205,13 @@ struct nm_mesh {
 
     // integrator buffers
     float *y[2], *acc, *k[7];
+    // RK4 state compensation: the low part of a two-sum of every state update,
+    // carried from step to step (and from call to call while the caller
+    // continues the same state: same buffer, t where the last call ended)
+    float *mlo;
+    const float *lo_mag;
+    double lo_t;
+    bool lo_valid;
     nm::Ctrl *ctrl;          // device controller state
     nm::Ctrl *ctrl_host;     // pinned mirror for read-back
     int64_t n_active;        // nodes with positive lumped mass
@@ -295,6 +303,7 @@ struct StageSpec {
     double t0;               // start-of-step time when ctrl is null
     double dt0;              // step when ctrl is null (RK4 / adjoint recompute)
     bool use_ctrl;           // stepping modes: t, dt from the device controller
+    float *lo;               // RK4 stage 4: compensation of the state (null: plain update)
 };
 
 hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp);

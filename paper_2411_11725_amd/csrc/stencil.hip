@@ -184,6 +184,11 @@ __device__ __forceinline__ void node_body(const StencilParams &P, const StageArg
 #pragma unroll
         for (int c = 0; c < 3; ++c) ac[c] = ldo(S.acc, oc[c]);
     }
+    float lo[3] = {0.f, 0.f, 0.f};
+    if (MODE == kModeRK4 && STAGE == 4 && S.lo) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lo[c] = ldo(S.lo, oc[c]);
+    }
     if (MODE == kModeDP45) {
 #pragma unroll
         for (int j = 0; j < NK; ++j)
@@ -513,7 +518,18 @@ __device__ __forceinline__ void node_body(const StencilParams &P, const StageArg
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (STAGE == 4) {
-                    sto(S.mstate, oc[c], ms[c] + c6 * (ac[c] + f[c]));
+                    const float inc = c6 * (ac[c] + f[c]);
+                    if (S.lo) {
+                        // two-sum of state and increment (plus the carried low
+                        // part): the rounding error of the float32 update is
+                        // kept, not lost, so it does not accumulate over steps
+                        const float b = inc + lo[c];
+                        const float sum = ms[c] + b, bv = sum - ms[c];
+                        sto(S.mstate, oc[c], sum);
+                        sto(S.lo, oc[c], (ms[c] - (sum - bv)) + (b - bv));
+                    } else {
+                        sto(S.mstate, oc[c], ms[c] + inc);
+                    }
                 } else {
                     sto(S.acc, oc[c], STAGE == 1 ? f[c] : ac[c] + 2.f * f[c]);
                     sto(S.y_next, oc[c], ms[c] + cy * f[c]);
@@ -980,6 +996,7 @@ hipError_t launch_stencil(nm_mesh *m, unsigned terms, const StageSpec &sp) {
     S.y_next = sp.y_next;
     S.mstate = sp.mstate;
     S.acc = m->acc;
+    S.lo = sp.lo;
     S.t0 = sp.t0;
     S.dt0 = sp.dt0;
     S.ctrl = sp.use_ctrl ? m->ctrl : nullptr;

@@ -5,9 +5,11 @@ must reproduce), and, with --adjoint, the oracle's own discrete-adjoint
 gradient at the same cells.  Calls only the oracle and the input generator:
 
     python tests/golden/make_magnonic_fd.py [--workers 6] [--adjoint] [--resume LOG]
+                                            [--adjoint-from FILE]
 
 --resume takes the progress lines ("run k/33: L = ...") an interrupted run
-of this script printed and recomputes only the runs missing there.
+of this script printed and recomputes only the runs missing there;
+--adjoint-from reuses the oracle-adjoint column of an earlier output.
 
 Objective: L = -(1/K) sum_{k=1..K} mean over the output region's nodes (both
 node layers) of m_z(t_k)^2, K = 4000, dt = 5e-14 s; the output region is the
@@ -38,7 +40,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 OUT = os.path.join(HERE, "magnonic_fd.txt")
 NSTEPS = 4000
 DT = 5e-14
-H_FD = 1e-3 / (4e-7 * np.pi)      # 1e-3 mT in A/m
+H_FD = 1e-6 / (4e-7 * np.pi)      # 1e-3 mT (1e-6 T) in A/m
 REGION = (slice(None), slice(56, 72), slice(192, 208))
 
 
@@ -90,6 +92,8 @@ def main():
     ap.add_argument("--workers", type=int, default=6)
     ap.add_argument("--adjoint", action="store_true")
     ap.add_argument("--resume", help="progress lines of an interrupted run")
+    ap.add_argument("--adjoint-from", help="an earlier output of this script whose oracle-adjoint column "
+                                          "(independent of h) is reused instead of recomputed")
     args = ap.parse_args()
     from multiprocessing import Pool
 
@@ -108,6 +112,17 @@ def main():
             vals[k] = v
             print("run %d/%d: L = %.17e" % (k + 1, len(jobs), v), flush=True)
         dth = adj.get() if adj is not None else None
+    if args.adjoint_from:
+        dth = np.zeros((3, 1, 128, 256))
+        got = 0
+        for line in open(args.adjoint_from):
+            w = line.split()
+            if len(w) == 8 and not w[0].startswith("#"):
+                dth[int(w[0]), int(w[1]), int(w[2]), int(w[3])] = float(w[7])
+                got += 1
+            elif w and w[0] == "adjoint_max_abs":
+                adj_max = float(w[1])
+        assert got == len(cells)
     L0 = vals[0]
     lines = ["# magnonic strip 256x128x1 (synth.magnonic), RK4 dt 5e-14 s x 4000, field map theta = 0;",
              "# L = -(1/4000) sum_k mean over nodes [:, 56:72, 192:208] of m_z(t_k)^2;",
@@ -123,7 +138,7 @@ def main():
             row += " % .17e" % dth[j, z, y, x]
         lines.append(row)
     if dth is not None:
-        lines.append("adjoint_max_abs %.17e" % np.abs(dth).max())
+        lines.append("adjoint_max_abs %.17e" % (adj_max if args.adjoint_from else np.abs(dth).max()))
     with open(OUT, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
