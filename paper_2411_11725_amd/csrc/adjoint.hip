@@ -21,12 +21,14 @@
 
 namespace nm {
 
-// u = df/dH^T w, vjp = df/dm^T w at (y, H); v = M^-1 u, vsum += v
+// u = df/dH^T w, vjp = df/dm^T w at (y, H); v = M^-1 u, vsum += v (in
+// float64: the field-map gradient sums hundreds of stage terms of both signs
+// per segment, and their cancellation would amplify float32 rounding)
 __global__ void __launch_bounds__(256)
 k_adj_vjp(const float *__restrict__ y, const float *__restrict__ H, const float *__restrict__ w,
           const float *__restrict__ inv_mass, const float *__restrict__ alpha_n,
           const float *__restrict__ gp_n, float *__restrict__ v, float *__restrict__ vjp,
-          float *__restrict__ vsum, long long nn) {
+          double *__restrict__ vsum, long long nn) {
     const long long n = (long long)blockIdx.x * 256 + threadIdx.x;
     if (n >= nn) return;
     float m[3], h[3], c[3];
@@ -48,23 +50,28 @@ k_adj_vjp(const float *__restrict__ y, const float *__restrict__ H, const float 
         const float vv = u * im;
         vjp[k * nn + n] = dm;
         v[k * nn + n] = vv;
-        if (vsum) vsum[k * nn + n] += vv;
+        if (vsum) vsum[k * nn + n] += (double)vv;
     }
 }
 
-// g = vjp + M Hv (= J^T w); lam_acc += g; w_next = cl lam + cg g (or lam_out = lam_acc)
+// g = vjp + M Hv (= J^T w); lam_acc += g; w_next = cl lam + cg g (or lam_out = lam_acc).
+// lam_lo: the rounding errors of the lam_acc additions (two-sums), carried
+// through the segment and folded into lambda at its end, so that lambda's
+// many small increments over a segment do not lose their low bits
 __global__ void __launch_bounds__(256)
 k_adj_combine(const float *__restrict__ vjp, const float *__restrict__ Hv,
               const float *__restrict__ inv_mass, const float *__restrict__ lam,
               float *__restrict__ lam_acc, float *__restrict__ w_next, float cl, float cg,
-              float *__restrict__ lam_out, int has_lin, long long nn) {
+              float *__restrict__ lam_out, float *__restrict__ lam_lo, int has_lin, long long nn) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= 3 * nn) return;
     const long long n = i % nn;
     const float im = inv_mass[n];
     const float M = im > 0.f ? 1.f / im : 0.f;
     const float g = vjp[i] + (has_lin ? M * Hv[i] : 0.f);
-    const float acc = lam_acc[i] + g;
+    const float a = lam_acc[i];
+    const float acc = a + g, bv = acc - a;
+    lam_lo[i] += (a - (acc - bv)) + (g - bv);
     if (lam_out) {
         lam_out[i] = acc;
     } else {
@@ -196,6 +203,10 @@ __global__ void __launch_bounds__(256) k_vcopy(float *__restrict__ y, const floa
     if (i < n) y[i] = x[i];
 }
 
+__global__ void __launch_bounds__(256) k_vadd(float *__restrict__ y, const float *__restrict__ x, long long n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] += x[i];
+}
 __global__ void __launch_bounds__(256) k_vzero(float *__restrict__ y, long long n) {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i < n) y[i] = 0.f;
@@ -215,8 +226,9 @@ __global__ void __launch_bounds__(256) k_add_dl(float *__restrict__ y, const Adj
 
 // grad_c += mu0 Ms_c V/8 sum_{n in c} v_n (the 4 nodes of a cell under the
 // film basis, NZ = 1: the field map enters each of them once)
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_cell_gather(const float *__restrict__ v, const float *__restrict__ wc, float *__restrict__ grad,
+k_cell_gather(const T *__restrict__ v, const float *__restrict__ wc, float *__restrict__ grad,
               int N1, int N2, int N3, int NZ) {
     const long long nc = (long long)N1 * N2 * N3;
     const long long c = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -225,13 +237,13 @@ k_cell_gather(const float *__restrict__ v, const float *__restrict__ wc, float *
     const long long nn = (long long)NX * NY * NZ;
     const int cx = (int)(c % N1), cy = (int)((c / N1) % N2), cz = (int)(c / ((long long)N1 * N2));
     for (int k = 0; k < 3; ++k) {
-        float s = 0.f;
+        T s = 0;
         for (int b = 0; b < 8; ++b) {
             if (cz + (b >> 2) >= NZ) continue;
             const long long nb = ((long long)(cz + (b >> 2)) * NY + cy + ((b >> 1) & 1)) * NX + cx + (b & 1);
             s += v[k * nn + nb];
         }
-        grad[k * nc + c] += wc[c] * s;
+        grad[k * nc + c] += (float)(wc[c] * s);
     }
 }
 
@@ -257,7 +269,7 @@ using namespace nm;
     } while (0)
 
 // workspace: nsteps states + 15 nodal vectors, then the segment slots
-static long long adj_vectors(int nsteps) { return (long long)nsteps + 15; }
+static long long adj_vectors(int nsteps) { return (long long)nsteps + 18; }
 static size_t adj_slot_offset(const nm_mesh *m, int nsteps) {
     const size_t b = sizeof(float) * 3 * (size_t)m->n_nodes * (size_t)adj_vectors(nsteps);
     return (b + 255) / 256 * 256;
@@ -309,7 +321,7 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
                "terms only (not the quartic cubic anisotropy)");
     const long long nn = m->n_nodes, n3 = 3 * nn;
     float *S = work;                                   // states m_0 .. m_{nsteps-1}
-    float *V = work + (long long)nsteps * n3;          // 15 scratch vectors
+    float *V = work + (long long)nsteps * n3;          // 18 scratch vectors
     float *lam = V + 14 * n3;                          // lambda inside the segment
     AdjSlots *slots = reinterpret_cast<AdjSlots *>(reinterpret_cast<char *>(work) + adj_slot_offset(m, nsteps));
     const unsigned lin = terms & ~(unsigned)NM_T_ZEEMAN;
@@ -317,7 +329,10 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
     const char *who = "nm_adjoint_step";
     const bool gather = grad_hcell != nullptr;
     const bool has_dl = dl_dm != nullptr;
-    float *vsum = V + 12 * n3;
+    // the field-map density in float64: two vectors' room from vector 15 on,
+    // at an even float offset (work is 256-byte aligned; vector 17 is spare)
+    float *vsum_f = V + 15 * n3 + (((long long)nsteps + 15) * n3 & 1);
+    double *vsum = reinterpret_cast<double *>(vsum_f);
 
     // the segment body: recorded once per (length, terms, dt, loss sampling,
     // workspace) as a HIP graph and replayed for every segment; its inputs
@@ -327,14 +342,18 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
         float *Y[5] = {nullptr, nullptr, V + 0 * n3, V + 1 * n3, V + 2 * n3};   // y2, y3, y4
         float *Hs[5] = {nullptr, V + 3 * n3, V + 4 * n3, V + 5 * n3, V + 6 * n3};
         float *w = V + 7 * n3, *v = V + 8 * n3, *vjp = V + 9 * n3, *Hv = V + 10 * n3;
-        float *lacc = V + 11 * n3, *wn = V + 13 * n3;
+        float *lacc = V + 11 * n3, *wn = V + 13 * n3, *lam_lo = V + 12 * n3;
         hipError_t e = hipSuccess;
 #define NM_ADJ(call)                    \
     do {                                \
         if (e == hipSuccess) e = (call); \
     } while (0)
-        // forward recompute of the segment's states from the checkpoint
+        // forward recompute of the segment's states from the checkpoint,
+        // with the compensated state update of the forward run (its carried
+        // low part starts at zero at the checkpoint; the mesh's buffer is
+        // borrowed, so a later RK4 call restarts its own compensation)
         hipLaunchKernelGGL(k_copy_m0, g3, dim3(256), 0, st, S, slots, n3);
+        hipLaunchKernelGGL(k_vzero, g3, dim3(256), 0, st, m->mlo, n3);
         for (int j = 0; j + 1 < nsteps; ++j) {
             float *cur = S + (long long)(j + 1) * n3;
             hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, cur, S + (long long)j * n3, n3);
@@ -343,6 +362,7 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
             sp.mode = kModeRK4;
             sp.use_ctrl = true;
             sp.mstate = cur;
+            sp.lo = m->mlo;   // read by stage 4 only
             const float *ins[4] = {cur, m->y[0], m->y[1], m->y[0]};
             float *outs[4] = {m->y[0], m->y[1], m->y[0], nullptr};
             for (int s = 1; s <= 4; ++s) {
@@ -354,7 +374,9 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
                 NM_ADJ(launch_stencil(m, terms, sp));
             }
         }
-        if (gather) hipLaunchKernelGGL(k_vzero, g3, dim3(256), 0, st, vsum, n3);
+        if (gather)
+            hipLaunchKernelGGL(k_vzero, dim3((unsigned)((2 * n3 + 255) / 256)), dim3(256), 0, st, vsum_f, 2 * n3);
+        hipLaunchKernelGGL(k_vzero, g3, dim3(256), 0, st, lam_lo, n3);
         if (has_dl && nsteps % dl_every == 0)
             hipLaunchKernelGGL(k_add_dl, g3, dim3(256), 0, st, lam, slots,
                                (long long)(nsteps / dl_every - 1) * n3, n3);
@@ -385,13 +407,14 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
                 }
                 // s > 1: w_{s-1} = cl lam + cg J_s^T w_s; s = 1: lam <- lam_acc + J_1^T w_1
                 hipLaunchKernelGGL(k_adj_combine, g3, dim3(256), 0, st, vjp, Hv, m->inv_mass, lam, lacc, wn,
-                                   cl[s], cg[s], s == 1 ? lam : nullptr, lin ? 1 : 0, nn);
+                                   cl[s], cg[s], s == 1 ? lam : nullptr, lam_lo, lin ? 1 : 0, nn);
                 if (s > 1) std::swap(w, wn);
             }
             if (has_dl && j > 0 && j % dl_every == 0)
                 hipLaunchKernelGGL(k_add_dl, g3, dim3(256), 0, st, lam, slots, (long long)(j / dl_every - 1) * n3,
                                    n3);
         }
+        hipLaunchKernelGGL(k_vadd, g3, dim3(256), 0, st, lam, lam_lo, n3);   // fold the low part in
 #undef NM_ADJ
         return e == hipSuccess ? hipGetLastError() : e;
     };
@@ -432,9 +455,10 @@ extern "C" nm_status nm_adjoint_step(nm_mesh *m, const float *m0, double t0, dou
     }
     hipLaunchKernelGGL(k_vcopy, g3, dim3(256), 0, st, lambda, lam, n3);
     if (gather)
-        hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
-                           m->wc, grad_hcell, m->N1, m->N2, m->N3, m->NZ);
+        hipLaunchKernelGGL(k_cell_gather<double>, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st,
+                           (const double *)vsum, m->wc, grad_hcell, m->N1, m->N2, m->N3, m->NZ);
     NM_HIP(hipGetLastError(), who);
+    m->lo_valid = false;   // the recompute used the RK4 compensation buffer
     return NM_OK;
 }
 
@@ -539,7 +563,7 @@ extern "C" nm_status nm_adjoint_continuous(nm_mesh *m, float *mag, double t_end,
         for (int j = 0; j < nsteps; ++j) NM_HIP(hipGraphLaunch(m->cadj_gexec, st), who);
     }
     if (gather)
-        hipLaunchKernelGGL(k_cell_gather, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
+        hipLaunchKernelGGL(k_cell_gather<float>, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, st, vsum,
                            m->wc, grad_hcell, m->N1, m->N2, m->N3, m->NZ);
     NM_HIP(hipGetLastError(), who);
     return NM_OK;
