@@ -438,7 +438,7 @@ def main():
     B.nm_llg_step(mesh, m, clk, B.NM_DP45, terms, t_end=t_cap, max_steps=args.warmup)
     torch.cuda.synchronize()
     # timed region: the stepping loop replays one captured HIP graph per batch
-    rhs0, acc0 = clk.rhs_evals, clk.accepted
+    rhs0, acc0, rej0 = clk.rhs_evals, clk.accepted, clk.rejected
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     B.nm_llg_step(mesh, m, clk, B.NM_DP45, terms, t_end=t_cap, max_steps=args.steps)
@@ -447,6 +447,9 @@ def main():
     print("timed region: %.3f s" % elapsed, file=sys.stderr, flush=True)
     rhs = clk.rhs_evals - rhs0
     steps = clk.accepted - acc0
+    # graph replays of the region: 16 attempts each, then powers of two
+    attempts = steps + clk.rejected - rej0
+    replays = attempts // 16 + bin(attempts % 16).count("1")
     value = nc * rhs / elapsed
     # per-kernel region: the same number of steps with every kernel bracketed
     # by timing-only HIP events on the mesh stream (direct launches)
@@ -480,6 +483,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": traffic},
         "kernels": kernels,
+        "timing": "value: the timed region of K accepted DP45 steps, replayed as captured HIP graphs (about %d "
+                  "replays, each followed by a read-back of the device controller); kernels and roofline: a "
+                  "second region of the same K steps with direct launches, every kernel bracketed by HIP "
+                  "events on the mesh stream" % replays,
     }
     if args.adjoint_steps > 0:
         out["adjoint"] = adjoint_bench(B, synth, args.adjoint_steps, 100)
