@@ -83,16 +83,34 @@ enum {
                         * array laid out as [3][1][N2+1][N1+1] */
 };
 
+/* Optional device-memory hooks: when alloc is set, every device buffer of
+ * the mesh (its state, stage and FFT workspaces, the k-space tensor and the
+ * tensor set-up's float64 temporaries) comes from alloc(bytes, ctx) and goes
+ * back through free(ptr, ctx) when the mesh is destroyed (the temporaries at
+ * the end of nm_demag_tensor_init), so that a framework's caching allocator
+ * (torch's, for instance) owns the memory.  The memory is used on the mesh's
+ * stream only; alloc returns NULL on failure (nm_mesh_create then fails with
+ * NM_ENOMEM) and must return 256-byte aligned pointers.  Both are called from
+ * the thread that calls nm_mesh_create / nm_demag_tensor_init /
+ * nm_mesh_destroy.  A zero-initialised struct selects the library's own
+ * allocation. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} nm_allocator;
+
 /* Grid and constants.  n[k] >= 2 for k = 0, 1 and n[2] >= 1 (= 1 for the
  * film basis); every padded FFT length (next power of two >= 2 n[k] - 1)
  * must not exceed 1024.  A zero-initialised descriptor selects the 3D
- * basis. */
+ * basis and the library's own allocation. */
 typedef struct {
     int n[3];          /* cells N1, N2, N3 */
     double h[3];       /* cell edges (m), > 0 */
     double gamma;      /* reduced gyromagnetic ratio, m/(A s), > 0 */
     void *stream;      /* hipStream_t for all work on this mesh */
     int basis;         /* NM_BASIS_3D or NM_BASIS_FILM */
+    nm_allocator alloc; /* optional device-memory hooks (see above) */
 } nm_mesh_desc;
 
 /* Cell-wise material parameters (Eqs. ms_discrete, cell_basis) and applied

@@ -31,9 +31,48 @@ EXPORTS = [
 PROF_SLOTS = ["xfwd", "yfwd", "conv", "yinv", "xinv", "stencil", "control", "other"]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class nm_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", c_void_p)]
+
+
 class nm_mesh_desc(ctypes.Structure):
     _fields_ = [("n", c_int * 3), ("h", c_double * 3), ("gamma", c_double), ("stream", c_void_p),
-                ("basis", c_int)]
+                ("basis", c_int), ("alloc", nm_allocator)]
+
+
+class TorchAllocator:
+    """nm_allocator hooks backed by torch's caching allocator on one device
+    and stream: a mesh created with it keeps its device memory in torch's
+    pool (torch.cuda.memory_allocated counts it).  Keep the object alive as
+    long as the meshes made with it (the binding keeps it with each mesh)."""
+
+    def __init__(self, device=None, stream=None):
+        import torch
+        self.device = torch.cuda.current_device() if device is None else torch.device(device).index
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        self.live = {}
+
+        def _alloc(nbytes, ctx):
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+            self.live[p] = int(nbytes)
+            return p
+
+        def _free(ptr, ctx):
+            if ptr in self.live:
+                del self.live[ptr]
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self._c = nm_allocator(ALLOC_FN(_alloc), FREE_FN(_free), None)
+
+    def hooks(self):
+        return self._c
+
+
+_mesh_allocators = {}   # mesh handle -> allocator object kept alive with the mesh
 
 
 class nm_material(ctypes.Structure):
@@ -146,20 +185,25 @@ def _stream_handle(stream):
 def nm_mesh_create(n, h, gamma, Ms, A, alpha, Ku=None, easy=None, h_cell=None,
                    h_uniform=(0.0, 0.0, 0.0), drive_mask=None, drive_amp=(0.0, 0.0, 0.0),
                    drive_freq=0.0, drive_phase=0.0, stream=None, basis=NM_BASIS_3D, D=None,
-                   dmi_type=NM_DMI_INTERFACIAL, Kc=None, cubic=None):
-    """Create a mesh from float32 device tensors (copied by the library)."""
+                   dmi_type=NM_DMI_INTERFACIAL, Kc=None, cubic=None, allocator=None):
+    """Create a mesh from float32 device tensors (copied by the library).
+    allocator: optional TorchAllocator (or any object with hooks()) whose
+    nm_allocator hooks provide the mesh's device memory."""
     desc = nm_mesh_desc((c_int * 3)(*n), (c_double * 3)(*h), float(gamma), _stream_handle(stream),
-                        int(basis))
+                        int(basis), allocator.hooks() if allocator is not None else nm_allocator())
     mat = nm_material(_ptr(Ms), _ptr(A), _ptr(alpha), _ptr(Ku), _ptr(easy), _ptr(h_cell),
                       (c_float * 3)(*h_uniform), _ptr(drive_mask), (c_float * 3)(*drive_amp),
                       float(drive_freq), float(drive_phase), _ptr(D), int(dmi_type), _ptr(Kc), _ptr(cubic))
     out = c_void_p()
     _check(lib().nm_mesh_create(ctypes.byref(desc), ctypes.byref(mat), ctypes.byref(out)))
+    if allocator is not None:
+        _mesh_allocators[out.value] = allocator
     return out
 
 
 def nm_mesh_destroy(mesh):
     _check(lib().nm_mesh_destroy(mesh))
+    _mesh_allocators.pop(mesh.value if isinstance(mesh, c_void_p) else mesh, None)
 
 
 def nm_mesh_info(mesh):
@@ -317,8 +361,10 @@ def nm_last_error():
 
 
 # ------------------------------------------------------------ marshalling
-def mesh_from_problem(p, device="cuda", stream=None, tensor=True):
-    """Upload a problem dict (see synth.make_problem) and create its mesh."""
+def mesh_from_problem(p, device="cuda", stream=None, tensor=True, allocator=None):
+    """Upload a problem dict (see synth.make_problem) and create its mesh
+    (allocator: optional hooks for the mesh's device memory, see
+    TorchAllocator)."""
     import torch
 
     def dev(a):
@@ -335,7 +381,7 @@ def mesh_from_problem(p, device="cuda", stream=None, tensor=True):
                           basis=NM_BASIS_FILM if p.get("basis", "3d") == "film" else NM_BASIS_3D,
                           D=arrays["D"],
                           dmi_type=NM_DMI_BULK if p.get("dmi_type", "interfacial") == "bulk" else NM_DMI_INTERFACIAL,
-                          Kc=arrays["Kc"], cubic=arrays["cubic"])
+                          Kc=arrays["Kc"], cubic=arrays["cubic"], allocator=allocator)
     if tensor:
         nm_demag_tensor_init(mesh)
     return mesh

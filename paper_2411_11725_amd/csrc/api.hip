@@ -195,6 +195,7 @@ static void free_mesh(nm_mesh *m) {
     for (void *p : ptrs) dev_free(p, m->pool);
     for (int j = 0; j < 7; ++j) dev_free(m->k[j], m->pool);
     host_free(m->ctrl_host, m->pool);
+    if (m->owns_pool) pool_destroy(m->pool);
     delete m;
 }
 
@@ -224,6 +225,8 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
         NM_REQUIRE(std::isfinite(d->h[k]) && d->h[k] > 0.0, NM_EINVAL, "nm_mesh_create: h must be > 0");
     NM_REQUIRE(std::isfinite(d->gamma) && d->gamma > 0.0, NM_EINVAL, "nm_mesh_create: gamma must be > 0");
     NM_REQUIRE(mat->Ms && mat->A && mat->alpha, NM_EINVAL, "nm_mesh_create: Ms, A and alpha are required");
+    NM_REQUIRE((d->alloc.alloc == nullptr) == (d->alloc.free == nullptr), NM_EINVAL,
+               "nm_mesh_create: allocator hooks alloc and free must be given together");
     NM_REQUIRE((mat->Ku == nullptr) == (mat->easy == nullptr), NM_EINVAL,
                "nm_mesh_create: Ku and easy must be given together");
     NM_REQUIRE((mat->Kc == nullptr) == (mat->cubic == nullptr), NM_EINVAL,
@@ -294,7 +297,8 @@ extern "C" nm_status nm_mesh_create(const nm_mesh_desc *d, const nm_material *ma
         m->gw = T.gw;
     }
 
-    m->pool = thread_pool();
+    m->owns_pool = d->alloc.alloc != nullptr;
+    m->pool = m->owns_pool ? pool_create_user(d->alloc) : thread_pool();
     hipError_t e = hipGetDevice(&m->device);
     // the per-device twiddle table is built here, never inside a graph capture
     if (e == hipSuccess && !twiddles(m->device)) e = hipErrorOutOfMemory;

@@ -350,10 +350,11 @@ hipError_t build_kspace_tensor_with(nm_mesh *m, void *work) {
     return e != hipSuccess ? e : e2;
 }
 
-// the same with the temporaries taken from the calling thread's pool, if it
-// has one (no device-wide wait when they are given back), else hipMalloc
+// the same with the temporaries taken from the mesh's allocator hooks if it
+// has them, else from the calling thread's pool if it has one (no
+// device-wide wait when they are given back), else hipMalloc
 hipError_t build_kspace_tensor(nm_mesh *m) {
-    DevPool *pool = thread_pool();
+    DevPool *pool = m->owns_pool ? m->pool : thread_pool();
     void *work = nullptr;
     hipError_t e = dev_alloc(&work, kspace_scratch_bytes(m), pool);
     if (e != hipSuccess) return e;

@@ -152,6 +152,7 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 struct DevPool;
 constexpr size_t kPoolHostBlock = 4096;   // pinned host blocks recycled by a pool
 DevPool *pool_create();
+DevPool *pool_create_user(const nm_allocator &a);   // every block from the caller's hooks
 void pool_destroy(DevPool *P);
 void set_thread_pool(DevPool *P);   // allocations of the calling thread come from P
 DevPool *thread_pool();
@@ -173,6 +174,7 @@ struct nm_mesh {
     hipStream_t stream;
     int device;
     nm::DevPool *pool;       // where the buffers came from (NULL: hipMalloc)
+    bool owns_pool;          // pool wraps the caller's allocator hooks (freed with the mesh)
 
     // owned material copies (cell arrays) and derived quantities
     float *Ms, *A2, *Ku, *easy, *h_cell, *drive_mask;

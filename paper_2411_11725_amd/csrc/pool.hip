@@ -10,6 +10,7 @@
 // tensor set-up temporaries) then come from it, and a mesh remembers the pool
 // its buffers came from.  Pinned host blocks for the step-controller mirror
 // are recycled the same way.
+#include <cstdint>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -30,11 +31,18 @@ struct DevPool {
     std::vector<void *> host_free;                      // recycled pinned blocks
     std::vector<void *> host_all;
     size_t chunk_bytes = size_t(512) << 20;
+    nm_allocator user{};   // caller's hooks: every block comes from user.alloc
 };
 
 static thread_local DevPool *t_pool = nullptr;
 
 DevPool *pool_create() { return new DevPool(); }
+
+DevPool *pool_create_user(const nm_allocator &a) {
+    DevPool *P = new DevPool();
+    P->user = a;
+    return P;
+}
 
 void pool_destroy(DevPool *P) {
     if (!P) return;
@@ -52,6 +60,15 @@ hipError_t dev_alloc(void **p, size_t bytes, DevPool *P) {
     bytes = (bytes + kAlign - 1) / kAlign * kAlign;
     if (bytes == 0) bytes = kAlign;
     if (!P) return hipMalloc(p, bytes);
+    if (P->user.alloc) {   // the caller's allocator, block by block
+        void *q = P->user.alloc(bytes, P->user.ctx);
+        if (!q || (reinterpret_cast<uintptr_t>(q) % kAlign) != 0) {
+            if (q) P->user.free(q, P->user.ctx);
+            return hipErrorOutOfMemory;
+        }
+        *p = q;
+        return hipSuccess;
+    }
     std::lock_guard<std::mutex> lk(P->mu);
     for (size_t ci = 0; ci < P->chunks.size(); ++ci) {
         auto &fr = P->chunks[ci].free;
@@ -83,6 +100,10 @@ void dev_free(void *p, DevPool *P) {
         (void)hipFree(p);
         return;
     }
+    if (P->user.alloc) {
+        P->user.free(p, P->user.ctx);
+        return;
+    }
     std::lock_guard<std::mutex> lk(P->mu);
     auto it = P->live.find((char *)p);
     if (it == P->live.end()) return;
@@ -106,7 +127,7 @@ void dev_free(void *p, DevPool *P) {
 }
 
 hipError_t host_alloc(void **p, size_t bytes, DevPool *P) {
-    if (!P) return hipHostMalloc(p, bytes, hipHostMallocDefault);
+    if (!P || P->user.alloc) return hipHostMalloc(p, bytes, hipHostMallocDefault);
     if (bytes > kPoolHostBlock) return hipErrorInvalidValue;
     std::lock_guard<std::mutex> lk(P->mu);
     if (!P->host_free.empty()) {
@@ -121,7 +142,7 @@ hipError_t host_alloc(void **p, size_t bytes, DevPool *P) {
 
 void host_free(void *p, DevPool *P) {
     if (!p) return;
-    if (!P) {
+    if (!P || P->user.alloc) {
         (void)hipHostFree(p);
         return;
     }
