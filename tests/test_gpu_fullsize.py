@@ -244,9 +244,9 @@ def test_magnonic_full_size_gradient_against_finite_differences():
     against the oracle's float64 discrete-adjoint gradient at the same cells,
     relative error |g - g_ref| / max(|g_ref|, 1e-3 max|g_ref|) <= 1e-4; the
     oracle's gradient is pinned by float64 central differences of its L
-    (h = 1e-3 mT) to 1e-5 in the same measure (8.6e-6 at worst, at a cell
-    next to the output region where L is close to quadratic in the field
-    and the difference carries its largest truncation term)."""
+    (h = 1e-3 mT) to 5e-6 in the same measure (1.2e-6 at worst, at a cell
+    whose gradient is 1.6e-17, where the two values of L differ in their
+    tenth digit and float64 rounding of L is what remains)."""
     from paper_2411_11725_amd.adjoint import LLGTrajectory
 
     L0, rows, adj_max = _magnonic_golden()
@@ -275,7 +275,7 @@ def test_magnonic_full_size_gradient_against_finite_differences():
     scale = np.abs(ref).max()
     floor = lambda v: max(abs(v), 1e-3 * scale)
     # the oracle's adjoint against the central differences
-    assert all(abs(a - f) <= 1e-5 * floor(a) for a, f in zip(ref, fd))
+    assert all(abs(a - f) <= 5e-6 * floor(a) for a, f in zip(ref, fd))
     errs = [abs(g[r[0], r[1], r[2], r[3]] - a) / floor(a) for r, a in zip(rows, ref)]
     worst = max(errs)
     wr = rows[int(np.argmax(errs))]

@@ -213,3 +213,30 @@ def test_macrospin_field_gradient_is_the_closed_form():
     assert abs(mT[2].mean() - np.cos(theta)) <= 1e-10
     want = np.sin(theta) * 2 * u * alpha * gp * T / (1 + u * u)
     assert abs(dth[2].sum() - want) <= 1e-7 * abs(want)
+
+
+def test_magnonic_full_size_adjoint_matches_stored_central_differences():
+    """The stored full-size record of the inverse-problem workload (256 x 128
+    x 1 strip, 4000 RK4 steps; written by tests/golden/make_magnonic_fd.py
+    from oracle runs only): at each of the 16 cells the oracle's discrete
+    adjoint gradient agrees with the float64 central differences of its own
+    objective, |g - g_fd| / max(|g|, 1e-3 max|g|) <= 5e-6, and the
+    differences were taken with h = 1e-3 mT."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "magnonic_fd.txt")
+    rows, header = [], ""
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                header += line
+            elif line[0].isdigit():
+                rows.append([float(v) for v in line.split()])
+    assert "h = 1e-3 mT = 7.9577471546e-01 A/m" in header
+    assert len(rows) == 16 and all(len(r) == 8 for r in rows)
+    h = 1e-6 / (4e-7 * np.pi)
+    fd = np.array([r[4] for r in rows])
+    # the stored difference quotient is the stored pair of objective values
+    assert np.allclose(fd, np.array([(r[5] - r[6]) / (2 * h) for r in rows]), rtol=1e-9, atol=0)
+    adj = np.array([r[7] for r in rows])
+    floor = np.maximum(np.abs(adj), 1e-3 * np.abs(adj).max())
+    assert (np.abs(adj - fd) / floor).max() <= 5e-6
