@@ -149,6 +149,20 @@ def test_padded_lengths_up_to_1024():
         assert rel_l2(g, oracle.heff(om, omat, om0, DEMAG)) <= 1e-5, n
 
 
+@pytest.mark.parametrize("n", [(5, 300, 1), (9, 200, 1), (40, 100, 1), (3, 129, 1), (70, 128, 1)])
+def test_film_long_columns_match_oracle(n):
+    """Single-layer films with the film convolution's long y columns (padded
+    lengths 256, 512, 1024: four, two and one column per block), ragged kx
+    column counts, and data rows up to exactly half the padded length (128
+    of 256)."""
+    p = synth.small_random(n, (3e-9, 2.5e-9, 3e-9), seed=47, anis=False, field=False)
+    g = _field(p, DEMAG)
+    om, omat, om0 = to_oracle(p)
+    want = oracle.heff(om, omat, om0, DEMAG)
+    assert rel_l2(g, want) <= 1e-5, n
+    assert np.abs(g - want).max() <= 1e-4 * np.abs(want).max(), n
+
+
 def test_results_are_bitwise_reproducible():
     p = synth.small_random((13, 7, 3), (2e-9,) * 3, seed=47)
     a = _field(p, ALL_TERMS)

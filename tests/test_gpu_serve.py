@@ -96,6 +96,26 @@ def test_served_solve_matches_the_oracle(n):
         assert np.abs(g - want).max() <= 1e-4
 
 
+def test_served_long_films_are_the_single_mesh_ones():
+    """Films with 512- and 1024-point y columns, two members per class so
+    the batched film convolution runs: each served result is bitwise
+    nm_llg_step's on its own mesh."""
+    reqs = [synth.make_problem(n, (3e-9, 3e-9, 3e-9), 8e5, 1.3e-11, 0.1, seed=90 + i)
+            for i, n in enumerate([(6, 140, 1), (6, 140, 1), (9, 300, 1), (9, 300, 1)])]
+    mix, res = _serve(reqs, max_active=len(reqs))
+    for p, m, r in zip(reqs, mix, res):
+        mesh = B.mesh_from_problem(p)
+        try:
+            mt = torch.as_tensor(p["m0"], device="cuda").contiguous()
+            clk = B.nm_clock(0.0, 1e-14, 0, 0, 0, 0.0)
+            B.nm_llg_step(mesh, mt, clk, B.NM_DP45, B.NM_T_ALL, t_end=T_END)
+            single = mt.cpu().numpy().ravel()
+        finally:
+            B.nm_mesh_destroy(mesh)
+        assert np.array_equal(m, single), p["n"]
+        assert (r.accepted, r.rejected, r.rhs_evals) == (clk.accepted, clk.rejected, clk.rhs_evals)
+
+
 def _material_requests():
     """Requests carrying every optional cell array the server takes:
     uniaxial Ku and easy axes, a per-cell field, DMI of both kinds, cubic
