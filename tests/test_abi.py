@@ -40,6 +40,20 @@ def test_footprint_is_host_only_and_validates():
     assert fp > 3 * 32 * 256 * 129 * 8
     assert binding.nm_mesh_footprint_bytes((1, 128, 32), (2e-9,) * 3) == 0
     assert binding.nm_mesh_footprint_bytes((2000, 4, 4), (2e-9,) * 3) == 0
+    # the longest padded axis is 1024 points: 512 cells fit on every axis, 513 do not
+    for ax in range(3):
+        n = [4, 4, 4]
+        n[ax] = 512
+        assert binding.nm_mesh_footprint_bytes(tuple(n), (2e-9,) * 3) > 0, n
+        n[ax] = 513
+        assert binding.nm_mesh_footprint_bytes(tuple(n), (2e-9,) * 3) == 0, n
+    # x and y need two cells, z one; the film basis one cell layer
+    for n in [(4, 1, 4), (4, 4, 0), (-3, 4, 4)]:
+        assert binding.nm_mesh_footprint_bytes(n, (2e-9,) * 3) == 0, n
+    assert binding.nm_mesh_footprint_bytes((2, 2, 1), (2e-9,) * 3) > 0
+    assert binding.nm_mesh_footprint_bytes((4, 4, 1), (2e-9,) * 3, basis=binding.NM_BASIS_FILM) > 0
+    assert binding.nm_mesh_footprint_bytes((4, 4, 2), (2e-9,) * 3, basis=binding.NM_BASIS_FILM) == 0
+    assert binding.nm_mesh_footprint_bytes((4, 4, 4), (2e-9,) * 3, basis=7) == 0
 
 
 @needs_lib

@@ -163,6 +163,18 @@ def test_film_long_columns_match_oracle(n):
     assert np.abs(g - want).max() <= 1e-4 * np.abs(want).max(), n
 
 
+@pytest.mark.parametrize("n", [(512, 3, 1), (3, 512, 2), (2, 3, 512), (512, 2, 2)])
+def test_largest_axis_length_matches_oracle(n):
+    """512 cells on an axis, the most a mesh takes (padded to 1024, the data
+    filling exactly half of the transform)."""
+    p = synth.small_random(n, (2e-9, 2e-9, 2e-9), seed=48, anis=False, field=False)
+    g = _field(p, DEMAG)
+    om, omat, om0 = to_oracle(p)
+    want = oracle.heff(om, omat, om0, DEMAG)
+    assert rel_l2(g, want) <= 1e-5, n
+    assert np.abs(g - want).max() <= 1e-4 * np.abs(want).max(), n
+
+
 def test_results_are_bitwise_reproducible():
     p = synth.small_random((13, 7, 3), (2e-9,) * 3, seed=47)
     a = _field(p, ALL_TERMS)
