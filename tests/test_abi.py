@@ -101,3 +101,27 @@ def test_adjoint_and_server_reject_bad_arguments_on_the_host():
     assert L.nm_profile_enable(None, 1) == binding.NM_EINVAL
     y, z = ctypes.c_int(0), ctypes.c_int(0)
     assert L.nm_mesh_tuning(None, 0, ctypes.byref(y), ctypes.byref(z)) == binding.NM_EINVAL
+
+
+def test_missing_library_raises_and_the_package_never_imports_the_oracle(monkeypatch, tmp_path):
+    """Without the HIP library every entry point raises (there is no fallback
+    path); no module of the package imports the oracle."""
+    import ast
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libnm.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        binding.nm_mesh_footprint_bytes((4, 4, 4), (2e-9,) * 3)
+    pkg = os.path.dirname(binding.__file__)
+    for name in sorted(os.listdir(pkg)):
+        if not name.endswith(".py"):
+            continue
+        tree = ast.parse(open(os.path.join(pkg, name)).read())
+        for node in ast.walk(tree):
+            mods = []
+            if isinstance(node, ast.Import):
+                mods = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom):
+                mods = [node.module or ""]
+            assert not any(m == "oracle" or m.startswith("oracle.") for m in mods), (name, mods)
